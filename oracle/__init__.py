@@ -1,0 +1,151 @@
+"""CPU oracle for the reproducible Jacobi-PCG hot path (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+bench's CPU-baseline leg, never by the library. It shares no code with the
+GPU path. The C source states what each function computes and which part of
+the paper it follows.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rpcg_oracle.c")
+_LIB = os.path.join(_HERE, "librpcg_oracle.so")
+
+OK, WARN_MAXIT, ERR_INVALID, ERR_NOT_SPD, ERR_BREAKDOWN, ERR_NONFINITE = 0, 1, -1, -4, -5, -6
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: no contraction of a*b+c, hardware fma for fma()."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-mfma", "-fPIC", "-shared",
+                        "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.rpcg_oracle_exdot.restype = ctypes.c_double
+        L.rpcg_oracle_exdot.argtypes = [ctypes.c_int64, P, P]
+        L.rpcg_oracle_exact_limbs.restype = ctypes.c_int
+        L.rpcg_oracle_exdot_exact.restype = ctypes.c_int
+        L.rpcg_oracle_exdot_exact.argtypes = [ctypes.c_int64, P, P, P, P]
+        L.rpcg_oracle_round_limbs.restype = ctypes.c_double
+        L.rpcg_oracle_round_limbs.argtypes = [P, ctypes.c_int]
+        L.rpcg_oracle_spmv.restype = None
+        L.rpcg_oracle_spmv.argtypes = [ctypes.c_int32, P, P, P, P, P]
+        L.rpcg_oracle_true_residual.restype = None
+        L.rpcg_oracle_true_residual.argtypes = [ctypes.c_int32, P, P, P, P, P, P]
+        L.rpcg_oracle_pcg.restype = ctypes.c_int
+        L.rpcg_oracle_pcg.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                                      P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def exdot(x, y) -> float:
+    """Correctly rounded exact dot product."""
+    x, y = _f64(x), _f64(y)
+    assert x.shape == y.shape
+    return lib().rpcg_oracle_exdot(x.size, _p(x), _p(y))
+
+
+def exdot_exact(x, y) -> int:
+    """Exact dot product as an integer E: sum x_i y_i = E * 2^-2148."""
+    x, y = _f64(x), _f64(y)
+    L = lib()
+    nl = L.rpcg_oracle_exact_limbs()
+    limbs = np.zeros(nl, dtype=np.uint32)
+    sign = ctypes.c_int(0)
+    rc = L.rpcg_oracle_exdot_exact(x.size, _p(x), _p(y), _p(limbs), ctypes.byref(sign))
+    if rc != 0:
+        raise ValueError("non-finite input")
+    v = int.from_bytes(limbs.astype("<u4").tobytes(), "little")
+    return -v if sign.value else v
+
+
+EXACT_LSB_EXP = -2148
+
+
+def round_exact(E: int) -> float:
+    """Round E * 2^-2148 to the nearest double (ties to even) with the oracle's rounding."""
+    L = lib()
+    nl = L.rpcg_oracle_exact_limbs()
+    mag = abs(E)
+    limbs = np.frombuffer(mag.to_bytes(4 * nl, "little"), dtype="<u4").copy()
+    return L.rpcg_oracle_round_limbs(_p(limbs), 1 if E < 0 else 0)
+
+
+def spmv(A, x):
+    x = _f64(x)
+    y = np.empty(A.n, dtype=np.float64)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val)
+    lib().rpcg_oracle_spmv(A.n, _p(rp), _p(ci), _p(va), _p(x), _p(y))
+    return y
+
+
+def true_residual(A, b, x):
+    """r_i = RN(b_i - sum_j a_ij x_j) with exact row sums."""
+    b, x = _f64(b), _f64(x)
+    r = np.empty(A.n, dtype=np.float64)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val)
+    lib().rpcg_oracle_true_residual(A.n, _p(rp), _p(ci), _p(va), _p(b), _p(x), _p(r))
+    return r
+
+
+def relres_true(A, b, x) -> float:
+    """sqrt(<r,r>) / sqrt(<b,b>) with r the exact-row-sum residual and exact dots."""
+    r = true_residual(A, b, x)
+    bb = exdot(b, b)
+    return float(np.sqrt(exdot(r, r)) / np.sqrt(bb)) if bb > 0 else float(np.sqrt(exdot(r, r)))
+
+
+def pcg(A, b, x0=None, tol=1e-8, maxit=2000, trace=False):
+    """Jacobi-PCG. Returns dict(x, iters, hist, status[, trace_r, trace_d, trace_x])."""
+    n = A.n
+    b = _f64(b)
+    x = np.zeros(n, dtype=np.float64) if x0 is None else _f64(x0).copy()
+    hist = np.zeros(maxit + 1, dtype=np.float64)
+    iters = ctypes.c_int32(0)
+    tr = td = tx = None
+    if trace:
+        tr = np.zeros((maxit + 1) * n, dtype=np.float64)
+        td = np.zeros_like(tr)
+        tx = np.zeros_like(tr)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val)
+    st = lib().rpcg_oracle_pcg(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit),
+                               _p(hist), ctypes.byref(iters), _p(tr), _p(td), _p(tx))
+    L = iters.value
+    out = dict(x=x, iters=L, hist=hist[:L + 1].copy(), status=st)
+    if trace:
+        out["trace_r"] = tr.reshape(maxit + 1, n)[:L + 1]
+        out["trace_d"] = td.reshape(maxit + 1, n)[:L + 1]
+        out["trace_x"] = tx.reshape(maxit + 1, n)[:L + 1]
+    return out

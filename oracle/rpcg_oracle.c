@@ -1,0 +1,335 @@
+/*
+ * CPU oracle for the reproducible Jacobi-PCG hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the library links, loads or calls
+ * this file; only the tests, the smoke check and the bench's CPU-baseline
+ * leg do. It shares no code with the GPU path.
+ *
+ * It is the plain definition of what the method computes, run slowly:
+ *
+ *  - exact dot product (Sections 2 and 2.1: the long-accumulator approach,
+ *    whose result is rounded once; Section 4.3 "Round"/"NearSum" give the
+ *    correctly rounded value): every product x_i*y_i is formed exactly as a
+ *    106-bit integer times a power of two, added into a fixed-point big
+ *    integer whose least significant bit is 2^-2148 (the smallest possible
+ *    product of two binary64 numbers), and the total is rounded once to the
+ *    nearest binary64, ties to even (IEEE 754 default rounding, Section 2).
+ *    The integer sum does not depend on the order of the terms.
+ *  - sparse matrix-vector product (Section 4.3, SpMV paragraph): per row,
+ *    sequential fma over the stored entries in CSR order, starting from +0.
+ *  - Jacobi-preconditioned CG (Fig. 1 steps S1-S8 in the order of Fig. 2,
+ *    S8 merged with S6 as in Section 3.2), axpy-type updates by fma
+ *    (Section 4.3), preconditioner by the precomputed inverse diagonal times
+ *    the vector (Section 4.3, preconditioner paragraph).
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -mfma -fPIC -shared
+ * (-ffp-contract=off: no multiply-add is fused unless fma() is written).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- exact accumulator ------------------------------------------------ */
+
+/* Bit k of the accumulator has weight 2^(k - ORC_BIAS). Products of two
+ * finite doubles are integer multiples of 2^-2148 and below 2^2048; 136
+ * limbs of 32 bits (4352 bits) leave more than 150 bits of headroom. */
+#define ORC_BIAS 2148
+#define ORC_LIMBS 136
+
+typedef struct {
+    uint32_t pos[ORC_LIMBS]; /* magnitude of the positive terms */
+    uint32_t neg[ORC_LIMBS]; /* magnitude of the negative terms */
+    int nonfinite;           /* an inf or NaN was seen */
+} orc_acc;
+
+static void acc_clear(orc_acc *a) { memset(a, 0, sizeof(*a)); }
+
+/* Split a finite double into (integer mantissa M, exponent E) with v = M*2^E,
+ * 0 <= M < 2^53, E >= -1074; the sign is returned separately. */
+static void split_double(double v, uint64_t *M, int *E, int *neg)
+{
+    uint64_t bits;
+    memcpy(&bits, &v, sizeof bits);
+    *neg = (int)(bits >> 63);
+    int be = (int)((bits >> 52) & 0x7FF);
+    uint64_t frac = bits & ((UINT64_C(1) << 52) - 1);
+    if (be == 0) {          /* zero or subnormal: frac * 2^-1074 */
+        *M = frac;
+        *E = -1074;
+    } else {                /* normal: (2^52 + frac) * 2^(be - 1075) */
+        *M = frac | (UINT64_C(1) << 52);
+        *E = be - 1075;
+    }
+}
+
+/* A[] += m * 2^shift, m < 2^128 given as 4 little-endian 32-bit words. */
+static void limbs_add_shifted(uint32_t *A, const uint32_t w[4], int shift)
+{
+    int li = shift / 32, b = shift % 32;
+    uint32_t s[5];
+    for (int j = 0; j < 5; ++j) {
+        uint64_t cur = j < 4 ? w[j] : 0;
+        uint64_t prev = j > 0 ? w[j - 1] : 0;
+        uint64_t v = (cur << b) | (b ? (prev >> (32 - b)) : 0);
+        s[j] = (uint32_t)v;
+    }
+    uint64_t carry = 0;
+    int k = 0;
+    for (; k < 5 && li + k < ORC_LIMBS; ++k) {
+        uint64_t t = (uint64_t)A[li + k] + s[k] + carry;
+        A[li + k] = (uint32_t)t;
+        carry = t >> 32;
+    }
+    for (int j = li + k; carry && j < ORC_LIMBS; ++j) {
+        uint64_t t = (uint64_t)A[j] + carry;
+        A[j] = (uint32_t)t;
+        carry = t >> 32;
+    }
+}
+
+/* Add the exact product x*y. */
+static void acc_add_product(orc_acc *a, double x, double y)
+{
+    if (!isfinite(x) || !isfinite(y)) { a->nonfinite = 1; return; }
+    uint64_t mx, my; int ex, ey, sx, sy;
+    split_double(x, &mx, &ex, &sx);
+    split_double(y, &my, &ey, &sy);
+    if (mx == 0 || my == 0) return;
+    unsigned __int128 p = (unsigned __int128)mx * my; /* < 2^106, exact */
+    uint32_t w[4];
+    for (int j = 0; j < 4; ++j) w[j] = (uint32_t)(p >> (32 * j));
+    int shift = ex + ey + ORC_BIAS;                   /* >= 0 */
+    limbs_add_shifted((sx ^ sy) ? a->neg : a->pos, w, shift);
+}
+
+/* Add the exact value of a double (product with 1). */
+static void acc_add_value(orc_acc *a, double v) { acc_add_product(a, v, 1.0); }
+
+static int limbs_cmp(const uint32_t *A, const uint32_t *B)
+{
+    for (int k = ORC_LIMBS - 1; k >= 0; --k)
+        if (A[k] != B[k]) return A[k] > B[k] ? 1 : -1;
+    return 0;
+}
+
+/* D = A - B, requires A >= B. */
+static void limbs_sub(uint32_t *D, const uint32_t *A, const uint32_t *B)
+{
+    int64_t borrow = 0;
+    for (int k = 0; k < ORC_LIMBS; ++k) {
+        int64_t t = (int64_t)A[k] - B[k] - borrow;
+        borrow = t < 0;
+        D[k] = (uint32_t)(t + (borrow ? (INT64_C(1) << 32) : 0));
+    }
+}
+
+static int limbs_bit(const uint32_t *D, int k)
+{
+    if (k < 0 || k >= 32 * ORC_LIMBS) return 0;
+    return (D[k / 32] >> (k % 32)) & 1;
+}
+
+/* Round (-1)^neg * D * 2^-ORC_BIAS to the nearest double, ties to even.
+ * Zero gives +0.0; magnitudes at or above 2^1024 - 2^970 give infinity. */
+static double round_magnitude(const uint32_t *D, int neg)
+{
+    int top = -1;
+    for (int k = ORC_LIMBS - 1; k >= 0 && top < 0; --k)
+        if (D[k]) for (int b = 31; b >= 0; --b)
+            if ((D[k] >> b) & 1) { top = 32 * k + b; break; }
+    if (top < 0) return 0.0;
+    int emsb = top - ORC_BIAS;               /* value in [2^emsb, 2^(emsb+1)) */
+    if (emsb >= 1024) return neg ? -INFINITY : INFINITY;
+    int q = emsb - 52;                       /* weight of the last kept bit */
+    if (q < -1074) q = -1074;                /* subnormal range */
+    int qb = q + ORC_BIAS;                   /* its bit index, >= 1074 */
+    uint64_t I = 0;
+    for (int k = top; k >= qb; --k) I = (I << 1) | (uint64_t)limbs_bit(D, k);
+    int half = limbs_bit(D, qb - 1);
+    /* sticky: is any bit below the rounding bit (index qb-1) set? */
+    int sticky = 0, lim = qb - 1;            /* bits [0, lim) */
+    for (int k = 0; k < lim / 32 && !sticky; ++k) sticky = D[k] != 0;
+    if (!sticky && lim % 32) sticky = (D[lim / 32] & ((UINT32_C(1) << (lim % 32)) - 1)) != 0;
+    if (half && (sticky || (I & 1))) I += 1; /* I <= 2^53 */
+    double r = ldexp((double)I, q);          /* exact, or inf on overflow */
+    return neg ? -r : r;
+}
+
+static double acc_round(const orc_acc *a)
+{
+    if (a->nonfinite) return NAN;
+    uint32_t D[ORC_LIMBS];
+    int c = limbs_cmp(a->pos, a->neg);
+    if (c == 0) return 0.0;
+    if (c > 0) { limbs_sub(D, a->pos, a->neg); return round_magnitude(D, 0); }
+    limbs_sub(D, a->neg, a->pos);
+    return round_magnitude(D, 1);
+}
+
+/* ---- exported API ------------------------------------------------------ */
+
+/* Correctly rounded exact dot product of x and y (length n). NaN if any
+ * input is not finite. */
+double rpcg_oracle_exdot(int64_t n, const double *x, const double *y)
+{
+    orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
+    acc_clear(a);
+    for (int64_t i = 0; i < n; ++i) acc_add_product(a, x[i], y[i]);
+    double r = acc_round(a);
+    free(a);
+    return r;
+}
+
+/* Exact value of the dot product as a signed fixed-point integer:
+ * sum x_i y_i = (-1)^sign * sum_k limbs[k] 2^(32k - 2148). limbs has
+ * rpcg_oracle_exact_limbs() entries. Returns 0, or -1 if an input is not
+ * finite. */
+int rpcg_oracle_exact_limbs(void) { return ORC_LIMBS; }
+
+int rpcg_oracle_exdot_exact(int64_t n, const double *x, const double *y,
+                            uint32_t *limbs, int *sign)
+{
+    orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
+    acc_clear(a);
+    for (int64_t i = 0; i < n; ++i) acc_add_product(a, x[i], y[i]);
+    int rc = a->nonfinite ? -1 : 0;
+    int c = limbs_cmp(a->pos, a->neg);
+    if (c >= 0) { limbs_sub(limbs, a->pos, a->neg); *sign = 0; }
+    else        { limbs_sub(limbs, a->neg, a->pos); *sign = 1; }
+    free(a);
+    return rc;
+}
+
+/* Round a signed fixed-point integer (same format as above) to double. */
+double rpcg_oracle_round_limbs(const uint32_t *limbs, int sign)
+{
+    return round_magnitude(limbs, sign);
+}
+
+/* y = A x, row by row: acc = +0; acc = fma(val_k, x[col_k], acc) for the
+ * stored entries of the row in CSR order. */
+void rpcg_oracle_spmv(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                      const double *val, const double *x, double *y)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            acc = fma(val[k], x[col[k]], acc);
+        y[i] = acc;
+    }
+}
+
+/* Residual with exact row sums: r_i = RN(b_i - sum_j a_ij x_j), each row
+ * accumulated exactly and rounded once. */
+void rpcg_oracle_true_residual(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                               const double *val, const double *b, const double *x,
+                               double *r)
+{
+    orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
+    for (int32_t i = 0; i < n; ++i) {
+        acc_clear(a);
+        acc_add_value(a, b[i]);
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            acc_add_product(a, -val[k], x[col[k]]);
+        r[i] = acc_round(a);
+    }
+    free(a);
+}
+
+/* Jacobi preconditioner apply (Section 4.3): z_i = RN(dinv_i * r_i), with
+ * dinv_i = RN(1 / a_ii) formed once at setup. */
+static void jacobi_apply(int32_t n, const double *dinv, const double *r, double *z)
+{
+    for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+}
+
+/* Status codes shared in value (not in code) with the library's header. */
+#define ORC_OK 0
+#define ORC_WARN_MAXIT 1
+#define ORC_ERR_INVALID (-1)
+#define ORC_ERR_NOT_SPD (-4)
+#define ORC_ERR_BREAKDOWN (-5)
+#define ORC_ERR_NONFINITE (-6)
+
+/*
+ * Jacobi-PCG on A x = b (Fig. 1 / Fig. 2).
+ *   x      in: starting guess x^(0); out: final iterate
+ *   tol    the loop runs while tau > thr, thr = RN(RN(tol*tol) * <b,b>),
+ *          tau = <r,r> (both exact dots, rounded once)
+ *   hist   optional [maxit+1]: tau^(0..L)
+ *   trace_r, trace_d, trace_x optional [(maxit+1)*n]: r, d, x after each
+ *          iteration (row l holds iteration l's vectors; d of row l is the
+ *          search direction used by iteration l+1)
+ *   *iters L, the number of loop bodies executed
+ * Returns a status code.
+ */
+int rpcg_oracle_pcg(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                    const double *val, const double *b, double *x,
+                    double tol, int32_t maxit, double *hist, int32_t *iters,
+                    double *trace_r, double *trace_d, double *trace_x)
+{
+    *iters = 0;
+    if (n < 0 || maxit < 0) return ORC_ERR_INVALID;
+    double *dinv = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *r = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *z = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *d = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *w = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int status = ORC_OK;
+
+    /* preconditioner M = diag(A): invert the diagonal once */
+    for (int32_t i = 0; i < n && status == ORC_OK; ++i) {
+        double aii = 0.0; int found = 0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) { aii = val[k]; found = 1; }
+        if (!found || !(aii > 0.0)) status = ORC_ERR_NOT_SPD;
+        else dinv[i] = 1.0 / aii;
+    }
+    for (int32_t i = 0; i < n && status == ORC_OK; ++i)
+        if (!isfinite(b[i]) || !isfinite(x[i])) status = ORC_ERR_NONFINITE;
+    if (status != ORC_OK) goto out;
+
+    /* r = b - A x0;  z = M^-1 r;  d = z;  beta = <z,r>;  tau = <r,r> */
+    rpcg_oracle_spmv(n, row_ptr, col, val, x, w);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
+    jacobi_apply(n, dinv, r, z);
+    for (int32_t i = 0; i < n; ++i) d[i] = z[i];
+    double beta = rpcg_oracle_exdot(n, z, r);
+    double tau = rpcg_oracle_exdot(n, r, r);
+    double bb = rpcg_oracle_exdot(n, b, b);
+    double thr = (tol * tol) * bb;
+    if (hist) hist[0] = tau;
+    if (trace_r) memcpy(trace_r, r, sizeof(double) * (size_t)n);
+    if (trace_d) memcpy(trace_d, d, sizeof(double) * (size_t)n);
+    if (trace_x) memcpy(trace_x, x, sizeof(double) * (size_t)n);
+    if (!isfinite(tau) || !isfinite(bb)) { status = ORC_ERR_NONFINITE; goto out; }
+
+    int32_t l = 0;
+    while (tau > thr && l < maxit) {
+        double beta_old = beta;
+        rpcg_oracle_spmv(n, row_ptr, col, val, d, w);           /* S1 */
+        double delta = rpcg_oracle_exdot(n, d, w);              /* S2 */
+        if (!(delta > 0.0)) { status = isfinite(delta) ? ORC_ERR_BREAKDOWN : ORC_ERR_NONFINITE; break; }
+        double rho = beta / delta;
+        for (int32_t i = 0; i < n; ++i) x[i] = fma(rho, d[i], x[i]);   /* S3 */
+        for (int32_t i = 0; i < n; ++i) r[i] = fma(-rho, w[i], r[i]);  /* S4 */
+        jacobi_apply(n, dinv, r, z);                            /* S5 */
+        beta = rpcg_oracle_exdot(n, z, r);                      /* S6 */
+        tau = rpcg_oracle_exdot(n, r, r);                       /* S8 */
+        double gamma = beta / beta_old;
+        for (int32_t i = 0; i < n; ++i) d[i] = fma(gamma, d[i], z[i]); /* S7 */
+        l += 1;
+        if (hist) hist[l] = tau;
+        if (trace_r) memcpy(trace_r + (size_t)l * n, r, sizeof(double) * (size_t)n);
+        if (trace_d) memcpy(trace_d + (size_t)l * n, d, sizeof(double) * (size_t)n);
+        if (trace_x) memcpy(trace_x + (size_t)l * n, x, sizeof(double) * (size_t)n);
+        if (!isfinite(tau)) { status = ORC_ERR_NONFINITE; break; }
+    }
+    *iters = l;
+    if (status == ORC_OK && tau > thr) status = ORC_WARN_MAXIT;
+out:
+    free(dinv); free(r); free(z); free(d); free(w);
+    return status;
+}

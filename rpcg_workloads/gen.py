@@ -1,0 +1,232 @@
+"""Generators for the synthetic workloads (host only, numpy).
+
+Workloads follow the paper's experiments: a 3D Poisson matrix from the
+27-point finite-difference stencil (Section 5.1), the right-hand side built
+from a known vector (Section 5.1 uses ``A * ones``), a zero initial guess;
+plus vector pairs for the standalone exact dot product with wide exponent
+ranges and prescribed condition numbers (Section 2.1, Section 4.1 cost model
+for wide dynamic ranges).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+_TWO52 = 1 << 52
+
+
+def _mix64(z: np.ndarray) -> np.ndarray:
+    """SplitMix64 output function on a uint64 array (wrapping arithmetic)."""
+    z = z.copy()
+    z ^= z >> np.uint64(30)
+    z *= _M1
+    z ^= z >> np.uint64(27)
+    z *= _M2
+    z ^= z >> np.uint64(31)
+    return z
+
+
+def _key(seed: int) -> np.uint64:
+    return _mix64(np.array([np.uint64(seed & 0xFFFFFFFFFFFFFFFF) ^ np.uint64(0x6A09E667F3BCC909)],
+                           dtype=np.uint64))[0]
+
+
+def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Counter-based stream: element i is mix64(key(seed) + (start + i + 1) * GOLDEN)."""
+    with np.errstate(over="ignore"):
+        idx = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+        z = _key(seed) + idx * GOLDEN
+        return _mix64(z)
+
+
+def uniform_pm1_int52(seed: int, n: int, start: int = 0) -> np.ndarray:
+    """Integers K in [-2^52, 2^52): the uniform value on [-1, 1) is K * 2^-52."""
+    k = (splitmix64(seed, n, start) >> np.uint64(11)).astype(np.int64)  # 53 random bits
+    return k - np.int64(_TWO52)
+
+
+def uniform_pm1(seed: int, n: int, start: int = 0) -> np.ndarray:
+    """Uniform doubles on [-1, 1) on the 2^-52 grid (exact int -> double conversion)."""
+    return uniform_pm1_int52(seed, n, start).astype(np.float64) * (2.0 ** -52)
+
+
+@dataclass
+class CSRHost:
+    """CSR matrix on the host: int32 row pointers and column indices, values."""
+    n: int
+    row_ptr: np.ndarray
+    col_idx: np.ndarray
+    val: np.ndarray
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+
+def stencil27_nnz(N: int) -> int:
+    return (3 * N - 2) ** 3
+
+
+def _stencil_offsets(kind: int):
+    if kind == 27:
+        return [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    if kind == 7:
+        return [(-1, 0, 0), (0, -1, 0), (0, 0, -1), (0, 0, 0), (0, 0, 1), (0, 1, 0), (1, 0, 0)]
+    raise ValueError(kind)
+
+
+def _stencil_pattern(N: int, kind: int):
+    """Column pattern of a Dirichlet stencil on an N^3 grid, rows in z-y-x order.
+
+    Offsets are visited in lexicographic (dz, dy, dx) order, so the column
+    indices of every row come out ascending. Returns (row_ptr, col, offset_id)."""
+    n = N ** 3
+    offs = _stencil_offsets(kind)
+    i = np.arange(n, dtype=np.int64)
+    z, y, x = i // (N * N), (i // N) % N, i % N
+    cols = np.empty((n, len(offs)), dtype=np.int64)
+    valid = np.empty((n, len(offs)), dtype=bool)
+    for t, (dz, dy, dx) in enumerate(offs):
+        ok = (z + dz >= 0) & (z + dz < N) & (y + dy >= 0) & (y + dy < N) & (x + dx >= 0) & (x + dx < N)
+        valid[:, t] = ok
+        cols[:, t] = i + dz * N * N + dy * N + dx
+    counts = valid.sum(axis=1)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    col = cols[valid]
+    oid = np.broadcast_to(np.arange(len(offs)), (n, len(offs)))[valid]
+    del cols
+    return row_ptr, col, oid, valid
+
+
+def stencil27_csr(N: int) -> CSRHost:
+    """27-point operator on an N^3 grid: 26 on the diagonal, -1 for each in-grid neighbour."""
+    n = N ** 3
+    if stencil27_nnz(N) >= 2 ** 31:
+        raise ValueError("nnz does not fit int32 row pointers")
+    row_ptr, col, oid, _ = _stencil_pattern(N, 27)
+    val = np.where(oid == 13, 26.0, -1.0)
+    return CSRHost(n, row_ptr.astype(np.int32), col.astype(np.int32), val.astype(np.float64))
+
+
+def stencil27_rhs_from_int52(N: int, K: np.ndarray) -> np.ndarray:
+    """b = A x* for x* = K * 2^-52 on the 27-point operator, rounded once per entry.
+
+    (A x*)_i * 2^52 = 27 K_i - sum over the 3x3x3 box around i of K (zero
+    outside the grid): an int64 with |value| < 2^58, converted to double by one
+    round-to-nearest-even conversion, then scaled by a power of two (exact)."""
+    K3 = K.reshape(N, N, N).astype(np.int64)
+    P = np.zeros((N + 2, N + 2, N + 2), dtype=np.int64)
+    P[1:-1, 1:-1, 1:-1] = K3
+    box = np.zeros_like(K3)
+    for dz in range(3):
+        for dy in range(3):
+            for dx in range(3):
+                box += P[dz:dz + N, dy:dy + N, dx:dx + N]
+    B = 27 * K3 - box
+    return (B.astype(np.float64) * (2.0 ** -52)).reshape(-1)
+
+
+def stencil7_varcoef_csr(N: int, seed: int, sigma: float = 1.0) -> CSRHost:
+    """7-point diffusion on an N^3 grid with i.i.d. face coefficients exp(sigma * N(0,1)).
+
+    Every cell face, boundary faces included, carries one coefficient k_f.
+    A_ij = -k_f for the face between cells i and j; A_ii = sum of the six faces
+    of cell i (boundary faces give Dirichlet coupling to zero). The matrix is
+    symmetric and strictly diagonally dominant, hence SPD."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    # faces normal to x: (N, N, N+1), y: (N, N+1, N), z: (N+1, N, N)
+    kx = np.exp(sigma * rng.standard_normal((N, N, N + 1)))
+    ky = np.exp(sigma * rng.standard_normal((N, N + 1, N)))
+    kz = np.exp(sigma * rng.standard_normal((N + 1, N, N)))
+    diag = (kx[:, :, :-1] + kx[:, :, 1:]) + (ky[:, :-1, :] + ky[:, 1:, :]) + (kz[:-1, :, :] + kz[1:, :, :])
+    # off-diagonal value for each of the 7 offsets, in (dz,dy,dx) lexicographic order
+    offv = {
+        (-1, 0, 0): -kz[:-1, :, :], (1, 0, 0): -kz[1:, :, :],
+        (0, -1, 0): -ky[:, :-1, :], (0, 1, 0): -ky[:, 1:, :],
+        (0, 0, -1): -kx[:, :, :-1], (0, 0, 1): -kx[:, :, 1:],
+        (0, 0, 0): diag,
+    }
+    row_ptr, col, oid, valid = _stencil_pattern(N, 7)
+    offs = _stencil_offsets(7)
+    vals = np.stack([offv[o].reshape(-1) for o in offs], axis=1)
+    val = vals[valid]
+    return CSRHost(N ** 3, row_ptr.astype(np.int32), col.astype(np.int32), val.astype(np.float64))
+
+
+def exdot_narrow(seed: int, n: int):
+    """Vector pair with values uniform on [-1, 1) (the PCG-like, narrow-range case)."""
+    return uniform_pm1(2 * seed, n), uniform_pm1(2 * seed + 1, n)
+
+
+def _wide_bits(seed: int, n: int, emin: int, emax: int) -> np.ndarray:
+    """Doubles +-m * 2^e: m with 52 random fraction bits, e uniform in [emin, emax], random sign."""
+    r1 = splitmix64(seed, n)
+    r2 = splitmix64(seed ^ 0x5DEECE66D, n)
+    span = np.uint64(emax - emin + 1)
+    e = (r2 % span).astype(np.int64) + emin
+    sign = (r2 >> np.uint64(63)).astype(np.uint64)
+    mant = r1 >> np.uint64(12)
+    bits = (sign << np.uint64(63)) | ((e + 1023).astype(np.uint64) << np.uint64(52)) | mant
+    return bits.view(np.float64)
+
+
+def exdot_wide(seed: int, n: int, emin: int = -200, emax: int = 200):
+    """Vector pair whose exponents are uniform over [emin, emax] with random signs."""
+    return _wide_bits(2 * seed, n, emin, emax), _wide_bits(2 * seed + 1, n, emin, emax)
+
+
+def exdot_conditioned(seed: int, n: int, cond: float, emin: int = -200, emax: int = 200):
+    """Wide-exponent vector pair whose dot product has condition number about ``cond``.
+
+    cond = sum|x_i y_i| / |sum x_i y_i|. For cond == 1 the signs of y copy the
+    signs of x, so every product is positive. For cond > 1 the vectors hold
+    mirrored pairs whose products cancel exactly, (x, y) and
+    (x * 2^t, -y * 2^-t), plus two signal entries (2^a, 2^b) and (2^a, 2^(b-1))
+    whose products sum to 1.5 * 2^(a+b), chosen so that this is near
+    sum|x_i y_i| / cond; positions are then shuffled by a seeded permutation.
+    The exact dot product is therefore the representable value 1.5 * 2^(a+b),
+    returned as the third element (None for cond == 1)."""
+    if n < 4 and cond != 1.0:
+        raise ValueError("need n >= 4")
+    if cond == 1.0:
+        x, y = exdot_wide(seed, n, emin, emax)
+        y = np.where(np.signbit(x) != np.signbit(y), -y, y)
+        return x, y, None
+    h = (n - 2) // 2
+    xa, ya = exdot_wide(seed, h, emin, emax)
+    t = (splitmix64(seed + 7777, h) % np.uint64(17)).astype(np.int64) - 8
+    xb = np.ldexp(xa, t)
+    yb = -np.ldexp(ya, -t)
+    # approximate magnitude of sum|x_i y_i| (only used to place the signal)
+    mag = 2.0 * float(np.sum(np.abs(xa * ya)))
+    target = int(np.floor(np.log2(mag / cond)))
+    a = target // 2
+    b = target - a
+    sig_x = np.array([2.0 ** a, 2.0 ** a])
+    sig_y = np.array([2.0 ** b, 2.0 ** (b - 1)])
+    x = np.concatenate([xa, xb, sig_x])
+    y = np.concatenate([ya, yb, sig_y])
+    if x.size < n:  # odd n: pad with an exact zero product
+        x = np.concatenate([x, [0.0]])
+        y = np.concatenate([y, [1.0]])
+    perm = np.argsort(splitmix64(seed + 99991, n), kind="stable")
+    exact = 1.5 * 2.0 ** (a + b)
+    return x[perm], y[perm], exact
+
+
+def random_spd_csr(n: int, seed: int, density: float = 0.3) -> CSRHost:
+    """Small integer SPD matrix A = B^T B + I (int64, exact) in CSR form with sorted columns."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    B = rng.integers(-2, 3, size=(n, n)) * (rng.random((n, n)) < density)
+    A = B.T @ B + np.eye(n, dtype=np.int64)
+    rows, cols = np.nonzero(A)
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    row_ptr = np.cumsum(row_ptr)
+    return CSRHost(n, row_ptr.astype(np.int32), cols.astype(np.int32), A[rows, cols].astype(np.float64))
