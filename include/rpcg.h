@@ -1,0 +1,178 @@
+/*
+ * rpcg.h - reproducible Jacobi-preconditioned Conjugate Gradient on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Iakymchuk, Barreda, Graillat, Aliaga, Quintana-Orti,
+ * "Reproducibility of Parallel Preconditioned Conjugate Gradient in Hybrid
+ * Programming Environments" (arXiv:2005.07282).
+ *
+ * Problem (Section 3.1): A x = b with A an n x n sparse symmetric positive
+ * definite matrix with nnz stored entries, b and x vectors of length n,
+ * Jacobi preconditioner M = diag(A), iteration of Fig. 1 in the order of
+ * Fig. 2 (S8 computed together with S6, Section 3.2).
+ *
+ * Reproducibility (Section 4): in the exact modes every dot product is the
+ * exact sum of products rounded once to nearest-even (Sections 2, 2.1, 4.3),
+ * SpMV rows are sequential fma chains in storage order and the axpy-type
+ * updates are single fma operations (Section 4.3). Results are therefore
+ * bit-identical for any launch configuration.
+ *
+ * Conventions for every entry point:
+ *  - Pointers are DEVICE pointers unless marked "host". The caller owns all
+ *    arrays; the library owns only its context workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Work is enqueued on it in order.
+ *  - Return value: 0 ok, > 0 warning (outputs valid), < 0 error (outputs
+ *    undefined; device memory given as output may have been written).
+ *  - Nothing is thrown across the interface.
+ *  - Calls on one context must not overlap (one context per host thread).
+ */
+#ifndef RPCG_H
+#define RPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Reduction mode of every dot product (Section 5.2 names the paper's three
+ * variants: Regular, Exblas, Opt = FPE8EE).
+ *  PLAIN  - ordinary binary64 partial sums in a fixed tree; deterministic for
+ *           one launch configuration but not across configurations.
+ *  FPE    - per-lane floating-point expansions (two of size fpe_size: result
+ *           and error, Section 4.2) updated with TwoSum (Alg. 1, 4) over
+ *           TwoProd (Alg. 2), merged by fpesum (Alg. 3) in a fixed order and
+ *           rounded once (NearSum, Section 4.3).
+ *  EXBLAS - per-lane expansion flushed into a workgroup long accumulator
+ *           (Section 2.1 and 4.1), accumulators summed as integers, rounded
+ *           once (exblas Round, Section 4.3). */
+typedef enum { RPCG_MODE_PLAIN = 0, RPCG_MODE_FPE = 1, RPCG_MODE_EXBLAS = 2 } rpcg_mode;
+
+enum {
+    RPCG_OK = 0,
+    RPCG_WARN_MAXIT = 1,        /* tau > threshold after maxit iterations */
+    RPCG_WARN_FPE_INEXACT = 2,  /* FPE capacity exceeded (Section 4.3 warning) and no
+                                   fallback, or a product left the exact domain */
+    RPCG_ERR_INVALID = -1,      /* bad argument */
+    RPCG_ERR_HIP = -2,          /* a HIP runtime call failed */
+    RPCG_ERR_OOM = -3,          /* workspace allocation failed */
+    RPCG_ERR_NOT_SPD = -4,      /* a diagonal entry is missing or not > 0 */
+    RPCG_ERR_BREAKDOWN = -5,    /* <d, A d> <= 0 inside the loop */
+    RPCG_ERR_NONFINITE = -6     /* inf/NaN in the input or an overflowing product */
+};
+
+/* Compressed sparse rows, zero-based. row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz; 0 <= col_idx[k] < n. Column order inside a row is the
+ * order of the SpMV fma chain (Section 4.3). All three arrays are device
+ * memory and are only read. */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+} rpcg_csr;
+
+/* Options. Fill with rpcg_opts_default() first, then change fields. */
+typedef struct {
+    double tol;            /* stop when <r,r> <= RN(RN(tol*tol) * <b,b>) (Fig. 1 tau_max; default 1e-8, Section 5.1) */
+    int32_t maxit;         /* default 2000 */
+    int32_t fpe_size;      /* expansion length p, 1..8 (Section 4.2: tunable); default 4 */
+    int32_t early_exit;    /* stop propagating zero errors (Section 4.2); default 1 */
+    int32_t fpe_fallback;  /* FPE mode: if any expansion overflows, recompute that dot
+                              exactly with the long accumulator; default 1 */
+    int32_t block_size;    /* threads per workgroup: 0 = auto, else 64..1024, multiple of 64 */
+    int32_t grid_size;     /* workgroups: 0 = auto, else 1..65536 */
+    int32_t timing;        /* 1: bracket every solver kernel with HIP events and report
+                              per-kernel times in rpcg_result (solver only) */
+    double *tau_history;   /* optional DEVICE array of maxit+1 doubles: tau^(0..L) */
+} rpcg_opts;
+
+/* Host-side result record (host memory). */
+typedef struct {
+    int32_t status;        /* same value as the return code */
+    int32_t iterations;    /* L: loop bodies executed */
+    double tau0;           /* <r0, r0> */
+    double tau_final;      /* <r_L, r_L> */
+    double threshold;      /* RN(RN(tol*tol) * <b,b>) */
+    int64_t fpe_escapes;   /* expansion overflows seen (FPE mode) */
+    int64_t fallbacks;     /* dots recomputed with the long accumulator */
+    double setup_ms;       /* wall time of setup (solver) */
+    double loop_ms;        /* wall time of the iteration loop (solver) */
+    double k_spmv_dot_ms;  /* timing=1: summed HIP-event time of the SpMV+dot kernel */
+    double k_update_ms;    /* timing=1: summed time of the update+two-dot kernel */
+    double k_direction_ms; /* timing=1: summed time of the direction-update kernel */
+    int32_t k_launches;    /* timing=1: launches of each of the three kernels */
+    int32_t grid_size;     /* launch configuration actually used */
+    int32_t block_size;
+} rpcg_result;
+
+typedef struct rpcg_ctx rpcg_ctx;
+
+void rpcg_opts_default(rpcg_opts *opts /* host */);
+const char *rpcg_status_string(int status);
+
+/* Create a context on HIP device `device` (made current for the calls).
+ * *ctx receives a handle owned by the caller until rpcg_destroy. */
+int rpcg_create(rpcg_ctx **ctx /* host */, int device);
+void rpcg_destroy(rpcg_ctx *ctx);
+
+/* Dot product out[0] = <x, y> over n elements (Section 2.1 exdot; Section 4.1
+ * Listing 1 for EXBLAS, Section 4.2 Listing 2 for FPE; Section 4.3 for the
+ * final rounding). x, y: device arrays of n doubles; out: device pointer to
+ * one double. n >= 0 (n = 0 gives +0). In FPE and EXBLAS mode the result is
+ * the exact dot rounded to nearest-even whenever every nonzero product has
+ * |x_i y_i| >= 2^-969 (TwoProd exact, Alg. 2) and sum |x_i y_i| < 2^1023
+ * (no expansion overflows); a product below 2^-969 gives
+ * RPCG_WARN_FPE_INEXACT, an inf/NaN input or an overflow gives
+ * RPCG_ERR_NONFINITE with out = NaN.
+ * `res` (host, may be NULL): when given, the call waits for the stream and
+ * fills status, fpe_escapes and fallbacks; when NULL the call is fully
+ * asynchronous and returns RPCG_OK after enqueueing. `opts` may be NULL. */
+int rpcg_exdot(rpcg_ctx *ctx, rpcg_mode mode, int64_t n, const double *x, const double *y,
+               double *out, const rpcg_opts *opts, rpcg_result *res, void *stream);
+
+/* y = A x (Section 4.3 SpMV): y_i = fold over the stored entries of row i in
+ * order of acc = fma(a_ik, x[col_k], acc), acc starting at +0. A: device CSR
+ * (see rpcg_csr; its structure is not checked here, a malformed matrix is
+ * undefined behaviour), x: n doubles, y: n doubles (must not alias x).
+ * Asynchronous; returns after enqueueing. */
+int rpcg_spmv(rpcg_ctx *ctx, const rpcg_csr *A /* host struct */, const double *x, double *y,
+              void *stream);
+
+/* Solve A x = b with Jacobi-PCG (Fig. 1 / Fig. 2). b: n doubles; x: n
+ * doubles, in: starting guess x^(0), out: final iterate. A must be SPD with a
+ * positive stored diagonal entry in every row. The CSR structure is checked
+ * on the device first (RPCG_ERR_INVALID if row_ptr or a column index is out
+ * of range); the library then keeps a sliced-ELL copy of A for the
+ * iteration (same rows, same entry order). Waits for completion; `res`
+ * (host, may be NULL) receives iterations, tau, status and timings. The
+ * returned status is also written to res->status. */
+int rpcg_pcg_solve(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr *A /* host struct */,
+                   const double *b, double *x, const rpcg_opts *opts, rpcg_result *res,
+                   void *stream);
+
+/* Long-accumulator interface (Section 4.3, Listing 3: the per-process
+ * accumulator that is summed as integers across processes, then rounded).
+ * The accumulator is RPCG_ACC_DIGITS signed 64-bit digits; digit k has weight
+ * 2^(32 k + RPCG_ACC_EXP0). Any integer sum of such vectors (e.g. an
+ * all-reduce over GPUs) represents the sum of the dots exactly as long as
+ * fewer than 2^29 vectors are added. */
+#define RPCG_ACC_DIGITS 68
+#define RPCG_ACC_EXP0 (-1088)
+
+/* digits[0..RPCG_ACC_DIGITS) = exact <x,y> (device array, overwritten).
+ * Same domain as rpcg_exdot. Asynchronous. */
+int rpcg_exdot_partial(rpcg_ctx *ctx, int64_t n, const double *x, const double *y,
+                       int64_t *digits, void *stream);
+
+/* out[0] = the value of `digits` rounded to nearest-even (device arrays).
+ * Asynchronous. */
+int rpcg_acc_round(rpcg_ctx *ctx, const int64_t *digits, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPCG_H */

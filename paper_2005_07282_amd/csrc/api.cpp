@@ -1,0 +1,417 @@
+// C-ABI of the reproducible Jacobi-PCG library (declared in include/rpcg.h).
+// Host side only: argument checks, workspace, launch configuration and the
+// iteration loop. Every arithmetic step runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rpcg.h"
+#include "kernels.hpp"
+
+using namespace rpcg;
+
+namespace {
+
+struct Buffer {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need)
+    {
+        if (need <= bytes) return hipSuccess;
+        if (p) { hipError_t e = hipFree(p); if (e != hipSuccess) return e; p = nullptr; bytes = 0; }
+        hipError_t e = hipMalloc(&p, need);
+        if (e == hipSuccess) bytes = need;
+        return e;
+    }
+    void release()
+    {
+        if (p) hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
+} // namespace
+
+struct rpcg_ctx {
+    int device = 0;
+    int num_cus = 256;
+    int ws_groups = 0;        // capacity of the dot workspaces, in workgroups
+    Buffer ws_mem;            // 3 dot workspaces
+    DotWs ws[3];
+    Buffer scalars;           // DotInfo + PcgState
+    DotInfo *info = nullptr;
+    PcgState *st = nullptr;
+    Buffer sell_off, sell_val, sell_col;
+    Buffer vecs;              // r, z, d, w, dinv
+    int *host_done = nullptr; // pinned: polled flags
+    PcgState *host_state = nullptr;
+    std::vector<hipEvent_t> events;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+};
+
+static int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return RPCG_OK;
+    if (e == hipErrorOutOfMemory) return RPCG_ERR_OOM;
+    return RPCG_ERR_HIP;
+}
+
+#define RPCG_TRY(expr)                                   \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_status(_e);     \
+    } while (0)
+
+static int ensure_ws(rpcg_ctx *c, int groups)
+{
+    if (groups <= c->ws_groups) return RPCG_OK;
+    size_t per = (size_t)groups * (ACC_WORDS * sizeof(long long) + 2 * sizeof(int) +
+                                   MAX_FPE * sizeof(double) + sizeof(int));
+    RPCG_TRY(c->ws_mem.ensure(3 * per + 256 * 4));
+    char *base = (char *)c->ws_mem.p;
+    for (int i = 0; i < 3; ++i) {
+        char *b = base + i * per;
+        c->ws[i].digits = (long long *)b;
+        b += (size_t)groups * ACC_WORDS * sizeof(long long);
+        c->ws[i].part = (double *)b;
+        b += (size_t)groups * MAX_FPE * sizeof(double);
+        c->ws[i].range = (int *)b;
+        b += (size_t)groups * 2 * sizeof(int);
+        c->ws[i].esc = (int *)b;
+    }
+    c->ws_groups = groups;
+    return RPCG_OK;
+}
+
+static bool valid_opts(const rpcg_opts &o)
+{
+    if (!(o.tol >= 0.0) || o.maxit < 0) return false;
+    if (o.fpe_size < 1 || o.fpe_size > MAX_FPE) return false;
+    if (o.block_size != 0 && (o.block_size < 64 || o.block_size > MAX_BLOCK || o.block_size % 64)) return false;
+    if (o.grid_size < 0 || o.grid_size > 65536) return false;
+    return true;
+}
+
+static LaunchCfg make_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long work_items, int block_default,
+                          hipStream_t s)
+{
+    LaunchCfg cfg;
+    cfg.block = o.block_size ? o.block_size : block_default;
+    long long want = (work_items + cfg.block - 1) / cfg.block;
+    long long cap = 8ll * c->num_cus;
+    cfg.grid = o.grid_size ? o.grid_size : (int)std::max(1ll, std::min(want, cap));
+    cfg.early_exit = o.early_exit != 0;
+    cfg.fpe_size = o.fpe_size;
+    cfg.fallback = o.fpe_fallback != 0;
+    cfg.stream = s;
+    return cfg;
+}
+
+extern "C" {
+
+void rpcg_opts_default(rpcg_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-8;
+    o->maxit = 2000;
+    o->fpe_size = 4;
+    o->early_exit = 1;
+    o->fpe_fallback = 1;
+}
+
+const char *rpcg_status_string(int s)
+{
+    switch (s) {
+    case RPCG_OK: return "ok";
+    case RPCG_WARN_MAXIT: return "warning: maximum iterations reached";
+    case RPCG_WARN_FPE_INEXACT: return "warning: expansion capacity exceeded or product outside the exact domain";
+    case RPCG_ERR_INVALID: return "error: invalid argument";
+    case RPCG_ERR_HIP: return "error: HIP runtime failure";
+    case RPCG_ERR_OOM: return "error: out of device memory";
+    case RPCG_ERR_NOT_SPD: return "error: missing or non-positive diagonal entry";
+    case RPCG_ERR_BREAKDOWN: return "error: <d, A d> <= 0";
+    case RPCG_ERR_NONFINITE: return "error: non-finite value";
+    default: return "unknown status";
+    }
+}
+
+int rpcg_create(rpcg_ctx **out, int device)
+{
+    if (!out) return RPCG_ERR_INVALID;
+    *out = nullptr;
+    int count = 0;
+    RPCG_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(device));
+    rpcg_ctx *c = new (std::nothrow) rpcg_ctx();
+    if (!c) return RPCG_ERR_OOM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
+    int rc = hip_status(c->scalars.ensure(1024));
+    if (rc == RPCG_OK) {
+        c->info = (DotInfo *)c->scalars.p;
+        c->st = (PcgState *)((char *)c->scalars.p + 256);
+        rc = hip_status(hipMemset(c->scalars.p, 0, 1024));
+    }
+    if (rc == RPCG_OK) rc = hip_status(hipHostMalloc((void **)&c->host_done, 64 * sizeof(int), hipHostMallocDefault));
+    if (rc == RPCG_OK) rc = hip_status(hipHostMalloc((void **)&c->host_state, sizeof(PcgState), hipHostMallocDefault));
+    if (rc == RPCG_OK) rc = hip_status(hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming));
+    if (rc == RPCG_OK) rc = hip_status(hipEventCreateWithFlags(&c->poll_ev[1], hipEventDisableTiming));
+    if (rc == RPCG_OK) rc = ensure_ws(c, 8 * c->num_cus);
+    if (rc != RPCG_OK) { rpcg_destroy(c); return rc; }
+    *out = c;
+    return RPCG_OK;
+}
+
+void rpcg_destroy(rpcg_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    c->ws_mem.release();
+    c->scalars.release();
+    c->sell_off.release();
+    c->sell_val.release();
+    c->sell_col.release();
+    c->vecs.release();
+    if (c->host_done) hipHostFree(c->host_done);
+    if (c->host_state) hipHostFree(c->host_state);
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
+    for (hipEvent_t e : c->poll_ev) if (e) hipEventDestroy(e);
+    delete c;
+}
+
+static int exdot_status(const DotInfo &inf, int mode, bool fallback)
+{
+    if (inf.flags & FLAG_NONFINITE) return RPCG_ERR_NONFINITE;
+    if (inf.flags & FLAG_INEXACT) return RPCG_WARN_FPE_INEXACT;
+    if (mode == MODE_FPE && inf.escapes > 0 && !fallback) return RPCG_WARN_FPE_INEXACT;
+    return RPCG_OK;
+}
+
+static int run_exdot(rpcg_ctx *c, int mode, int64_t n, const double *x, const double *y, double *out,
+                     int64_t *digits, const rpcg_opts *opts, rpcg_result *res, void *stream)
+{
+    if (!c || n < 0 || (n > 0 && (!x || !y)) || (!out && !digits)) return RPCG_ERR_INVALID;
+    if (mode != MODE_PLAIN && mode != MODE_FPE && mode != MODE_EXBLAS) return RPCG_ERR_INVALID;
+    rpcg_opts o;
+    rpcg_opts_default(&o);
+    if (opts) o = *opts;
+    if (!valid_opts(o)) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    LaunchCfg cfg = make_cfg(c, o, std::max<int64_t>(1, (n + 7) / 8), 256, s);
+    int rc = ensure_ws(c, cfg.grid);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
+    if (digits) RPCG_TRY(launch_exdot_partial(n, x, y, (long long *)digits, c->ws[0], c->info, cfg));
+    else RPCG_TRY(launch_exdot(mode, n, x, y, out, c->ws[0], c->info, cfg));
+    if (res) {
+        std::memset(res, 0, sizeof(*res));
+        DotInfo inf;
+        RPCG_TRY(hipMemcpyAsync(&inf, c->info, sizeof inf, hipMemcpyDeviceToHost, s));
+        RPCG_TRY(hipStreamSynchronize(s));
+        res->fpe_escapes = inf.escapes;
+        res->fallbacks = inf.fallbacks;
+        res->grid_size = cfg.grid;
+        res->block_size = cfg.block;
+        res->status = exdot_status(inf, mode, cfg.fallback);
+        return res->status;
+    }
+    return RPCG_OK;
+}
+
+int rpcg_exdot(rpcg_ctx *c, rpcg_mode mode, int64_t n, const double *x, const double *y, double *out,
+               const rpcg_opts *opts, rpcg_result *res, void *stream)
+{
+    return run_exdot(c, (int)mode, n, x, y, out, nullptr, opts, res, stream);
+}
+
+int rpcg_exdot_partial(rpcg_ctx *c, int64_t n, const double *x, const double *y, int64_t *digits,
+                       void *stream)
+{
+    if (!digits) return RPCG_ERR_INVALID;
+    return run_exdot(c, MODE_EXBLAS, n, x, y, nullptr, digits, nullptr, nullptr, stream);
+}
+
+int rpcg_acc_round(rpcg_ctx *c, const int64_t *digits, double *out, void *stream)
+{
+    if (!c || !digits || !out) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    RPCG_TRY(launch_acc_round((const long long *)digits, out, (hipStream_t)stream));
+    return RPCG_OK;
+}
+
+static bool valid_csr(const rpcg_csr *A)
+{
+    if (!A || A->n < 0 || A->nnz < 0) return false;
+    if (A->n > 0 && (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))) return false;
+    return true;
+}
+
+int rpcg_spmv(rpcg_ctx *c, const rpcg_csr *A, const double *x, double *y, void *stream)
+{
+    if (!c || !valid_csr(A) || (A->n > 0 && (!x || !y)) || (A->n > 0 && x == y)) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    RPCG_TRY(launch_spmv_csr(A->n, A->row_ptr, A->col_idx, A->val, x, y, (hipStream_t)stream));
+    return RPCG_OK;
+}
+
+static int ensure_events(rpcg_ctx *c, size_t need)
+{
+    while (c->events.size() < need) {
+        hipEvent_t e;
+        RPCG_TRY(hipEventCreate(&e));
+        c->events.push_back(e);
+    }
+    return RPCG_OK;
+}
+
+int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const double *b, double *x,
+                   const rpcg_opts *opts, rpcg_result *res, void *stream)
+{
+    using clk = std::chrono::steady_clock;
+    int mode = (int)mode_in;
+    if (res) std::memset(res, 0, sizeof(*res));
+    if (!c || !valid_csr(A) || (A->n > 0 && (!b || !x))) return RPCG_ERR_INVALID;
+    if (mode != MODE_PLAIN && mode != MODE_FPE && mode != MODE_EXBLAS) return RPCG_ERR_INVALID;
+    rpcg_opts o;
+    rpcg_opts_default(&o);
+    if (opts) o = *opts;
+    if (!valid_opts(o)) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int n = A->n;
+    auto t0 = clk::now();
+
+    // workspace: SELL-64 copy of A and five work vectors
+    const int nslices = (n + 63) / 64;
+    LaunchCfg cfg_rows = make_cfg(c, o, std::max(1, n), 256, s);
+    LaunchCfg cfg_sl = make_cfg(c, o, std::max(1ll, (long long)nslices * 64), 256, s);
+    int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
+    if (rc != RPCG_OK) return rc;
+    // the matrix is checked before anything indexes through it
+    int *bad = &c->info->flags;
+    RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
+    RPCG_TRY(launch_csr_check(n, A->nnz, A->row_ptr, A->col_idx, bad, s));
+    int bad_h = 0;
+    RPCG_TRY(hipMemcpyAsync(&bad_h, bad, sizeof bad_h, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    if (bad_h) return RPCG_ERR_INVALID;
+    RPCG_TRY(c->sell_off.ensure(sizeof(long long) * (nslices + 1)));
+    long long *off = (long long *)c->sell_off.p;
+    RPCG_TRY(hipMemsetAsync(off, 0, sizeof(long long) * (nslices + 1), s));
+    RPCG_TRY(launch_sell_widths(n, A->row_ptr, off + 1, nslices, s));
+    RPCG_TRY(launch_sell_scan(off, nslices, s));
+    long long padded = 0;
+    RPCG_TRY(hipMemcpyAsync(&padded, off + nslices, sizeof padded, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    RPCG_TRY(c->sell_val.ensure(sizeof(double) * std::max(1ll, padded)));
+    RPCG_TRY(c->sell_col.ensure(sizeof(int) * std::max(1ll, padded)));
+    RPCG_TRY(launch_sell_fill(n, A->row_ptr, A->col_idx, A->val, off, (double *)c->sell_val.p,
+                              (int *)c->sell_col.p, s));
+    RPCG_TRY(c->vecs.ensure(sizeof(double) * 5 * (size_t)std::max(1, n)));
+    double *vb = (double *)c->vecs.p;
+    PcgVecs v;
+    v.b = b;
+    v.x = x;
+    v.r = vb;
+    v.z = vb + n;
+    v.d = vb + 2 * (size_t)n;
+    v.w = vb + 3 * (size_t)n;
+    v.dinv = vb + 4 * (size_t)n;
+    v.hist = o.tau_history;
+    SellMat M;
+    M.n = n;
+    M.nslices = nslices;
+    M.off = off;
+    M.val = (const double *)c->sell_val.p;
+    M.col = (const int *)c->sell_col.p;
+    M.row_ptr = A->row_ptr;
+
+    RPCG_TRY(launch_pcg_setup(mode, M, A->col_idx, A->val, v, c->st, c->ws, o.tol, o.maxit, cfg_rows));
+    RPCG_TRY(hipStreamSynchronize(s));
+    auto t1 = clk::now();
+
+    // iteration loop: batches of K1/K2/K3, polling the device `done` flag one
+    // batch behind so the host never waits on the iteration it launches
+    const bool timing = o.timing != 0;
+    const int batch = 8;
+    if (timing) { rc = ensure_events(c, (size_t)6 * std::max(1, o.maxit)); if (rc) return rc; }
+    int launched = 0;
+    volatile int *hd = c->host_done;
+    hd[0] = hd[1] = 0;
+    for (int bidx = 0; launched < o.maxit; ++bidx) {
+        int cnt = std::min(batch, o.maxit - launched);
+        for (int it = 0; it < cnt; ++it) {
+            hipEvent_t *ev = timing ? &c->events[(size_t)(launched + it) * 6] : nullptr;
+            if (ev) RPCG_TRY(hipEventRecord(ev[0], s));
+            RPCG_TRY(launch_pcg_spmv_dot(mode, M, v, c->st, c->ws[0], cfg_sl));
+            if (ev) RPCG_TRY(hipEventRecord(ev[1], s));
+            if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
+            RPCG_TRY(launch_pcg_update(mode, n, v, c->st, c->ws + 1, cfg_rows));
+            if (ev) RPCG_TRY(hipEventRecord(ev[3], s));
+            if (ev) RPCG_TRY(hipEventRecord(ev[4], s));
+            RPCG_TRY(launch_pcg_direction(n, v, c->st, cfg_rows));
+            if (ev) RPCG_TRY(hipEventRecord(ev[5], s));
+        }
+        launched += cnt;
+        RPCG_TRY(hipMemcpyAsync((void *)&hd[bidx & 1], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        RPCG_TRY(hipEventRecord(c->poll_ev[bidx & 1], s));
+        if (bidx > 0) {
+            int pb = (bidx - 1) & 1;
+            RPCG_TRY(hipEventSynchronize(c->poll_ev[pb]));
+            if (hd[pb]) break;
+        }
+    }
+    RPCG_TRY(hipStreamSynchronize(s));
+    auto t2 = clk::now();
+    RPCG_TRY(hipMemcpy(c->host_state, c->st, sizeof(PcgState), hipMemcpyDeviceToHost));
+    const PcgState &S = *c->host_state;
+    int status;
+    if (S.status < 0) status = S.status;
+    else if (!(S.tau <= S.thr)) status = RPCG_WARN_MAXIT;
+    else if ((S.flags & FLAG_INEXACT) || (mode == MODE_FPE && S.escapes > 0 && !o.fpe_fallback))
+        status = RPCG_WARN_FPE_INEXACT;
+    else status = RPCG_OK;
+    if (res) {
+        res->status = status;
+        res->iterations = S.iter;
+        res->tau0 = S.tau0;
+        res->tau_final = S.tau;
+        res->threshold = S.thr;
+        res->fpe_escapes = S.escapes;
+        res->fallbacks = S.fallbacks;
+        res->setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        res->loop_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+        res->grid_size = cfg_rows.grid;
+        res->block_size = cfg_rows.block;
+        if (timing) {
+            // the first L launches of each kernel did the work; later ones were no-ops
+            int L = std::min(S.iter, launched);
+            double sums[3] = {0, 0, 0};
+            for (int i = 0; i < L; ++i)
+                for (int k = 0; k < 3; ++k) {
+                    float ms = 0.f;
+                    hipEvent_t *ev = &c->events[(size_t)i * 6];
+                    if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess) sums[k] += ms;
+                }
+            res->k_spmv_dot_ms = sums[0];
+            res->k_update_ms = sums[1];
+            res->k_direction_ms = sums[2];
+            res->k_launches = L;
+        }
+    }
+    return status;
+}
+
+} // extern "C"

@@ -1,0 +1,124 @@
+// Host-visible declarations shared by the kernel translation unit and the
+// C-ABI implementation: device-side state records, workspace descriptors and
+// the launch functions (each kernel is launched only from its own .hip file).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rpcg {
+
+enum Mode { MODE_PLAIN = 0, MODE_FPE = 1, MODE_EXBLAS = 2 };
+
+// Flag bits collected on the device.
+enum {
+    FLAG_NONFINITE = 1, // inf/NaN input, overflowing product or overflowing expansion
+    FLAG_INEXACT = 2,   // a nonzero product below 2^-969 (TwoProd error not representable)
+    FLAG_NOT_SPD = 4,   // missing or non-positive diagonal entry
+};
+
+constexpr int MAX_BLOCK = 1024;
+constexpr int MAX_WAVES = MAX_BLOCK / 64;
+constexpr int MAX_FPE = 8;
+constexpr int ACC_WORDS = 68; // same as ACC_DIGITS in numerics.hpp
+
+// Per-dot reduction workspace for up to `gmax` workgroups.
+struct DotWs {
+    long long *digits; // [gmax][ACC_WORDS] workgroup accumulators (exblas)
+    int *range;        // [gmax][2] nonzero word range of each workgroup accumulator
+    double *part;      // [gmax][MAX_FPE] workgroup expansions (fpe) or partial sums (plain)
+    int *esc;          // [gmax] escape counts (fpe)
+};
+
+// Scalars of one standalone dot call (device memory).
+struct DotInfo {
+    unsigned ticket;
+    int flags;
+    int need_fallback;
+    int pad;
+    long long escapes;
+    long long fallbacks;
+};
+
+// PCG state on the device. Written only by the last workgroup of a kernel
+// (or by a single thread of the setup), read by every workgroup of later
+// kernels.
+struct PcgState {
+    double beta;   // beta of the current iteration (Fig. 2)
+    double rho;    // rho = beta / <d, w>
+    double gamma;  // beta_new / beta_old
+    double tau;    // <r, r>
+    double thr;    // RN(RN(tol*tol) * <b,b>)
+    double delta;  // <d, w>
+    double bb;     // <b, b>
+    double tau0;
+    int iter;      // iterations completed (L)
+    int done;      // nonzero: every later kernel is a no-op
+    int status;    // rpcg status code
+    int maxit;
+    unsigned ticket[4];
+    int flags;
+    int pad;
+    long long escapes;
+    long long fallbacks;
+};
+
+// Sliced-ELL copy of the matrix with slice height 64 (one wavefront): entry
+// k of row 64*s + j sits at off[s] + 64*k + j, so lane j of a wavefront
+// walks its row while each load of the wavefront is one contiguous 512-byte
+// (values) or 256-byte (columns) segment. Rows keep their CSR order and
+// length; padding entries are never read.
+struct SellMat {
+    int n;
+    int nslices;
+    const long long *off; // [nslices + 1]
+    const double *val;
+    const int *col;
+    const int *row_ptr;   // the caller's CSR row pointers (row lengths)
+};
+
+struct LaunchCfg {
+    int grid;
+    int block;
+    bool early_exit;
+    int fpe_size;
+    bool fallback;
+    hipStream_t stream;
+};
+
+// ---- launch functions (return hipError_t of the launch) ----
+
+hipError_t launch_exdot(int mode, long long n, const double *x, const double *y, double *out,
+                        const DotWs &ws, DotInfo *info, const LaunchCfg &cfg);
+hipError_t launch_exdot_partial(long long n, const double *x, const double *y, long long *digits,
+                                const DotWs &ws, DotInfo *info, const LaunchCfg &cfg);
+hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s);
+hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
+                           const double *x, double *y, hipStream_t s);
+
+// Structural check of a caller's CSR (sets *bad to nonzero if malformed).
+hipError_t launch_csr_check(int n, int nnz, const int *row_ptr, const int *col, int *bad, hipStream_t s);
+
+// SELL construction: width of each slice, offsets (prefix sums), fill.
+hipError_t launch_sell_widths(int n, const int *row_ptr, long long *off_plus1, int nslices,
+                              hipStream_t s);
+hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
+hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
+                            const long long *off, double *sval, int *scol, hipStream_t s);
+
+struct PcgVecs {
+    const double *b;
+    double *x, *r, *z, *d, *w, *dinv;
+    double *hist; // optional [maxit + 1]
+};
+
+hipError_t launch_pcg_setup(int mode, const SellMat &A, const int *col, const double *val,
+                            const PcgVecs &v, PcgState *st, const DotWs *ws3, double tol,
+                            int maxit, const LaunchCfg &cfg);
+hipError_t launch_pcg_spmv_dot(int mode, const SellMat &A, const PcgVecs &v, PcgState *st,
+                               const DotWs &ws, const LaunchCfg &cfg);
+hipError_t launch_pcg_update(int mode, int n, const PcgVecs &v, PcgState *st, const DotWs *ws2,
+                             const LaunchCfg &cfg);
+hipError_t launch_pcg_direction(int n, const PcgVecs &v, PcgState *st, const LaunchCfg &cfg);
+
+} // namespace rpcg

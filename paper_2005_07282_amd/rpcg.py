@@ -1,0 +1,255 @@
+"""Python binding of librpcg.so: argument marshalling only.
+
+Every arithmetic step runs in the library's HIP kernels; torch provides the
+device memory (tensors) and the stream. The binding refuses to run if the
+library is missing, is not built for this GPU, or a tensor is not a
+contiguous CUDA/HIP tensor of the right dtype.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librpcg.so")
+
+MODES = {"plain": 0, "fpe": 1, "exblas": 2}
+
+OK, WARN_MAXIT, WARN_FPE_INEXACT = 0, 1, 2
+ERR_INVALID, ERR_HIP, ERR_OOM, ERR_NOT_SPD, ERR_BREAKDOWN, ERR_NONFINITE = -1, -2, -3, -4, -5, -6
+
+ACC_DIGITS = 68
+ACC_EXP0 = -1088
+
+
+class RpcgError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: status {status} ({status_string(status)})")
+        self.status = status
+
+
+class _Csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("fpe_size", ctypes.c_int32),
+                ("early_exit", ctypes.c_int32), ("fpe_fallback", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("tau_history", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("tau0", ctypes.c_double),
+                ("tau_final", ctypes.c_double), ("threshold", ctypes.c_double),
+                ("fpe_escapes", ctypes.c_int64), ("fallbacks", ctypes.c_int64),
+                ("setup_ms", ctypes.c_double), ("loop_ms", ctypes.c_double),
+                ("k_spmv_dot_ms", ctypes.c_double), ("k_update_ms", ctypes.c_double),
+                ("k_direction_ms", ctypes.c_double), ("k_launches", ctypes.c_int32),
+                ("grid_size", ctypes.c_int32), ("block_size", ctypes.c_int32)]
+
+
+_lib = None
+_ctx = {}
+
+
+def lib():
+    """Load librpcg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2005_07282_amd/build.py "
+                               "(or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.rpcg_opts_default.argtypes = [ctypes.POINTER(_Opts)]
+        L.rpcg_opts_default.restype = None
+        L.rpcg_status_string.argtypes = [ctypes.c_int]
+        L.rpcg_status_string.restype = ctypes.c_char_p
+        L.rpcg_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        L.rpcg_create.restype = ctypes.c_int
+        L.rpcg_destroy.argtypes = [P]
+        L.rpcg_destroy.restype = None
+        L.rpcg_exdot.argtypes = [P, ctypes.c_int, I64, P, P, P, ctypes.POINTER(_Opts), ctypes.POINTER(_Result), P]
+        L.rpcg_exdot.restype = ctypes.c_int
+        L.rpcg_spmv.argtypes = [P, ctypes.POINTER(_Csr), P, P, P]
+        L.rpcg_spmv.restype = ctypes.c_int
+        L.rpcg_pcg_solve.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_Opts),
+                                     ctypes.POINTER(_Result), P]
+        L.rpcg_pcg_solve.restype = ctypes.c_int
+        L.rpcg_exdot_partial.argtypes = [P, I64, P, P, P, P]
+        L.rpcg_exdot_partial.restype = ctypes.c_int
+        L.rpcg_acc_round.argtypes = [P, P, P, P]
+        L.rpcg_acc_round.restype = ctypes.c_int
+        _ = I32
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot",
+            "rpcg_spmv", "rpcg_pcg_solve", "rpcg_exdot_partial", "rpcg_acc_round"]
+
+
+def status_string(s: int) -> str:
+    return lib().rpcg_status_string(int(s)).decode()
+
+
+def context(device: int | None = None):
+    """The library context of a device (created once per process)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _ctx:
+        h = ctypes.c_void_p()
+        rc = lib().rpcg_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_create")
+        _ctx[device] = h
+    return _ctx[device]
+
+
+def _stream(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _check(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _opts(**kw) -> _Opts:
+    o = _Opts()
+    lib().rpcg_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if k == "tau_history":
+            _check(v, torch.float64, "tau_history")
+            o.tau_history = v.data_ptr()
+        elif hasattr(o, k):
+            setattr(o, k, v)
+        else:
+            raise TypeError(f"unknown option {k}")
+    return o
+
+
+def _result_dict(r: _Result) -> dict:
+    return {f: getattr(r, f) for f, _ in _Result._fields_}
+
+
+@dataclass
+class CSR:
+    """A CSR matrix whose arrays live on the GPU (int32 indices, float64 values)."""
+    n: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.numel())
+
+    @staticmethod
+    def from_host(A, device="cuda") -> "CSR":
+        return CSR(int(A.n), torch.as_tensor(A.row_ptr, dtype=torch.int32).to(device),
+                   torch.as_tensor(A.col_idx, dtype=torch.int32).to(device),
+                   torch.as_tensor(A.val, dtype=torch.float64).to(device))
+
+    def _c(self) -> _Csr:
+        _check(self.row_ptr, torch.int32, "row_ptr")
+        _check(self.col_idx, torch.int32, "col_idx")
+        _check(self.val, torch.float64, "val")
+        if self.row_ptr.numel() != self.n + 1 or self.val.numel() != self.col_idx.numel():
+            raise ValueError("inconsistent CSR sizes")
+        return _Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.val.data_ptr())
+
+
+def exdot(x: torch.Tensor, y: torch.Tensor, mode: str = "exblas", out: torch.Tensor | None = None,
+          sync: bool = True, **opts):
+    """<x, y> on the GPU. Returns (out tensor of one double, info dict or None if sync=False)."""
+    _check(x, torch.float64, "x")
+    _check(y, torch.float64, "y")
+    if x.numel() != y.numel() or x.device != y.device:
+        raise ValueError("x and y must have the same length and device")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(out, torch.float64, "out")
+    o = _opts(**opts)
+    r = _Result()
+    rc = lib().rpcg_exdot(context(x.device.index), MODES[mode], x.numel(), x.data_ptr(), y.data_ptr(),
+                          out.data_ptr(), ctypes.byref(o), ctypes.byref(r) if sync else None,
+                          _stream(x.device))
+    if rc < 0:
+        raise RpcgError(rc, "rpcg_exdot")
+    return out, (_result_dict(r) if sync else None)
+
+
+def exdot_partial(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """Exact <x, y> as RPCG_ACC_DIGITS int64 digits (digit k weighs 2^(32k - 1088))."""
+    _check(x, torch.float64, "x")
+    _check(y, torch.float64, "y")
+    digits = torch.empty(ACC_DIGITS, dtype=torch.int64, device=x.device)
+    rc = lib().rpcg_exdot_partial(context(x.device.index), x.numel(), x.data_ptr(), y.data_ptr(),
+                                  digits.data_ptr(), _stream(x.device))
+    if rc < 0:
+        raise RpcgError(rc, "rpcg_exdot_partial")
+    return digits
+
+
+def acc_round(digits: torch.Tensor) -> torch.Tensor:
+    _check(digits, torch.int64, "digits")
+    out = torch.empty(1, dtype=torch.float64, device=digits.device)
+    rc = lib().rpcg_acc_round(context(digits.device.index), digits.data_ptr(), out.data_ptr(),
+                              _stream(digits.device))
+    if rc < 0:
+        raise RpcgError(rc, "rpcg_acc_round")
+    return out
+
+
+def digits_to_int(digits: torch.Tensor) -> int:
+    """Exact value of a digit vector as an integer E: value = E * 2^ACC_EXP0."""
+    return sum(int(v) << (32 * k) for k, v in enumerate(digits.cpu().tolist()))
+
+
+def spmv(A: CSR, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+    _check(x, torch.float64, "x")
+    if y is None:
+        y = torch.empty(A.n, dtype=torch.float64, device=x.device)
+    _check(y, torch.float64, "y")
+    c = A._c()
+    rc = lib().rpcg_spmv(context(x.device.index), ctypes.byref(c), x.data_ptr(), y.data_ptr(), _stream(x.device))
+    if rc < 0:
+        raise RpcgError(rc, "rpcg_spmv")
+    return y
+
+
+def pcg_solve(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str = "exblas",
+              history: bool = True, raise_on_error: bool = True, **opts):
+    """Jacobi-PCG. Returns (x, info); info['hist'] holds tau^(0..L) when history=True."""
+    _check(b, torch.float64, "b")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    _check(x, torch.float64, "x")
+    o = _opts(**opts)
+    hist = None
+    if history and o.tau_history is None:
+        hist = torch.zeros(o.maxit + 1, dtype=torch.float64, device=b.device)
+        o.tau_history = hist.data_ptr()
+    c = A._c()
+    r = _Result()
+    rc = lib().rpcg_pcg_solve(context(b.device.index), MODES[mode], ctypes.byref(c), b.data_ptr(),
+                              x.data_ptr(), ctypes.byref(o), ctypes.byref(r), _stream(b.device))
+    info = _result_dict(r)
+    info["status"] = rc
+    if hist is not None:
+        info["hist"] = hist[: r.iterations + 1].cpu()
+    if rc < 0 and raise_on_error:
+        raise RpcgError(rc, "rpcg_pcg_solve")
+    return x, info

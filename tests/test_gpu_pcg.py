@@ -1,0 +1,216 @@
+"""GPU parity of rpcg_pcg_solve against the oracle.
+
+Exact modes (exblas, fpe): iteration count, the whole tau history and the
+solution are bit-identical to the oracle for every launch configuration.
+Plain mode: converges, and its true relative residual is within 1e-12 of
+the oracle's at the same iteration count."""
+
+import math
+
+import numpy as np
+import pytest
+
+from rpcg_workloads import (CSRHost, random_spd_csr, stencil27_csr, stencil27_rhs_from_int52,
+                            stencil7_varcoef_csr, uniform_pm1, uniform_pm1_int52)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_07282_amd import rpcg
+    rpcg.context(0)
+    return rpcg
+
+
+def stencil_problem(N, seed):
+    A = stencil27_csr(N)
+    K = uniform_pm1_int52(seed, A.n)
+    return A, stencil27_rhs_from_int52(N, K), K * 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def w1(orc):
+    """The 32^3 parity workload: 27-point operator, b = A x*, x* ~ U[-1,1) (seed 1)."""
+    A, b, xs = stencil_problem(32, 1)
+    ref = orc.pcg(A, b, tol=1e-8, maxit=2000)
+    assert ref["status"] == 0
+    return A, b, xs, ref
+
+
+def _eq(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return a.shape == b.shape and np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def _solve(R, A, b, mode, **kw):
+    Ad = R.CSR.from_host(A)
+    x, info = R.pcg_solve(Ad, torch.from_numpy(b).cuda(), mode=mode, **kw)
+    return x.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("mode", ["exblas", "fpe"])
+def test_w1_bitexact(R, w1, mode):
+    A, b, xs, ref = w1
+    print(f"pcg 32^3 {mode}", flush=True)
+    x, info = _solve(R, A, b, mode)
+    assert info["status"] == 0
+    assert info["iterations"] == ref["iters"]
+    assert _eq(info["hist"].numpy(), ref["hist"])
+    assert _eq(x, ref["x"])
+    if mode == "fpe":
+        assert info["fpe_escapes"] == 0 and info["fallbacks"] == 0
+
+
+LAUNCH = [(64, 1), (64, 37), (128, 256), (256, 0), (512, 13), (1024, 64), (256, 2048)]
+
+
+@pytest.mark.parametrize("mode", ["exblas", "fpe"])
+def test_w1_launch_config_invariance(R, w1, mode):
+    A, b, xs, ref = w1
+    for block, grid in LAUNCH:
+        for p in ((3, 4, 8) if mode == "fpe" else (1, 4)):
+            print(f"pcg 32^3 {mode} block={block} grid={grid} p={p}", flush=True)
+            x, info = _solve(R, A, b, mode, block_size=block, grid_size=grid, fpe_size=p)
+            assert info["iterations"] == ref["iters"], (block, grid, p)
+            assert _eq(info["hist"].numpy(), ref["hist"]), (block, grid, p)
+            assert _eq(x, ref["x"]), (block, grid, p)
+
+
+def test_w1_plain_within_tolerance(R, orc, w1):
+    """Plain fp64 (the paper's Regular variant): converges; at the oracle's
+    iteration count its true relative residual is within 1e-12 of the oracle's."""
+    A, b, xs, ref = w1
+    x, info = _solve(R, A, b, "plain")
+    assert info["status"] == 0
+    assert abs(info["iterations"] - ref["iters"]) <= 2
+    x2, info2 = _solve(R, A, b, "plain", maxit=ref["iters"])
+    rr_plain = orc.relres_true(A, b, x2)
+    rr_orc = orc.relres_true(A, b, ref["x"])
+    assert abs(rr_plain - rr_orc) <= 1e-12
+    h = info["hist"].numpy()
+    L = min(len(h), len(ref["hist"]))
+    rel = np.abs(h[:L] / ref["hist"][:L] - 1)
+    print("plain vs exact tau, max relative deviation", rel.max())
+    assert rel.max() < 1e-6
+
+
+def test_paper_rhs_ones(R, orc):
+    """Section 5.1: b = A * ones, x0 = 0, tolerance 1e-8."""
+    A = stencil27_csr(24)
+    b = orc.spmv(A, np.ones(A.n))
+    ref = orc.pcg(A, b, tol=1e-8)
+    for mode in ("exblas", "fpe"):
+        x, info = _solve(R, A, b, mode)
+        assert info["iterations"] == ref["iters"]
+        assert _eq(x, ref["x"])
+
+
+@pytest.mark.parametrize("case", ["spd_small", "stencil7", "ragged_n", "nonzero_x0"])
+def test_other_systems_bitexact(R, orc, case):
+    x0 = None
+    if case == "spd_small":
+        A = random_spd_csr(37, 4)
+        b = uniform_pm1(3, A.n)
+    elif case == "stencil7":
+        A = stencil7_varcoef_csr(13, 8)
+        b = uniform_pm1(4, A.n)
+    elif case == "ragged_n":
+        A, b, _ = stencil_problem(11, 6)  # n = 1331, not a multiple of 64
+    else:
+        A, b, _ = stencil_problem(9, 2)
+        x0 = uniform_pm1(9, A.n)
+    ref = orc.pcg(A, b, x0=x0, tol=1e-10, maxit=3000)
+    for mode in ("exblas", "fpe"):
+        Ad = R.CSR.from_host(A)
+        x, info = R.pcg_solve(Ad, torch.from_numpy(b).cuda(), None if x0 is None else torch.from_numpy(x0).cuda(),
+                              mode=mode, tol=1e-10, maxit=3000)
+        assert info["status"] == ref["status"]
+        assert info["iterations"] == ref["iters"], (case, mode)
+        assert _eq(info["hist"].numpy(), ref["hist"])
+        assert _eq(x.cpu().numpy(), ref["x"])
+
+
+def test_status_cases(R, orc):
+    A = stencil27_csr(6)
+    b = orc.spmv(A, np.ones(A.n))
+    # maxit
+    for mode in ("exblas", "fpe", "plain"):
+        x, info = _solve(R, A, b, mode, maxit=3)
+        assert info["status"] == R.WARN_MAXIT and info["iterations"] == 3
+    ref = orc.pcg(A, b, maxit=3)
+    x, info = _solve(R, A, b, "exblas", maxit=3)
+    assert _eq(x, ref["x"]) and _eq(info["hist"].numpy(), ref["hist"])
+    # zero right-hand side: zero iterations
+    x, info = _solve(R, A, np.zeros(A.n), "exblas")
+    assert info["status"] == 0 and info["iterations"] == 0 and not x.any()
+    # maxit = 0
+    x, info = _solve(R, A, b, "exblas", maxit=0)
+    assert info["status"] == R.WARN_MAXIT and info["iterations"] == 0
+    # negative diagonal
+    bad = CSRHost(A.n, A.row_ptr, A.col_idx, np.where(A.val == 26.0, -26.0, A.val))
+    with pytest.raises(R.RpcgError) as e:
+        _solve(R, bad, b, "exblas")
+    assert e.value.status == R.ERR_NOT_SPD
+    # missing diagonal
+    nodiag = CSRHost(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    with pytest.raises(R.RpcgError) as e:
+        _solve(R, nodiag, np.ones(2), "exblas")
+    assert e.value.status == R.ERR_NOT_SPD
+    # non-finite right-hand side
+    bn = b.copy()
+    bn[3] = np.nan
+    with pytest.raises(R.RpcgError) as e:
+        _solve(R, A, bn, "exblas")
+    assert e.value.status == R.ERR_NONFINITE
+    # indefinite: breakdown
+    ind = CSRHost(2, np.array([0, 2, 4], np.int32), np.array([0, 1, 0, 1], np.int32), np.array([1.0, 3.0, 3.0, 1.0]))
+    with pytest.raises(R.RpcgError) as e:
+        _solve(R, ind, np.array([1.0, -1.0]), "exblas")
+    assert e.value.status == R.ERR_BREAKDOWN
+
+
+def test_empty_system(R):
+    A = CSRHost(0, np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0))
+    x, info = _solve(R, A, np.zeros(0), "exblas")
+    assert info["status"] == 0 and info["iterations"] == 0
+
+
+def test_repeat_solves_identical(R, w1):
+    """Back-to-back solves (reused workspace, tickets and state) give the same bits."""
+    A, b, xs, ref = w1
+    xa, ia = _solve(R, A, b, "exblas")
+    xb, ib = _solve(R, A, b, "exblas")
+    assert _eq(xa, xb) and _eq(ia["hist"].numpy(), ib["hist"].numpy())
+
+
+def test_timing_fields(R, w1):
+    A, b, xs, ref = w1
+    x, info = _solve(R, A, b, "exblas", timing=1)
+    assert info["k_launches"] == ref["iters"]
+    assert info["k_spmv_dot_ms"] > 0 and info["k_update_ms"] > 0 and info["k_direction_ms"] > 0
+    assert _eq(x, ref["x"])
+
+
+@pytest.mark.slow
+def test_160_cube_first_iterations_bitexact(R, orc):
+    """Full-size operator (160^3, the bench configuration): the first three
+    iterations match the oracle bit for bit; the full solve converges with
+    the tau history consistent with the stopping rule."""
+    A, b, xs = stencil_problem(160, 2)
+    print("pcg 160^3 maxit=3", flush=True)
+    ref = orc.pcg(A, b, tol=1e-8, maxit=3)
+    x, info = _solve(R, A, b, "exblas", maxit=3)
+    assert _eq(info["hist"].numpy(), ref["hist"])
+    assert _eq(x, ref["x"])
+    print("pcg 160^3 full", flush=True)
+    x, info = _solve(R, A, b, "exblas")
+    assert info["status"] == 0
+    h = info["hist"].numpy()
+    assert h[-1] <= info["threshold"] < h[-2]
+    idx = np.random.default_rng(0).choice(A.n, 2000, replace=False)
+    assert np.max(np.abs(x[idx] - xs[idx])) < 1e-5

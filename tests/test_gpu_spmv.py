@@ -1,0 +1,66 @@
+"""GPU parity of rpcg_spmv against the oracle's fma chains (bit-exact)."""
+
+import numpy as np
+import pytest
+
+from rpcg_workloads import CSRHost, stencil27_csr, stencil7_varcoef_csr, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_07282_amd import rpcg
+    rpcg.context(0)
+    return rpcg
+
+
+def _random_csr(n, seed, maxrow=40):
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, maxrow, n)
+    lens[rng.random(n) < 0.05] = 0
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(lens)
+    col = rng.integers(0, n, rp[-1]).astype(np.int32)
+    val = rng.standard_normal(rp[-1]) * np.exp2(rng.integers(-30, 30, rp[-1]))
+    return CSRHost(n, rp.astype(np.int32), col, val)
+
+
+@pytest.mark.parametrize("case", ["random", "stencil27", "stencil7", "empty_rows", "tiny"])
+def test_spmv_bitexact(R, orc, case):
+    print(f"spmv {case}", flush=True)
+    if case == "random":
+        A = _random_csr(10007, 1)
+    elif case == "stencil27":
+        A = stencil27_csr(19)
+    elif case == "stencil7":
+        A = stencil7_varcoef_csr(17, 3)
+    elif case == "empty_rows":
+        A = CSRHost(5, np.array([0, 0, 2, 2, 3, 3], np.int32), np.array([4, 0, 1], np.int32),
+                    np.array([2.0, -0.0, 3.0]))
+    else:
+        A = CSRHost(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.0]))
+    x = uniform_pm1(5, A.n) * 1e3
+    want = orc.spmv(A, x)
+    y = R.spmv(R.CSR.from_host(A), torch.from_numpy(x).cuda())
+    got = y.cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+def test_spmv_zero_rows(R):
+    A = CSRHost(0, np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0))
+    y = R.spmv(R.CSR.from_host(A), torch.zeros(0, dtype=torch.float64, device="cuda"))
+    assert y.numel() == 0
+
+
+def test_spmv_rejects_aliasing_and_bad_dtype(R):
+    A = stencil27_csr(4)
+    Ad = R.CSR.from_host(A)
+    x = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(R.RpcgError):
+        R.spmv(Ad, x, x)
+    with pytest.raises(TypeError):
+        R.spmv(Ad, x.float())

@@ -1,0 +1,72 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function the
+header declares, and its host-only entry points behave (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rpcg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpcg_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2005_07282_amd import rpcg
+    if not os.path.exists(rpcg.LIB_PATH):
+        from paper_2005_07282_amd import build
+        build.build()
+    return rpcg.lib()
+
+
+def test_header_lists_the_entry_points():
+    names = _declared()
+    for n in ("rpcg_exdot", "rpcg_spmv", "rpcg_pcg_solve", "rpcg_create", "rpcg_destroy",
+              "rpcg_exdot_partial", "rpcg_acc_round", "rpcg_opts_default", "rpcg_status_string"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_binding_names_match_header():
+    from paper_2005_07282_amd import rpcg
+    assert sorted(rpcg.EXPORTED) == _declared()
+
+
+def test_opts_default_and_status_strings(L):
+    from paper_2005_07282_amd import rpcg
+    o = rpcg._Opts()
+    L.rpcg_opts_default(ctypes.byref(o))
+    assert o.tol == 1e-8 and o.maxit == 2000 and o.fpe_size == 4
+    assert o.early_exit == 1 and o.fpe_fallback == 1 and o.tau_history is None
+    for s in (0, 1, 2, -1, -2, -3, -4, -5, -6):
+        assert rpcg.status_string(s) != "unknown status"
+    assert rpcg.status_string(99) == "unknown status"
+
+
+def test_struct_layout_matches_header():
+    """Field order and sizes of the ctypes mirrors agree with the C structs."""
+    from paper_2005_07282_amd import rpcg
+    assert ctypes.sizeof(rpcg._Csr) == 32
+    assert ctypes.sizeof(rpcg._Opts) == 48
+    assert rpcg._Result.iterations.offset == 4 and rpcg._Result.tau0.offset == 8
+
+
+def test_null_arguments_rejected_without_gpu(L):
+    from paper_2005_07282_amd import rpcg
+    assert L.rpcg_create(None, 0) == rpcg.ERR_INVALID
+    assert L.rpcg_exdot(None, 2, 10, None, None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_spmv(None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_pcg_solve(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_acc_round(None, None, None, None) == rpcg.ERR_INVALID
+    L.rpcg_destroy(None)
