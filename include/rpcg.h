@@ -43,7 +43,8 @@ extern "C" {
  *  FPE    - per-lane floating-point expansions (two of size fpe_size: result
  *           and error, Section 4.2) updated with TwoSum (Alg. 1, 4) over
  *           TwoProd (Alg. 2), merged by fpesum (Alg. 3) in a fixed order and
- *           rounded once (NearSum, Section 4.3).
+ *           rounded once (NearSum, Section 4.3); see fpe_fallback for what
+ *           happens when an expansion is too short.
  *  EXBLAS - per-lane expansion flushed into a workgroup long accumulator
  *           (Section 2.1 and 4.1), accumulators summed as integers, rounded
  *           once (exblas Round, Section 4.3). */
@@ -80,12 +81,19 @@ typedef struct {
     int32_t maxit;         /* default 2000 */
     int32_t fpe_size;      /* expansion length p, 1..8 (Section 4.2: tunable); default 4 */
     int32_t early_exit;    /* stop propagating zero errors (Section 4.2); default 1 */
-    int32_t fpe_fallback;  /* FPE mode: if any expansion overflows, recompute that dot
-                              exactly with the long accumulator; default 1 */
-    int32_t block_size;    /* threads per workgroup: 0 = auto, else 64..1024, multiple of 64 */
-    int32_t grid_size;     /* workgroups: 0 = auto, else 1..65536 */
+    int32_t fpe_fallback;  /* FPE mode: what an expansion cannot hold (an escape, the
+                              capacity warning of Section 4.3) is kept exactly in a long
+                              accumulator, so the result stays exact (default 1); 0 drops
+                              it as the expansion-only variant does (RPCG_WARN_FPE_INEXACT) */
+    int32_t block_size;    /* threads per workgroup of the dot and vector kernels:
+                              0 = auto, else 64..1024, multiple of 64 */
+    int32_t grid_size;     /* workgroups of the dot and vector kernels: 0 = auto, else 1..65536 */
     int32_t timing;        /* 1: bracket every solver kernel with HIP events and report
                               per-kernel times in rpcg_result (solver only) */
+    int32_t xcd_parts;     /* SpMV work split into this many contiguous row ranges, one per
+                              XCD (0 = auto = 1, no split). Results do not depend on it. */
+    int32_t spmv_block_size; /* solver SpMV kernel: threads per workgroup (0 = auto) */
+    int32_t spmv_grid_size;  /* solver SpMV kernel: workgroups (0 = auto) */
     double *tau_history;   /* optional DEVICE array of maxit+1 doubles: tau^(0..L) */
 } rpcg_opts;
 
@@ -97,13 +105,13 @@ typedef struct {
     double tau_final;      /* <r_L, r_L> */
     double threshold;      /* RN(RN(tol*tol) * <b,b>) */
     int64_t fpe_escapes;   /* expansion overflows seen (FPE mode) */
-    int64_t fallbacks;     /* dots recomputed with the long accumulator */
+    int64_t fallbacks;     /* FPE mode: dots in which an escape was kept by the long accumulator */
     double setup_ms;       /* wall time of setup (solver) */
     double loop_ms;        /* wall time of the iteration loop (solver) */
     double k_spmv_dot_ms;  /* timing=1: summed HIP-event time of the SpMV+dot kernel */
     double k_update_ms;    /* timing=1: summed time of the update+two-dot kernel */
     double k_direction_ms; /* timing=1: summed time of the direction-update kernel */
-    int32_t k_launches;    /* timing=1: launches of each of the three kernels */
+    int32_t k_launches;    /* timing=1: iterations whose kernels were timed */
     int32_t grid_size;     /* launch configuration actually used */
     int32_t block_size;
 } rpcg_result;

@@ -47,8 +47,9 @@ struct rpcg_ctx {
     Buffer scalars;           // DotInfo + PcgState
     DotInfo *info = nullptr;
     PcgState *st = nullptr;
-    Buffer sell_off, sell_val, sell_col;
+    Buffer sell_off, sell_val, sell_col, sell_len;
     Buffer vecs;              // r, z, d, w, dinv
+    Buffer beta_hist;         // beta of every iteration
     int *host_done = nullptr; // pinned: polled flags
     PcgState *host_state = nullptr;
     std::vector<hipEvent_t> events;
@@ -95,6 +96,10 @@ static bool valid_opts(const rpcg_opts &o)
     if (o.fpe_size < 1 || o.fpe_size > MAX_FPE) return false;
     if (o.block_size != 0 && (o.block_size < 64 || o.block_size > MAX_BLOCK || o.block_size % 64)) return false;
     if (o.grid_size < 0 || o.grid_size > 65536) return false;
+    if (o.xcd_parts < 0 || o.xcd_parts > 64) return false;
+    if (o.spmv_block_size != 0 && (o.spmv_block_size < 64 || o.spmv_block_size > MAX_BLOCK || o.spmv_block_size % 64))
+        return false;
+    if (o.spmv_grid_size < 0 || o.spmv_grid_size > 65536) return false;
     return true;
 }
 
@@ -109,7 +114,28 @@ static LaunchCfg make_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long work_
     cfg.early_exit = o.early_exit != 0;
     cfg.fpe_size = o.fpe_size;
     cfg.fallback = o.fpe_fallback != 0;
+    cfg.xcd_parts = o.xcd_parts ? o.xcd_parts : 1;
     cfg.stream = s;
+    return cfg;
+}
+
+// Vector kernels (setup, K2, K3): 512-thread workgroups, at most two per CU,
+// so that the slot merges in the next kernel's prologue stay short.
+static LaunchCfg make_vec_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long n, hipStream_t s)
+{
+    LaunchCfg cfg = make_cfg(c, o, n, 512, s);
+    if (!o.grid_size) cfg.grid = (int)std::max(1ll, std::min((n + cfg.block - 1) / cfg.block, 2ll * c->num_cus));
+    return cfg;
+}
+
+// SpMV kernel: one wavefront per 64-row slice at a time; own overrides.
+static LaunchCfg make_spmv_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long nslices, hipStream_t s)
+{
+    rpcg_opts q = o;
+    q.block_size = o.spmv_block_size;
+    q.grid_size = o.spmv_grid_size;
+    LaunchCfg cfg = make_cfg(c, q, std::max(1ll, nslices * 64), 256, s);
+    if (!q.grid_size) cfg.grid = (int)std::max(1ll, std::min((nslices * 64 + cfg.block - 1) / cfg.block, 4ll * c->num_cus));
     return cfg;
 }
 
@@ -182,7 +208,9 @@ void rpcg_destroy(rpcg_ctx *c)
     c->sell_off.release();
     c->sell_val.release();
     c->sell_col.release();
+    c->sell_len.release();
     c->vecs.release();
+    c->beta_hist.release();
     if (c->host_done) hipHostFree(c->host_done);
     if (c->host_state) hipHostFree(c->host_state);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
@@ -213,8 +241,8 @@ static int run_exdot(rpcg_ctx *c, int mode, int64_t n, const double *x, const do
     int rc = ensure_ws(c, cfg.grid);
     if (rc != RPCG_OK) return rc;
     RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
-    if (digits) RPCG_TRY(launch_exdot_partial(n, x, y, (long long *)digits, c->ws[0], c->info, cfg));
-    else RPCG_TRY(launch_exdot(mode, n, x, y, out, c->ws[0], c->info, cfg));
+    if (digits) RPCG_TRY(launch_exdot_partial(n, x, y, (long long *)digits, c->ws[0], c->ws_groups, c->info, cfg));
+    else RPCG_TRY(launch_exdot(mode, n, x, y, out, c->ws[0], c->ws_groups, c->info, cfg));
     if (res) {
         std::memset(res, 0, sizeof(*res));
         DotInfo inf;
@@ -266,6 +294,9 @@ int rpcg_spmv(rpcg_ctx *c, const rpcg_csr *A, const double *x, double *y, void *
     return RPCG_OK;
 }
 
+// events per timed iteration: boundaries around K1 | K2 | K3
+static const int EV_PER_IT = 4;
+
 static int ensure_events(rpcg_ctx *c, size_t need)
 {
     while (c->events.size() < need) {
@@ -295,8 +326,8 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
 
     // workspace: SELL-64 copy of A and five work vectors
     const int nslices = (n + 63) / 64;
-    LaunchCfg cfg_rows = make_cfg(c, o, std::max(1, n), 256, s);
-    LaunchCfg cfg_sl = make_cfg(c, o, std::max(1ll, (long long)nslices * 64), 256, s);
+    LaunchCfg cfg_rows = make_vec_cfg(c, o, std::max(1, n), s);
+    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s);
     int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
     if (rc != RPCG_OK) return rc;
     // the matrix is checked before anything indexes through it
@@ -310,15 +341,23 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     RPCG_TRY(c->sell_off.ensure(sizeof(long long) * (nslices + 1)));
     long long *off = (long long *)c->sell_off.p;
     RPCG_TRY(hipMemsetAsync(off, 0, sizeof(long long) * (nslices + 1), s));
-    RPCG_TRY(launch_sell_widths(n, A->row_ptr, off + 1, nslices, s));
+    int *max_len = &c->info->max_len; // zeroed with the info record above
+    RPCG_TRY(launch_sell_widths(n, A->row_ptr, off + 1, nslices, max_len, s));
     RPCG_TRY(launch_sell_scan(off, nslices, s));
     long long padded = 0;
+    int max_len_h = 0;
     RPCG_TRY(hipMemcpyAsync(&padded, off + nslices, sizeof padded, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipMemcpyAsync(&max_len_h, max_len, sizeof max_len_h, hipMemcpyDeviceToHost, s));
     RPCG_TRY(hipStreamSynchronize(s));
     RPCG_TRY(c->sell_val.ensure(sizeof(double) * std::max(1ll, padded)));
     RPCG_TRY(c->sell_col.ensure(sizeof(int) * std::max(1ll, padded)));
+    unsigned char *len8 = nullptr;
+    if (max_len_h < 256) {
+        RPCG_TRY(c->sell_len.ensure((size_t)std::max(1, n)));
+        len8 = (unsigned char *)c->sell_len.p;
+    }
     RPCG_TRY(launch_sell_fill(n, A->row_ptr, A->col_idx, A->val, off, (double *)c->sell_val.p,
-                              (int *)c->sell_col.p, s));
+                              (int *)c->sell_col.p, len8, s));
     RPCG_TRY(c->vecs.ensure(sizeof(double) * 5 * (size_t)std::max(1, n)));
     double *vb = (double *)c->vecs.p;
     PcgVecs v;
@@ -330,6 +369,8 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     v.w = vb + 3 * (size_t)n;
     v.dinv = vb + 4 * (size_t)n;
     v.hist = o.tau_history;
+    RPCG_TRY(c->beta_hist.ensure(sizeof(double) * ((size_t)o.maxit + 1)));
+    v.beta_hist = (double *)c->beta_hist.p;
     SellMat M;
     M.n = n;
     M.nslices = nslices;
@@ -337,8 +378,10 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     M.val = (const double *)c->sell_val.p;
     M.col = (const int *)c->sell_col.p;
     M.row_ptr = A->row_ptr;
+    M.len8 = len8;
 
-    RPCG_TRY(launch_pcg_setup(mode, M, A->col_idx, A->val, v, c->st, c->ws, o.tol, o.maxit, cfg_rows));
+    const int stride = c->ws_groups;
+    RPCG_TRY(launch_pcg_setup(mode, M, A->col_idx, A->val, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_rows));
     RPCG_TRY(hipStreamSynchronize(s));
     auto t1 = clk::now();
 
@@ -346,23 +389,22 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     // batch behind so the host never waits on the iteration it launches
     const bool timing = o.timing != 0;
     const int batch = 8;
-    if (timing) { rc = ensure_events(c, (size_t)6 * std::max(1, o.maxit)); if (rc) return rc; }
+    if (timing) { rc = ensure_events(c, (size_t)EV_PER_IT * std::max(1, o.maxit)); if (rc) return rc; }
     int launched = 0;
     volatile int *hd = c->host_done;
     hd[0] = hd[1] = 0;
     for (int bidx = 0; launched < o.maxit; ++bidx) {
         int cnt = std::min(batch, o.maxit - launched);
         for (int it = 0; it < cnt; ++it) {
-            hipEvent_t *ev = timing ? &c->events[(size_t)(launched + it) * 6] : nullptr;
+            const int l = launched + it;
+            hipEvent_t *ev = timing ? &c->events[(size_t)l * EV_PER_IT] : nullptr;
             if (ev) RPCG_TRY(hipEventRecord(ev[0], s));
-            RPCG_TRY(launch_pcg_spmv_dot(mode, M, v, c->st, c->ws[0], cfg_sl));
+            RPCG_TRY(launch_pcg_spmv_dot(mode, M, v, c->st, c->ws[0], stride, cfg_sl));
             if (ev) RPCG_TRY(hipEventRecord(ev[1], s));
+            RPCG_TRY(launch_pcg_update(mode, l, n, v, c->st, c->ws[0], cfg_sl.grid, c->ws + 1, stride, cfg_rows));
             if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
-            RPCG_TRY(launch_pcg_update(mode, n, v, c->st, c->ws + 1, cfg_rows));
+            RPCG_TRY(launch_pcg_direction(mode, l, n, v, c->st, c->ws + 1, cfg_rows.grid, stride, cfg_rows));
             if (ev) RPCG_TRY(hipEventRecord(ev[3], s));
-            if (ev) RPCG_TRY(hipEventRecord(ev[4], s));
-            RPCG_TRY(launch_pcg_direction(n, v, c->st, cfg_rows));
-            if (ev) RPCG_TRY(hipEventRecord(ev[5], s));
         }
         launched += cnt;
         RPCG_TRY(hipMemcpyAsync((void *)&hd[bidx & 1], &c->st->done, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -396,14 +438,14 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
         res->grid_size = cfg_rows.grid;
         res->block_size = cfg_rows.block;
         if (timing) {
-            // the first L launches of each kernel did the work; later ones were no-ops
+            // the first L iterations did the work; later launches were no-ops
             int L = std::min(S.iter, launched);
             double sums[3] = {0, 0, 0};
             for (int i = 0; i < L; ++i)
                 for (int k = 0; k < 3; ++k) {
                     float ms = 0.f;
-                    hipEvent_t *ev = &c->events[(size_t)i * 6];
-                    if (hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]) == hipSuccess) sums[k] += ms;
+                    hipEvent_t *ev = &c->events[(size_t)i * EV_PER_IT];
+                    if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) sums[k] += ms;
                 }
             res->k_spmv_dot_ms = sums[0];
             res->k_update_ms = sums[1];

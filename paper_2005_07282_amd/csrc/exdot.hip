@@ -1,22 +1,21 @@
-// Standalone dot product kernels (exact, expansion-only and plain), the
+// Standalone dot product kernels (exact, expansion-based and plain), the
 // rounding of a long accumulator, and the CSR SpMV.
 #include "reduce.hpp"
 
 namespace rpcg {
 
 // ---------------------------------------------------------------------------
-// Standalone dot product
+// Standalone dot product: per-workgroup partials, then a one-workgroup
+// finalize that merges them and rounds once.
 
 template <int MODE, int P>
 __global__ void __launch_bounds__(MAX_BLOCK)
-k_exdot(long long n, const double *__restrict__ x, const double *__restrict__ y, double *out,
-        DotWs ws, DotInfo *info, bool ee, bool fallback, bool conditional, long long *digits_out)
+k_exdot_part(long long n, const double *__restrict__ x, const double *__restrict__ y, SlotView sv,
+             DotInfo *info, bool ee, bool capture)
 {
     __shared__ RedShared sh;
-    if (conditional && info->need_fallback == 0) return;
     long long *acc = sh.acc[0];
-    if constexpr (MODE == MODE_EXBLAS) zero_acc(acc);
-    if (threadIdx.x == 0) sh.flags = 0;
+    zero_acc(acc);
     __syncthreads();
 
     LaneDot<MODE, P> L;
@@ -30,48 +29,53 @@ k_exdot(long long n, const double *__restrict__ x, const double *__restrict__ y,
         const double2 *y2 = reinterpret_cast<const double2 *>(y);
         for (long long i = tid; i < n2; i += stride) {
             double2 a = x2[i], b = y2[i];
-            L.add(a.x, b.x, acc, ee);
-            L.add(a.y, b.y, acc, ee);
+            L.add(a.x, b.x, acc, ee, capture);
+            L.add(a.y, b.y, acc, ee, capture);
         }
-        if ((n & 1) && tid == 0) L.add(x[n - 1], y[n - 1], acc, ee);
+        if ((n & 1) && tid == 0) L.add(x[n - 1], y[n - 1], acc, ee, capture);
     } else {
-        for (long long i = tid; i < n; i += stride) L.add(x[i], y[i], acc, ee);
+        for (long long i = tid; i < n; i += stride) L.add(x[i], y[i], acc, ee, capture);
     }
-    block_finish<MODE, P>(L, acc, ws, blockIdx.x, ee, &info->flags, sh);
-    if (!arrive_last(&info->ticket, sh)) return;
+    block_finish<MODE, P>(L, acc, sv, blockIdx.x, ee, capture, &info->flags, sh);
+}
 
-    long long esc = 0;
-    double r;
+// One workgroup: merges the G slots, rounds, writes *out and the counters;
+// or, with digits_out, writes the exact sum as normalized accumulator words.
+template <int MODE, int P>
+__global__ void __launch_bounds__(MAX_BLOCK)
+k_exdot_fin(int G, SlotView sv, DotInfo *info, double *out, long long *digits_out, bool ee, bool capture)
+{
+    __shared__ RedShared sh;
+    long long *acc = sh.acc[0];
     if (digits_out) {
-        // exact partial: sum the slots into the caller's digit vector, fully normalized
         if constexpr (MODE == MODE_EXBLAS) {
             zero_acc(acc);
             __syncthreads();
-            for (int k = 0; k < ACC_DIGITS; ++k) {
-                long long s = 0;
-                for (int g = threadIdx.x; g < (int)gridDim.x; g += blockDim.x)
-                    s += ws.digits[(long long)g * ACC_DIGITS + k];
-                s = block_sum_ll(s, sh);
-                if (threadIdx.x == 0) acc[k] = s;
+            for (int k = wave_id(); k < ACC_DIGITS; k += num_waves()) {
+                long long s = sum_row(sv.ws.digits + (long long)k * sv.stride, G);
+                if (lane_id() == 0) acc[k] = s;
             }
-            if (threadIdx.x == 0) {
-                acc_normalize(acc);
-                for (int k = 0; k < ACC_DIGITS; ++k) digits_out[k] = acc[k];
+            __syncthreads();
+            if (wave_id() == 0) {
+                const int l = lane_id();
+                long long a = (2 * l < ACC_DIGITS) ? acc[2 * l] : 0;
+                long long b = (2 * l + 1 < ACC_DIGITS) ? acc[2 * l + 1] : 0;
+                wave_normalize(a, b);
+                if (2 * l < ACC_DIGITS) digits_out[2 * l] = a;
+                if (2 * l + 1 < ACC_DIGITS) digits_out[2 * l + 1] = b;
             }
         }
         return;
     }
-    r = merge_slots<MODE, P>(ws, gridDim.x, ee, acc, &info->flags, &esc, sh);
-    if constexpr (MODE == MODE_FPE) {
-        if (threadIdx.x == 0) {
+    long long esc = 0;
+    int fl = 0;
+    double r = merge_slots<MODE, P>(sv, G, ee, capture, acc, &esc, &info->flags, sh, 0);
+    if (threadIdx.x == 0) {
+        fl = info->flags;
+        *out = (fl & FLAG_NONFINITE) ? __builtin_nan("") : r;
+        if constexpr (MODE == MODE_FPE) {
             info->escapes += esc;
-            info->need_fallback = (fallback && esc > 0) ? 1 : 0;
-            *out = r;
-        }
-    } else {
-        if (threadIdx.x == 0) {
-            *out = r;
-            if (conditional) { info->need_fallback = 0; info->fallbacks += 1; }
+            if (esc > 0 && capture) info->fallbacks += 1;
         }
     }
 }
@@ -81,7 +85,8 @@ __global__ void k_acc_round(const long long *digits, double *out)
     __shared__ long long acc[ACC_DIGITS];
     for (int k = threadIdx.x; k < ACC_DIGITS; k += blockDim.x) acc[k] = digits[k];
     __syncthreads();
-    if (threadIdx.x == 0) *out = acc_round(acc);
+    double r = wave_acc_round(acc);
+    if (threadIdx.x == 0) *out = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -103,27 +108,24 @@ __global__ void k_spmv_csr(int n, const int *__restrict__ rp, const int *__restr
 // Launch functions
 
 hipError_t launch_exdot(int mode, long long n, const double *x, const double *y, double *out,
-                        const DotWs &ws, DotInfo *info, const LaunchCfg &c)
+                        const DotWs &ws, int stride, DotInfo *info, const LaunchCfg &c)
 {
+    SlotView sv{ws, stride};
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
-        k_exdot<decltype(m)::value, decltype(p)::value><<<c.grid, c.block, 0, c.stream>>>(
-            n, x, y, out, ws, info, c.early_exit, c.fallback, false, nullptr);
+        constexpr int M = decltype(m)::value, PP = decltype(p)::value;
+        k_exdot_part<M, PP><<<c.grid, c.block, 0, c.stream>>>(n, x, y, sv, info, c.early_exit, c.fallback);
+        k_exdot_fin<M, PP><<<1, MAX_BLOCK, 0, c.stream>>>(c.grid, sv, info, out, nullptr, c.early_exit,
+                                                          c.fallback);
     });
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (mode == MODE_FPE && c.fallback) {
-        hipLaunchKernelGGL((k_exdot<MODE_EXBLAS, 4>), dim3(c.grid), dim3(c.block), 0, c.stream,
-                           n, x, y, out, ws, info, true, false, true, nullptr);
-        e = hipGetLastError();
-    }
-    return e;
+    return hipGetLastError();
 }
 
 hipError_t launch_exdot_partial(long long n, const double *x, const double *y, long long *digits,
-                                const DotWs &ws, DotInfo *info, const LaunchCfg &c)
+                                const DotWs &ws, int stride, DotInfo *info, const LaunchCfg &c)
 {
-    hipLaunchKernelGGL((k_exdot<MODE_EXBLAS, 4>), dim3(c.grid), dim3(c.block), 0, c.stream,
-                       n, x, y, nullptr, ws, info, true, false, false, digits);
+    SlotView sv{ws, stride};
+    k_exdot_part<MODE_EXBLAS, 4><<<c.grid, c.block, 0, c.stream>>>(n, x, y, sv, info, true, true);
+    k_exdot_fin<MODE_EXBLAS, 4><<<1, MAX_BLOCK, 0, c.stream>>>(c.grid, sv, info, nullptr, digits, true, true);
     return hipGetLastError();
 }
 

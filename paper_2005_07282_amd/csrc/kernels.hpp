@@ -22,9 +22,9 @@ constexpr int MAX_WAVES = MAX_BLOCK / 64;
 constexpr int MAX_FPE = 8;
 constexpr int ACC_WORDS = 68; // same as ACC_DIGITS in numerics.hpp
 
-// Per-dot reduction workspace for up to `gmax` workgroups.
+// Per-dot reduction workspace for up to `gmax` workgroups (slots).
 struct DotWs {
-    long long *digits; // [gmax][ACC_WORDS] workgroup accumulators (exblas)
+    long long *digits; // [ACC_WORDS][gmax] workgroup accumulator words, word-major
     int *range;        // [gmax][2] nonzero word range of each workgroup accumulator
     double *part;      // [gmax][MAX_FPE] workgroup expansions (fpe) or partial sums (plain)
     int *esc;          // [gmax] escape counts (fpe)
@@ -32,9 +32,9 @@ struct DotWs {
 
 // Scalars of one standalone dot call (device memory).
 struct DotInfo {
-    unsigned ticket;
+    unsigned pad0;
     int flags;
-    int need_fallback;
+    int max_len;   // longest row (SELL construction scratch)
     int pad;
     long long escapes;
     long long fallbacks;
@@ -56,7 +56,6 @@ struct PcgState {
     int done;      // nonzero: every later kernel is a no-op
     int status;    // rpcg status code
     int maxit;
-    unsigned ticket[4];
     int flags;
     int pad;
     long long escapes;
@@ -75,6 +74,7 @@ struct SellMat {
     const double *val;
     const int *col;
     const int *row_ptr;   // the caller's CSR row pointers (row lengths)
+    const unsigned char *len8; // row lengths as bytes when every row has < 256 entries, else null
 };
 
 struct LaunchCfg {
@@ -83,15 +83,17 @@ struct LaunchCfg {
     bool early_exit;
     int fpe_size;
     bool fallback;
+    int xcd_parts; // SpMV: number of contiguous slice ranges (one per XCD)
     hipStream_t stream;
 };
 
 // ---- launch functions (return hipError_t of the launch) ----
+// `stride` is the slot capacity of the dot workspaces (see DotWs).
 
 hipError_t launch_exdot(int mode, long long n, const double *x, const double *y, double *out,
-                        const DotWs &ws, DotInfo *info, const LaunchCfg &cfg);
+                        const DotWs &ws, int stride, DotInfo *info, const LaunchCfg &cfg);
 hipError_t launch_exdot_partial(long long n, const double *x, const double *y, long long *digits,
-                                const DotWs &ws, DotInfo *info, const LaunchCfg &cfg);
+                                const DotWs &ws, int stride, DotInfo *info, const LaunchCfg &cfg);
 hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s);
 hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
                            const double *x, double *y, hipStream_t s);
@@ -101,24 +103,30 @@ hipError_t launch_csr_check(int n, int nnz, const int *row_ptr, const int *col, 
 
 // SELL construction: width of each slice, offsets (prefix sums), fill.
 hipError_t launch_sell_widths(int n, const int *row_ptr, long long *off_plus1, int nslices,
-                              hipStream_t s);
+                              int *max_len, hipStream_t s);
 hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
 hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
-                            const long long *off, double *sval, int *scol, hipStream_t s);
+                            const long long *off, double *sval, int *scol, unsigned char *len8,
+                            hipStream_t s);
 
 struct PcgVecs {
     const double *b;
     double *x, *r, *z, *d, *w, *dinv;
-    double *hist; // optional [maxit + 1]
+    double *hist;      // optional [maxit + 1]: tau history
+    double *beta_hist; // [maxit + 1]: beta of every iteration
 };
 
+// Setup (state init, partials, one-workgroup finalize) into ws3[0..2].
 hipError_t launch_pcg_setup(int mode, const SellMat &A, const int *col, const double *val,
-                            const PcgVecs &v, PcgState *st, const DotWs *ws3, double tol,
+                            const PcgVecs &v, PcgState *st, const DotWs *ws3, int stride, double tol,
                             int maxit, const LaunchCfg &cfg);
+// Iteration l: K1 writes its partials to `ws`; K2 merges them (Gd slots) and
+// writes two dots into ws2[0..1]; K3 merges those (G slots).
 hipError_t launch_pcg_spmv_dot(int mode, const SellMat &A, const PcgVecs &v, PcgState *st,
-                               const DotWs &ws, const LaunchCfg &cfg);
-hipError_t launch_pcg_update(int mode, int n, const PcgVecs &v, PcgState *st, const DotWs *ws2,
-                             const LaunchCfg &cfg);
-hipError_t launch_pcg_direction(int n, const PcgVecs &v, PcgState *st, const LaunchCfg &cfg);
+                               const DotWs &ws, int stride, const LaunchCfg &cfg);
+hipError_t launch_pcg_update(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs &wsd, int Gd,
+                             const DotWs *ws2, int stride, const LaunchCfg &cfg);
+hipError_t launch_pcg_direction(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs *ws2, int G,
+                                int stride, const LaunchCfg &cfg);
 
 } // namespace rpcg

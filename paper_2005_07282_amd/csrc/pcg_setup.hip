@@ -1,10 +1,8 @@
-// Jacobi-PCG setup kernel: preconditioner, initial residual and dots.
+// Jacobi-PCG setup kernels: preconditioner, initial residual and dots
+// (Fig. 1/Fig. 2 initialisation; Section 4.3 Jacobi: inverse diagonal once).
 #include "reduce.hpp"
 
 namespace rpcg {
-
-// ---------------------------------------------------------------------------
-// Jacobi-PCG kernels (Fig. 2 order; S8 with S6)
 
 __global__ void k_state_init(PcgState *st, int maxit)
 {
@@ -14,16 +12,16 @@ __global__ void k_state_init(PcgState *st, int maxit)
     *st = z;
 }
 
-// Setup: dinv = 1/a_ii, r = b - A x0, z = dinv r, d = z, and the dots
-// beta = <z,r>, tau = <r,r>, <b,b>; then thr and the stopping test.
+// dinv = RN(1/a_ii), r = RN(b - A x0), z = RN(dinv r), d = z, and the
+// workgroup partials of <z,r>, <r,r>, <b,b>.
 template <int MODE, int P>
 __global__ void __launch_bounds__(MAX_BLOCK)
 k_pcg_setup(int n, const int *__restrict__ rp, const int *__restrict__ col,
-            const double *__restrict__ val, PcgVecs v, PcgState *st, DotWs w0, DotWs w1, DotWs w2,
-            double tol, bool ee, bool fallback)
+            const double *__restrict__ val, PcgVecs v, PcgState *st, SlotView w0, SlotView w1, SlotView w2,
+            bool ee, bool capture)
 {
     __shared__ RedShared sh;
-    if constexpr (MODE == MODE_EXBLAS) { zero_acc(sh.acc[0]); zero_acc(sh.acc[1]); zero_acc(sh.acc[2]); }
+    zero_acc(sh.acc[0]); zero_acc(sh.acc[1]); zero_acc(sh.acc[2]);
     __syncthreads();
     LaneDot<MODE, P> Lb, Lt, Lbb;
     Lb.init(); Lt.init(); Lbb.init();
@@ -47,33 +45,32 @@ k_pcg_setup(int n, const int *__restrict__ rp, const int *__restrict__ col,
         v.r[i] = ri;
         v.z[i] = zi;
         v.d[i] = zi;
-        Lb.add(zi, ri, sh.acc[0], ee);
-        Lt.add(ri, ri, sh.acc[1], ee);
-        Lbb.add(bi, bi, sh.acc[2], ee);
+        Lb.add(zi, ri, sh.acc[0], ee, capture);
+        Lt.add(ri, ri, sh.acc[1], ee, capture);
+        Lbb.add(bi, bi, sh.acc[2], ee, capture);
     }
     if (flags) atomicOr(&st->flags, flags);
-    block_finish<MODE, P>(Lb, sh.acc[0], w0, blockIdx.x, ee, &st->flags, sh);
-    block_finish<MODE, P>(Lt, sh.acc[1], w1, blockIdx.x, ee, &st->flags, sh);
-    block_finish<MODE, P>(Lbb, sh.acc[2], w2, blockIdx.x, ee, &st->flags, sh);
-    if (!arrive_last(&st->ticket[0], sh)) return;
+    block_finish<MODE, P>(Lb, sh.acc[0], w0, blockIdx.x, ee, capture, &st->flags, sh);
+    block_finish<MODE, P>(Lt, sh.acc[1], w1, blockIdx.x, ee, capture, &st->flags, sh);
+    block_finish<MODE, P>(Lbb, sh.acc[2], w2, blockIdx.x, ee, capture, &st->flags, sh);
+}
 
+// One workgroup: beta0, tau0, <b,b>; thr = RN(RN(tol*tol) <b,b>); stopping test.
+template <int MODE, int P>
+__global__ void __launch_bounds__(MAX_BLOCK)
+k_pcg_fin_setup(int G, PcgVecs v, PcgState *st, SlotView w0, SlotView w1, SlotView w2, double tol, bool ee,
+                bool capture)
+{
+    __shared__ RedShared sh;
     long long e0, e1, e2;
-    double beta = merge_slots<MODE, P>(w0, gridDim.x, ee, sh.acc[0], &st->flags, &e0, sh);
-    double tau = merge_slots<MODE, P>(w1, gridDim.x, ee, sh.acc[1], &st->flags, &e1, sh);
-    double bb = merge_slots<MODE, P>(w2, gridDim.x, ee, sh.acc[2], &st->flags, &e2, sh);
-    if constexpr (MODE == MODE_FPE) {
-        if (threadIdx.x == 0) sh.need_fb = fallback && (e0 + e1 + e2) > 0;
-        __syncthreads();
-        if (sh.need_fb) {
-            double t0 = block_exact_dot(n, v.z, v.r, sh.acc[0], &st->flags, sh);
-            double t1 = block_exact_dot(n, v.r, v.r, sh.acc[0], &st->flags, sh);
-            double t2 = block_exact_dot(n, v.b, v.b, sh.acc[0], &st->flags, sh);
-            if (threadIdx.x == 0) { beta = t0; tau = t1; bb = t2; st->fallbacks += 1; }
-        }
-    }
+    double beta = merge_slots<MODE, P>(w0, G, ee, capture, sh.acc[0], &e0, &st->flags, sh, 0);
+    double tau = merge_slots<MODE, P>(w1, G, ee, capture, sh.acc[1], &e1, &st->flags, sh, 1);
+    double bb = merge_slots<MODE, P>(w2, G, ee, capture, sh.acc[2], &e2, &st->flags, sh, 2);
     if (threadIdx.x == 0) {
         st->escapes += e0 + e1 + e2;
+        if (capture) st->fallbacks += (e0 > 0) + (e1 > 0) + (e2 > 0);
         int f = st->flags;
+        v.beta_hist[0] = beta;
         st->beta = beta;
         st->tau = tau;
         st->tau0 = tau;
@@ -88,19 +85,20 @@ k_pcg_setup(int n, const int *__restrict__ rp, const int *__restrict__ col,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Launch functions
-
 hipError_t launch_pcg_setup(int mode, const SellMat &A, const int *col, const double *val,
-                            const PcgVecs &v, PcgState *st, const DotWs *ws3, double tol, int maxit,
+                            const PcgVecs &v, PcgState *st, const DotWs *ws3, int stride, double tol, int maxit,
                             const LaunchCfg &c)
 {
+    SlotView s0{ws3[0], stride}, s1{ws3[1], stride}, s2{ws3[2], stride};
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, c.stream, st, maxit);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
-        k_pcg_setup<decltype(m)::value, decltype(p)::value><<<c.grid, c.block, 0, c.stream>>>(
-            A.n, A.row_ptr, col, val, v, st, ws3[0], ws3[1], ws3[2], tol, c.early_exit, c.fallback);
+        constexpr int M = decltype(m)::value, PP = decltype(p)::value;
+        k_pcg_setup<M, PP><<<c.grid, c.block, 0, c.stream>>>(A.n, A.row_ptr, col, val, v, st, s0, s1, s2,
+                                                             c.early_exit, c.fallback);
+        k_pcg_fin_setup<M, PP><<<1, MAX_BLOCK, 0, c.stream>>>(c.grid, v, st, s0, s1, s2, tol, c.early_exit,
+                                                              c.fallback);
     });
     return hipGetLastError();
 }

@@ -1,94 +1,135 @@
-// Jacobi-PCG iteration, second and third kernels: vector updates, Jacobi
-// preconditioner and the two fused dots (S3-S6, S8), then the search
-// direction update (S7).
+// Jacobi-PCG iteration, second and third kernels.
+//
+// K2 starts by merging the SpMV kernel's partials of <d, w> (every workgroup
+// alike) into delta and rho = beta / delta (S2), then applies the vector
+// updates and the Jacobi preconditioner (S3-S5) and forms the partials of
+// beta = <z, r> and tau = <r, r> (S6, S8).
+// K3 starts by merging those into beta, tau and gamma = beta / beta_old, runs
+// the stopping test of Fig. 1, and updates the search direction (S7).
+//
+// The iteration number l is a launch argument, so the scalars one kernel
+// writes for later iterations (beta history, tau history, done flag) are
+// never read by another workgroup of the same kernel.
 #include "reduce.hpp"
 
 namespace rpcg {
 
-// K2: x += rho d (S3), r -= rho w (S4), z = dinv r (S5), beta = <z,r> (S6),
-// tau = <r,r> (S8); the last workgroup sets gamma, the history and `done`.
 template <int MODE, int P>
 __global__ void __launch_bounds__(MAX_BLOCK)
-k_pcg_update(int n, PcgVecs v, PcgState *st, DotWs wb, DotWs wt, bool ee, bool fallback)
+k_pcg_update(int l, int n, PcgVecs v, PcgState *st, SlotView sd, int Gd, SlotView wb, SlotView wt, bool ee,
+             bool capture)
 {
     __shared__ RedShared sh;
     if (st->done) return;
-    if constexpr (MODE == MODE_EXBLAS) { zero_acc(sh.acc[0]); zero_acc(sh.acc[1]); }
+    // S2: delta = <d, w> rounded once; rho = beta_l / delta
+    long long esc_d = 0;
+    const double delta = merge_slots<MODE, P>(sd, Gd, ee, capture, sh.acc[0], &esc_d, &st->flags, sh, 0);
+    const bool bad = (st->flags & FLAG_NONFINITE) || !is_finite_bits(delta);
+    const bool breakdown = !(delta > 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->escapes += esc_d;
+        if (capture && esc_d > 0) st->fallbacks += 1;
+        st->delta = delta;
+        if (bad) { st->status = -6; st->done = 1; }
+        else if (breakdown) { st->status = -5; st->done = 1; }
+    }
+    if (bad || breakdown) return;
+    const double rho = v.beta_hist[l] / delta;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rho = rho;
+
+    zero_acc(sh.acc[0]);
+    zero_acc(sh.acc[1]);
     __syncthreads();
-    const double rho = st->rho;
     LaneDot<MODE, P> Lb, Lt;
-    Lb.init(); Lt.init();
+    Lb.init();
+    Lt.init();
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
         double di = v.d[i], wi = v.w[i];
-        v.x[i] = __builtin_fma(rho, di, v.x[i]);
-        double ri = __builtin_fma(-rho, wi, v.r[i]);
-        double zi = v.dinv[i] * ri;
+        v.x[i] = __builtin_fma(rho, di, v.x[i]);         // S3
+        double ri = __builtin_fma(-rho, wi, v.r[i]);      // S4
+        double zi = v.dinv[i] * ri;                       // S5
         v.r[i] = ri;
         v.z[i] = zi;
-        Lb.add(zi, ri, sh.acc[0], ee);
-        Lt.add(ri, ri, sh.acc[1], ee);
+        Lb.add(zi, ri, sh.acc[0], ee, capture);           // S6
+        Lt.add(ri, ri, sh.acc[1], ee, capture);           // S8
     }
-    block_finish<MODE, P>(Lb, sh.acc[0], wb, blockIdx.x, ee, &st->flags, sh);
-    block_finish<MODE, P>(Lt, sh.acc[1], wt, blockIdx.x, ee, &st->flags, sh);
-    if (!arrive_last(&st->ticket[2], sh)) return;
-
-    long long eb, et;
-    double beta = merge_slots<MODE, P>(wb, gridDim.x, ee, sh.acc[0], &st->flags, &eb, sh);
-    double tau = merge_slots<MODE, P>(wt, gridDim.x, ee, sh.acc[1], &st->flags, &et, sh);
-    if constexpr (MODE == MODE_FPE) {
-        if (threadIdx.x == 0) sh.need_fb = fallback && (eb + et) > 0;
-        __syncthreads();
-        if (sh.need_fb) {
-            double t0 = block_exact_dot(n, v.z, v.r, sh.acc[0], &st->flags, sh);
-            double t1 = block_exact_dot(n, v.r, v.r, sh.acc[0], &st->flags, sh);
-            if (threadIdx.x == 0) { beta = t0; tau = t1; st->fallbacks += 1; }
-        }
-    }
-    if (threadIdx.x == 0) {
-        st->escapes += eb + et;
-        if ((st->flags & FLAG_NONFINITE) || !is_finite_bits(beta) || !is_finite_bits(tau)) {
-            st->status = -6;
-            st->done = 1;
-        } else {
-            st->gamma = beta / st->beta;
-            st->beta = beta;
-            st->tau = tau;
-            int it = st->iter + 1;
-            st->iter = it;
-            if (v.hist) v.hist[it] = tau;
-            if (tau <= st->thr || it >= st->maxit) st->done = 1;
-        }
-    }
+    block_finish<MODE, P>(Lb, sh.acc[0], wb, blockIdx.x, ee, capture, &st->flags, sh);
+    block_finish<MODE, P>(Lt, sh.acc[1], wt, blockIdx.x, ee, capture, &st->flags, sh);
 }
 
-// K3: d = gamma d + z (S7).
+// Elements per thread whose operands K3 loads before merging the dots, so
+// the loads are in flight while the merge runs.
+constexpr int DIR_PREFETCH = 8;
+
+template <int MODE, int P>
 __global__ void __launch_bounds__(MAX_BLOCK)
-k_pcg_direction(int n, PcgVecs v, const PcgState *st)
+k_pcg_direction(int l, int n, PcgVecs v, PcgState *st, SlotView wb, SlotView wt, int G, bool ee, bool capture)
 {
+    __shared__ RedShared sh;
     if (st->done) return;
-    const double gamma = st->gamma;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
+    const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    double dv[DIR_PREFETCH], zv[DIR_PREFETCH];
+#pragma unroll
+    for (int j = 0; j < DIR_PREFETCH; ++j) {
+        const long long i = i0 + j * stride;
+        dv[j] = i < n ? v.d[i] : 0.0;
+        zv[j] = i < n ? v.z[i] : 0.0;
+    }
+    long long eb = 0, et = 0;
+    const double beta = merge_slots<MODE, P>(wb, G, ee, capture, sh.acc[0], &eb, &st->flags, sh, 0);
+    const double tau = merge_slots<MODE, P>(wt, G, ee, capture, sh.acc[1], &et, &st->flags, sh, 1);
+    const bool bad = (st->flags & FLAG_NONFINITE) || !is_finite_bits(beta) || !is_finite_bits(tau);
+    const int it = l + 1;
+    const bool stop = bad || tau <= st->thr || it >= st->maxit;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->escapes += eb + et;
+        if (capture) st->fallbacks += (eb > 0) + (et > 0);
+        if (bad) {
+            st->status = -6;
+        } else {
+            v.beta_hist[it] = beta;
+            st->beta = beta;
+            st->tau = tau;
+            st->iter = it;
+            if (v.hist) v.hist[it] = tau;
+        }
+        if (stop) st->done = 1;
+    }
+    if (stop) return;
+    const double gamma = beta / v.beta_hist[l];
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->gamma = gamma;
+#pragma unroll
+    for (int j = 0; j < DIR_PREFETCH; ++j) {
+        const long long i = i0 + j * stride;
+        if (i < n) v.d[i] = __builtin_fma(gamma, dv[j], zv[j]);   // S7
+    }
+    for (long long i = i0 + DIR_PREFETCH * stride; i < n; i += stride)
         v.d[i] = __builtin_fma(gamma, v.d[i], v.z[i]);
 }
 
-// ---------------------------------------------------------------------------
-// Launch functions
-
-hipError_t launch_pcg_update(int mode, int n, const PcgVecs &v, PcgState *st, const DotWs *ws2,
-                             const LaunchCfg &c)
+hipError_t launch_pcg_update(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs &wsd, int Gd,
+                             const DotWs *ws2, int stride, const LaunchCfg &c)
 {
+    SlotView sd{wsd, stride}, sb{ws2[0], stride}, stt{ws2[1], stride};
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
-        k_pcg_update<decltype(m)::value, decltype(p)::value><<<c.grid, c.block, 0, c.stream>>>(
-            n, v, st, ws2[0], ws2[1], c.early_exit, c.fallback);
+        constexpr int M = decltype(m)::value, PP = decltype(p)::value;
+        k_pcg_update<M, PP><<<c.grid, c.block, 0, c.stream>>>(l, n, v, st, sd, Gd, sb, stt, c.early_exit,
+                                                              c.fallback);
     });
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_direction(int n, const PcgVecs &v, PcgState *st, const LaunchCfg &c)
+hipError_t launch_pcg_direction(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs *ws2, int G,
+                                int stride, const LaunchCfg &c)
 {
-    hipLaunchKernelGGL(k_pcg_direction, dim3(c.grid), dim3(c.block), 0, c.stream, n, v, st);
+    SlotView sb{ws2[0], stride}, stt{ws2[1], stride};
+    dispatch(mode, c.fpe_size, [&](auto m, auto p) {
+        constexpr int M = decltype(m)::value, PP = decltype(p)::value;
+        k_pcg_direction<M, PP><<<c.grid, c.block, 0, c.stream>>>(l, n, v, st, sb, stt, G, c.early_exit,
+                                                                 c.fallback);
+    });
     return hipGetLastError();
 }
 

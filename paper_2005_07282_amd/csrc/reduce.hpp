@@ -1,15 +1,18 @@
 // Device-side reduction machinery shared by the kernel translation units:
-// per-lane accumulators, workgroup partials, the last-workgroup ticket and
-// the merge of workgroup partials.
+// per-lane accumulators, workgroup partials, the merge of workgroup partials
+// and the correctly rounded conversion of a long accumulator.
 //
 // Reduction structure (Section 3.2 / 4.3 mapped onto one GPU): each lane
-// keeps its own accumulator (an expansion, or a plain sum), the lanes of a
+// keeps its own accumulator (an expansion, or a plain sum); the lanes of a
 // workgroup combine into one workgroup partial (a long accumulator in LDS,
-// or an expansion merged in a fixed tree), every workgroup writes its
-// partial to a slot, and the last workgroup to arrive (atomic ticket with
-// device-scope release/acquire fences) combines the slots and rounds once.
-// This replaces the paper's MPI_Reduce + Round + MPI_Bcast: the rounded
-// scalar lands in device memory where the next kernel reads it.
+// or an expansion merged in a fixed tree) written to a slot. The kernel that
+// needs the scalar next merges all slots in a fixed order at its start, in
+// every workgroup alike, and rounds once; the kernel boundary makes the slots
+// visible, so no device-scope fence or atomic ticket is needed inside the
+// producing kernel (on multi-XCD gfx950 a per-workgroup release fence writes
+// back the XCD's L2 and serialises the workgroups). This replaces the paper's
+// MPI_Reduce + Round + MPI_Bcast: every consumer computes the same rounded
+// scalar from the same integers.
 #pragma once
 
 #include "kernels.hpp"
@@ -18,7 +21,6 @@
 #include <type_traits>
 
 namespace rpcg {
-
 
 static_assert(ACC_WORDS == ACC_DIGITS, "accumulator size mismatch");
 
@@ -37,15 +39,13 @@ __device__ __forceinline__ T wave_sum_down(T v)
 
 // Shared memory of the reduction machinery for up to three dots per kernel.
 struct RedShared {
-    long long acc[3][ACC_DIGITS];   // workgroup long accumulators
+    long long acc[3][ACC_DIGITS]; // long accumulators
     long long red_ll[MAX_WAVES];
     double part[MAX_WAVES * MAX_FPE];
     int rng[2];
-    int flags;
     int esc;
-    int last;
-    int need_fb;
-    double result[3];
+    int pad;
+    double val[3];
 };
 
 __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags)
@@ -59,11 +59,20 @@ __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags
 }
 
 // Per-lane accumulator of one dot product.
+//
+// EXBLAS (Section 4.1, Listing 1): the TwoProd result and error go into one
+// expansion; what an expansion cannot hold is flushed into the workgroup's
+// long accumulator, so nothing is lost.
+// FPE (Section 4.2): two expansions, results and errors. A nonzero remainder
+// after the last level is an "escape" (the capacity warning of Section 4.3);
+// it is counted and, with `capture`, added to the long accumulator so the
+// result stays exact; without `capture` it is dropped as in the paper.
+// PLAIN: an fma running sum.
 template <int MODE, int P>
 struct LaneDot {
-    double a[P]; // EXBLAS: the lane's expansion; FPE: expansion of the TwoProd results
-    double e[P]; // FPE: expansion of the TwoProd errors (Section 4.2: two expansions)
-    double s;    // PLAIN: running fma sum
+    double a[P];
+    double e[P];
+    double s;
     int esc;
     int flags;
 
@@ -76,7 +85,7 @@ struct LaneDot {
         flags = 0;
     }
 
-    __device__ __forceinline__ void add(double x, double y, long long *acc, bool ee)
+    __device__ __forceinline__ void add(double x, double y, long long *acc, bool ee, bool capture)
     {
         if constexpr (MODE == MODE_PLAIN) {
             s = __builtin_fma(x, y, s);
@@ -85,15 +94,15 @@ struct LaneDot {
             two_prod(x, y, r, t);
             if (__builtin_fabs(r) < 0x1p-969 && x != 0.0 && y != 0.0) flags |= FLAG_INEXACT;
             if constexpr (MODE == MODE_EXBLAS) {
-                // Listing 1: both halves go into the same expansion; what
-                // does not fit is flushed into the long accumulator.
                 double left = fpe_accumulate<P>(a, r, ee);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
                 left = fpe_accumulate<P>(a, t, ee);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
             } else {
-                esc += fpe_accumulate<P>(a, r, ee) != 0.0;
-                esc += fpe_accumulate<P>(e, t, ee) != 0.0;
+                double left = fpe_accumulate<P>(a, r, ee);
+                if (left != 0.0) { ++esc; if (capture) acc_add_lds(acc, left, flags); }
+                left = fpe_accumulate<P>(e, t, ee);
+                if (left != 0.0) { ++esc; if (capture) acc_add_lds(acc, left, flags); }
             }
         }
     }
@@ -104,9 +113,24 @@ __device__ __forceinline__ void zero_acc(long long *acc)
     for (int k = threadIdx.x; k < ACC_DIGITS; k += blockDim.x) acc[k] = 0;
 }
 
+// fpesum (Alg. 3) of b into a; each remainder is counted and, with capture,
+// kept exactly in the long accumulator.
+template <int P>
+__device__ __forceinline__ int fpe_sum_capture(double (&a)[P], const double (&b)[P], bool ee, bool capture,
+                                               long long *acc, int &flags)
+{
+    int esc = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        double left = fpe_accumulate<P>(a, b[i], ee);
+        if (left != 0.0) { ++esc; if (capture) acc_add_lds(acc, left, flags); }
+    }
+    return esc;
+}
+
 // Merge the expansions of one wavefront into lane 0 (fixed tree order).
 template <int P>
-__device__ __forceinline__ int wave_fpe_merge(double (&a)[P], bool ee)
+__device__ __forceinline__ int wave_fpe_merge(double (&a)[P], bool ee, bool capture, long long *acc, int &flags)
 {
     int esc = 0;
 #pragma unroll
@@ -114,36 +138,8 @@ __device__ __forceinline__ int wave_fpe_merge(double (&a)[P], bool ee)
         double b[P];
 #pragma unroll
         for (int i = 0; i < P; ++i) b[i] = __shfl_down(a[i], off, 64);
-        if (lane_id() < off) esc += fpe_sum<P>(a, b, ee);
+        if (lane_id() < off) esc += fpe_sum_capture<P>(a, b, ee, capture, acc, flags);
     }
-    return esc;
-}
-
-// Merge the expansions of all wavefronts of the workgroup into thread 0's `a`.
-// Every thread must call; returns (in thread 0) the escapes of all merges.
-template <int P>
-__device__ int block_fpe_merge(double (&a)[P], bool ee, RedShared &sh);
-
-__device__ inline int block_sum_i(int v, RedShared &sh);
-
-template <int P>
-__device__ int block_fpe_merge(double (&a)[P], bool ee, RedShared &sh)
-{
-    int esc = block_sum_i(wave_fpe_merge<P>(a, ee), sh); // escapes of every lane, in thread 0
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int i = 0; i < P; ++i) sh.part[wave_id() * MAX_FPE + i] = a[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < num_waves(); ++w) {
-            double b[P];
-#pragma unroll
-            for (int i = 0; i < P; ++i) b[i] = sh.part[w * MAX_FPE + i];
-            esc += fpe_sum<P>(a, b, ee);
-        }
-    }
-    __syncthreads();
     return esc;
 }
 
@@ -160,6 +156,7 @@ __device__ inline double block_sum_d(double v, RedShared &sh)
     return t;
 }
 
+// Workgroup sum of an integer into thread 0.
 __device__ inline long long block_sum_ll(long long v, RedShared &sh)
 {
     v = wave_sum_down(v);
@@ -172,162 +169,287 @@ __device__ inline long long block_sum_ll(long long v, RedShared &sh)
     return t;
 }
 
-__device__ inline int block_sum_i(int v, RedShared &sh)
+// Merge the expansions of all wavefronts of the workgroup into thread 0's
+// `a` (pairwise tree over the wavefronts). Every thread must call. Returns
+// the escapes of all merges (valid in thread 0).
+template <int P>
+__device__ int block_fpe_merge(double (&a)[P], bool ee, bool capture, long long *acc, int &flags,
+                               RedShared &sh)
 {
-    return (int)block_sum_ll((long long)v, sh);
+    long long esc = wave_fpe_merge<P>(a, ee, capture, acc, flags);
+    esc = block_sum_ll(esc, sh);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) sh.part[wave_id() * MAX_FPE + i] = a[i];
+    }
+    if (threadIdx.x == 0) sh.esc = 0;
+    __syncthreads();
+    const int W = num_waves();
+    for (int step = 1; step < W; step <<= 1) {
+        const int w = wave_id();
+        if (lane_id() == 0 && (w % (2 * step)) == 0 && w + step < W) {
+            double x[P], y[P];
+#pragma unroll
+            for (int i = 0; i < P; ++i) { x[i] = sh.part[w * MAX_FPE + i]; y[i] = sh.part[(w + step) * MAX_FPE + i]; }
+            int e2 = fpe_sum_capture<P>(x, y, ee, capture, acc, flags);
+            if (e2) atomicAdd(&sh.esc, e2);
+#pragma unroll
+            for (int i = 0; i < P; ++i) sh.part[w * MAX_FPE + i] = x[i];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) a[i] = sh.part[i];
+        esc += sh.esc;
+    }
+    __syncthreads();
+    return (int)esc;
 }
 
-// Workgroup partial of one dot into slot g of `ws`. All threads call.
+// ---------------------------------------------------------------------------
+// Slots: one workgroup partial per producing workgroup. Long-accumulator
+// words are stored word-major (word k of slot g at digits[k * stride + g]) so
+// that the merge reads each word of all slots as one coalesced run.
+
+struct SlotView {
+    DotWs ws;
+    int stride; // slot capacity (words of one index are `stride` apart)
+};
+
+// Write the workgroup partial of one dot into slot g. All threads call.
 template <int MODE, int P>
-__device__ void block_finish(LaneDot<MODE, P> &L, long long *acc, const DotWs &ws, int g, bool ee,
-                             int *gflags, RedShared &sh)
+__device__ void block_finish(LaneDot<MODE, P> &L, long long *acc, const SlotView &sv, int g, bool ee,
+                             bool capture, int *gflags, RedShared &sh)
 {
-    if constexpr (MODE == MODE_EXBLAS) {
+    if constexpr (MODE == MODE_PLAIN) {
+        double t = block_sum_d(L.s, sh);
+        if (threadIdx.x == 0) sv.ws.part[g] = t;
+        return;
+    } else {
+        if constexpr (MODE == MODE_EXBLAS) {
+            // merge the lane expansions of the wavefront first (what does not
+            // fit goes into the accumulator), then one lane flushes the rest:
+            // far fewer same-address LDS atomics than a flush from every lane
+            wave_fpe_merge<P>(L.a, ee, true, acc, L.flags);
+            if (lane_id() == 0) {
 #pragma unroll
-        for (int i = 0; i < P; ++i)
-            if (L.a[i] != 0.0) acc_add_lds(acc, L.a[i], L.flags);
+                for (int i = 0; i < P; ++i)
+                    if (L.a[i] != 0.0) acc_add_lds(acc, L.a[i], L.flags);
+            }
+        } else {
+            L.esc += fpe_sum_capture<P>(L.a, L.e, ee, capture, acc, L.flags);
+            int esc = block_fpe_merge<P>(L.a, ee, capture, acc, L.flags, sh);
+            long long esc_lanes = block_sum_ll(L.esc, sh);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) sv.ws.part[(long long)g * MAX_FPE + i] = L.a[i];
+                sv.ws.esc[g] = (int)(esc + esc_lanes);
+            }
+        }
         if (threadIdx.x == 0) { sh.rng[0] = ACC_DIGITS; sh.rng[1] = -1; }
         __syncthreads();
         // one carry step keeps every word below 2^33 in magnitude, so the
-        // integer sum over slots cannot overflow
+        // integer sum over the slots cannot overflow
         for (int k = threadIdx.x; k < ACC_DIGITS; k += blockDim.x) {
             long long v = acc[k];
             long long cin = k ? (acc[k - 1] >> 32) : 0;
             long long o = (k == ACC_DIGITS - 1) ? v + cin : (v & 0xFFFFFFFFll) + cin;
-            ws.digits[(long long)g * ACC_DIGITS + k] = o;
+            sv.ws.digits[(long long)k * sv.stride + g] = o;
             if (o != 0) { atomicMin(&sh.rng[0], k); atomicMax(&sh.rng[1], k); }
         }
         __syncthreads();
-        if (threadIdx.x == 0) { ws.range[2 * g] = sh.rng[0]; ws.range[2 * g + 1] = sh.rng[1]; }
-    } else if constexpr (MODE == MODE_FPE) {
-        L.esc += fpe_sum<P>(L.a, L.e, ee);
-        int esc = block_sum_i(L.esc, sh);
-        esc += block_fpe_merge<P>(L.a, ee, sh);
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int i = 0; i < P; ++i) ws.part[(long long)g * MAX_FPE + i] = L.a[i];
-            ws.esc[g] = esc;
-        }
-    } else {
-        double t = block_sum_d(L.s, sh);
-        if (threadIdx.x == 0) ws.part[g] = t;
+        if (threadIdx.x == 0) { sv.ws.range[2 * g] = sh.rng[0]; sv.ws.range[2 * g + 1] = sh.rng[1]; }
+        if (L.flags) atomicOr(gflags, L.flags);
     }
-    if (L.flags) atomicOr(gflags, L.flags);
 }
 
-// Called by every thread after its slot writes; true in the last workgroup.
-__device__ inline bool arrive_last(unsigned *ticket, RedShared &sh)
+// ---------------------------------------------------------------------------
+// Correct rounding of a long accumulator by one full wavefront.
+//
+// Lane l holds words 2l and 2l+1 (lanes past the top hold zeros). Carries
+// move up by shuffles until every word below the top is in [0, 2^32); the
+// sign is the top word's; the leading word, the 53 bits below the leading
+// one and the rounding/sticky information are read with uniform lane
+// indices. Same result as acc_round() in numerics.hpp.
+
+constexpr int TOP_LANE = (ACC_DIGITS - 1) / 2; // lane holding the top word (as its odd word)
+static_assert(ACC_DIGITS % 2 == 0, "two words per lane");
+
+__device__ __forceinline__ void wave_normalize(long long &a, long long &b)
 {
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        sh.last = (prev == gridDim.x - 1);
+    const int l = lane_id();
+    for (int it = 0; it < 2 * ACC_DIGITS; ++it) {
+        long long ca = a >> 32;
+        a &= 0xFFFFFFFFll;
+        b += ca;
+        long long cb = 0;
+        if (l != TOP_LANE) { cb = b >> 32; b &= 0xFFFFFFFFll; }
+        long long cin = __shfl_up(cb, 1, 64);
+        if (l == 0) cin = 0;
+        a += cin;
+        if (__ballot((a >> 32) != 0) == 0) break;
     }
-    __syncthreads();
-    bool last = sh.last != 0;
-    if (last) {
-        __threadfence();
-        if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    return last;
 }
 
-// In the last workgroup: combine the G slots of one dot, round once.
-// Result valid in thread 0; *esc_out gets the total escapes (FPE).
+__device__ __forceinline__ long long wave_word(long long a, long long b, int k)
+{
+    if (k < 0 || k >= ACC_DIGITS) return 0;
+    long long v = __shfl((k & 1) ? b : a, k >> 1, 64);
+    return v;
+}
+
+__device__ inline double wave_acc_round(const long long *acc)
+{
+    const int l = lane_id();
+    long long a = (2 * l < ACC_DIGITS) ? acc[2 * l] : 0;
+    long long b = (2 * l + 1 < ACC_DIGITS) ? acc[2 * l + 1] : 0;
+    wave_normalize(a, b);
+    const bool neg = __shfl(b, TOP_LANE, 64) < 0;
+    if (neg) {
+        a = -a;
+        b = -b;
+        wave_normalize(a, b);
+    }
+    const unsigned long long mb = __ballot(b != 0), ma = __ballot(a != 0);
+    int h = -1;
+    if (mb) h = 2 * (63 - __builtin_clzll(mb)) + 1;
+    if (ma) h = max(h, 2 * (63 - __builtin_clzll(ma)));
+    if (h < 0) return 0.0;
+    const unsigned long long dh = (unsigned long long)wave_word(a, b, h);
+    const int msb = 63 - __builtin_clzll(dh);
+    const int B = 32 * h + msb;  // bit index of the leading one
+    const int E = B + ACC_EXP0;  // value in [2^E, 2^(E+1))
+    if (E >= 1024) return neg ? -__builtin_inf() : __builtin_inf();
+    int q = E - 52;
+    if (q < -1074) q = -1074;
+    const int Q = q - ACC_EXP0;  // bit index of the last kept bit, >= 14
+    const int kq = Q >> 5, sq = Q & 31;
+    const unsigned long long w0 = (unsigned)wave_word(a, b, kq);
+    const unsigned long long w1 = (unsigned)wave_word(a, b, kq + 1);
+    const unsigned long long w2 = (unsigned)wave_word(a, b, kq + 2);
+    const unsigned long long lo64 = w0 | (w1 << 32);
+    const unsigned long long r = (lo64 >> sq) | (sq ? (w2 << (64 - sq)) : 0ull);
+    const int len = B - Q + 1; // <= 53
+    unsigned long long I = r & ((1ull << len) - 1);
+    // rounding bit Q-1 and sticky bits below it
+    const int R = Q - 1, kr = R >> 5, sr = R & 31;
+    const unsigned long long wr = (unsigned)wave_word(a, b, kr);
+    const bool half = (wr >> sr) & 1ull;
+    bool sticky = (wr & ((1ull << sr) - 1)) != 0;
+    const bool low = ((2 * l < kr) && a != 0) || ((2 * l + 1 < kr) && b != 0);
+    sticky = sticky || (__ballot(low) != 0);
+    if (half && (sticky || (I & 1ull))) I += 1;
+    unsigned long long bits = ((unsigned long long)(q + 1074) << 52) + I;
+    if (neg) bits |= 1ull << 63;
+    return __builtin_bit_cast(double, bits);
+}
+
+// ---------------------------------------------------------------------------
+// Merge of the G slots of one dot, in every workgroup alike. All threads of
+// the workgroup call; the result is returned to every thread. `acc` is an
+// LDS accumulator the merge may overwrite. *esc_out (thread 0) receives the
+// escapes (FPE); flags seen on the way are or-ed into *flags_out.
+
+// Sum of row[0..G) by one wavefront (result in lane 0); eight independent
+// loads per lane are in flight at a time.
+__device__ __forceinline__ long long sum_row(const long long *row, int G)
+{
+    long long s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int g = lane_id();
+    for (; g + 7 * 64 < G; g += 8 * 64) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += row[g + 64 * j];
+    }
+    for (; g < G; g += 64) s[0] += row[g];
+    long long t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+    return wave_sum_down(t);
+}
+
 template <int MODE, int P>
-__device__ double merge_slots(const DotWs &ws, int G, bool ee, long long *acc, int *gflags,
-                              long long *esc_out, RedShared &sh)
+__device__ double merge_slots(const SlotView &sv, int G, bool ee, bool capture, long long *acc,
+                              long long *esc_out, int *flags_out, RedShared &sh, int slot_val)
 {
     *esc_out = 0;
-    if constexpr (MODE == MODE_EXBLAS) {
-        int kmin = ACC_DIGITS, kmax = -1;
-        for (int g = threadIdx.x; g < G; g += blockDim.x) {
-            kmin = min(kmin, ws.range[2 * g]);
-            kmax = max(kmax, ws.range[2 * g + 1]);
-        }
-        if (threadIdx.x == 0) { sh.rng[0] = ACC_DIGITS; sh.rng[1] = -1; }
-        zero_acc(acc);
-        __syncthreads();
-        atomicMin(&sh.rng[0], kmin);
-        atomicMax(&sh.rng[1], kmax);
-        __syncthreads();
-        int K0 = sh.rng[0], K1 = sh.rng[1];
-        for (int k = K0; k <= K1; ++k) {
-            long long s = 0;
-            for (int g = threadIdx.x; g < G; g += blockDim.x) s += ws.digits[(long long)g * ACC_DIGITS + k];
-            s = block_sum_ll(s, sh);
-            if (threadIdx.x == 0) acc[k] = s;
-        }
-        __syncthreads();
-        double r = 0.0;
-        if (threadIdx.x == 0) {
-            int f = __hip_atomic_load(gflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            r = (f & FLAG_NONFINITE) ? __builtin_nan("") : acc_round(acc);
-        }
-        __syncthreads();
-        return r;
-    } else if constexpr (MODE == MODE_FPE) {
-        double a[P];
+    double r;
+    if constexpr (MODE == MODE_PLAIN) {
+        // fixed order: wavefront 0 sums the slots lane-strided, then the tree
+        if (wave_id() == 0) {
+            double s[4] = {0.0, 0.0, 0.0, 0.0};
+            int g = lane_id();
+            for (; g + 3 * 64 < G; g += 4 * 64) {
 #pragma unroll
-        for (int i = 0; i < P; ++i) a[i] = 0.0;
-        int esc = 0;
-        long long esc_slots = 0;
-        for (int g = threadIdx.x; g < G; g += blockDim.x) {
-            double b[P];
-#pragma unroll
-            for (int i = 0; i < P; ++i) b[i] = ws.part[(long long)g * MAX_FPE + i];
-            esc += fpe_sum<P>(a, b, ee);
-            esc_slots += ws.esc[g];
-        }
-        long long tot = block_sum_ll(esc_slots + esc, sh);
-        int e2 = block_fpe_merge<P>(a, ee, sh);
-        double r = 0.0;
-        if (threadIdx.x == 0) {
-            tot += e2;
-            *esc_out = tot;
-            for (int k = 0; k < ACC_DIGITS; ++k) acc[k] = 0;
-            bool fin = true;
-#pragma unroll
-            for (int i = 0; i < P; ++i) { fin = fin && is_finite_bits(a[i]); }
-            int f = __hip_atomic_load(gflags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (!fin || (f & FLAG_NONFINITE)) r = __builtin_nan("");
-            else {
-#pragma unroll
-                for (int i = 0; i < P; ++i) acc_add(acc, a[i]); // NearSum: RN of the exact sum
-                r = acc_round(acc);
+                for (int j = 0; j < 4; ++j) s[j] += sv.ws.part[g + 64 * j];
             }
+            for (; g < G; g += 64) s[0] += sv.ws.part[g];
+            double t = wave_sum_down((s[0] + s[1]) + (s[2] + s[3]));
+            if (lane_id() == 0) sh.val[slot_val] = t;
         }
+        __syncthreads();
+        r = sh.val[slot_val];
         __syncthreads();
         return r;
     } else {
-        double s = 0.0;
-        for (int g = threadIdx.x; g < G; g += blockDim.x) s += ws.part[g];
-        return block_sum_d(s, sh);
+        int flags = 0;
+        zero_acc(acc);
+        if (threadIdx.x == 0) { sh.rng[0] = ACC_DIGITS; sh.rng[1] = -1; }
+        __syncthreads();
+        // FPE: merge the workgroup expansions (pairwise tree from the slots up)
+        double a[P > 0 ? P : 1];
+        if constexpr (MODE == MODE_FPE) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) a[i] = 0.0;
+            long long esc_slots = 0;
+            for (int g = threadIdx.x; g < G; g += blockDim.x) {
+                double b[P];
+#pragma unroll
+                for (int i = 0; i < P; ++i) b[i] = sv.ws.part[(long long)g * MAX_FPE + i];
+                int e = fpe_sum_capture<P>(a, b, ee, capture, acc, flags);
+                esc_slots += e + sv.ws.esc[g];
+            }
+            long long esc_tot = block_sum_ll(esc_slots, sh);
+            int e2 = block_fpe_merge<P>(a, ee, capture, acc, flags, sh);
+            if (threadIdx.x == 0) *esc_out = esc_tot + e2;
+        }
+        // long-accumulator words: global nonzero range, then one word per wavefront
+        int kmin = ACC_DIGITS, kmax = -1;
+        for (int g = threadIdx.x; g < G; g += blockDim.x) {
+            kmin = min(kmin, sv.ws.range[2 * g]);
+            kmax = max(kmax, sv.ws.range[2 * g + 1]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            kmin = min(kmin, __shfl_down(kmin, off, 64));
+            kmax = max(kmax, __shfl_down(kmax, off, 64));
+        }
+        if (lane_id() == 0) { atomicMin(&sh.rng[0], kmin); atomicMax(&sh.rng[1], kmax); }
+        __syncthreads();
+        const int K0 = sh.rng[0], K1 = sh.rng[1];
+        for (int k = K0 + wave_id(); k <= K1; k += num_waves()) {
+            long long s = sum_row(sv.ws.digits + (long long)k * sv.stride, G);
+            if (lane_id() == 0) atomicAdd((unsigned long long *)&acc[k], (unsigned long long)s);
+        }
+        __syncthreads();
+        if constexpr (MODE == MODE_FPE) {
+            // NearSum (Section 4.3): the rounded exact value of the final
+            // expansion plus whatever was captured
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int i = 0; i < P; ++i) acc_add_lds(acc, a[i], flags);
+            }
+            __syncthreads();
+        }
+        if (flags) atomicOr(flags_out, flags);
+        if (wave_id() == 0) {
+            double v = wave_acc_round(acc);
+            if (lane_id() == 0) sh.val[slot_val] = v;
+        }
+        __syncthreads();
+        r = sh.val[slot_val];
+        __syncthreads();
+        return r;
     }
 }
-
-// Exact dot computed by the calling workgroup alone (FPE fallback path).
-// All threads call; result in thread 0.
-__device__ inline double block_exact_dot(long long n, const double *x, const double *y, long long *acc,
-                                  int *gflags, RedShared &sh)
-{
-    zero_acc(acc);
-    __syncthreads();
-    LaneDot<MODE_EXBLAS, 4> L;
-    L.init();
-    for (long long i = threadIdx.x; i < n; i += blockDim.x) L.add(x[i], y[i], acc, true);
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        if (L.a[i] != 0.0) acc_add_lds(acc, L.a[i], L.flags);
-    if (L.flags) atomicOr(gflags, L.flags);
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = acc_round(acc);
-    __syncthreads();
-    return r;
-}
-
 
 template <int V>
 using IC = std::integral_constant<int, V>;

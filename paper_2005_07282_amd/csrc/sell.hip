@@ -25,7 +25,7 @@ __global__ void k_csr_check(int n, int nnz, const int *__restrict__ rp, const in
     }
 }
 
-__global__ void k_sell_widths(int n, const int *__restrict__ rp, long long *off_plus1, int nslices)
+__global__ void k_sell_widths(int n, const int *__restrict__ rp, long long *off_plus1, int nslices, int *max_len)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslices) return;
@@ -33,6 +33,7 @@ __global__ void k_sell_widths(int n, const int *__restrict__ rp, long long *off_
     int i0 = s * 64, i1 = min(n, i0 + 64);
     for (int i = i0; i < i1; ++i) w = max(w, rp[i + 1] - rp[i]);
     off_plus1[s] = 64ll * w;
+    atomicMax(max_len, w);
 }
 
 // In-place inclusive prefix sum of off[1..nslices] with off[0] = 0, one workgroup of 1024.
@@ -57,20 +58,26 @@ __global__ void __launch_bounds__(1024) k_sell_scan(long long *off, int nslices)
     if (t == 0) off[0] = 0;
 }
 
-__global__ void k_sell_fill(int n, const int *__restrict__ rp, const int *__restrict__ col,
+// One thread per (slice, lane) position, including the lanes past the last
+// row of the last slice: every stored position gets a valid column, so the
+// SpMV can load and gather a whole slice width without bounds branches.
+__global__ void k_sell_fill(int n, int nslices, const int *__restrict__ rp, const int *__restrict__ col,
                             const double *__restrict__ val, const long long *__restrict__ off,
-                            double *__restrict__ sval, int *__restrict__ scol)
+                            double *__restrict__ sval, int *__restrict__ scol, unsigned char *__restrict__ len8)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= 64ll * nslices) return;
     long long s = i >> 6, j = i & 63;
     long long base = off[s] + j;
     int width = (int)((off[s + 1] - off[s]) >> 6);
-    int r0 = rp[i], len = rp[i + 1] - r0;
+    bool row = i < n;
+    int r0 = row ? rp[i] : 0, len = row ? rp[i + 1] - r0 : 0;
+    int pad_col = row ? (int)i : 0;
+    if (len8 && row) len8[i] = (unsigned char)len;
     for (int k = 0; k < width; ++k) {
         bool in = k < len;
         sval[base + 64ll * k] = in ? val[r0 + k] : 0.0;
-        scol[base + 64ll * k] = in ? col[r0 + k] : (int)i;
+        scol[base + 64ll * k] = in ? col[r0 + k] : pad_col;
     }
 }
 
@@ -86,11 +93,12 @@ hipError_t launch_csr_check(int n, int nnz, const int *row_ptr, const int *col, 
     return hipGetLastError();
 }
 
-hipError_t launch_sell_widths(int n, const int *row_ptr, long long *off_plus1, int nslices, hipStream_t s)
+hipError_t launch_sell_widths(int n, const int *row_ptr, long long *off_plus1, int nslices, int *max_len,
+                              hipStream_t s)
 {
     if (nslices == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sell_widths, dim3((nslices + 255) / 256), dim3(256), 0, s, n, row_ptr,
-                       off_plus1, nslices);
+                       off_plus1, nslices, max_len);
     return hipGetLastError();
 }
 
@@ -101,11 +109,12 @@ hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s)
 }
 
 hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
-                            const long long *off, double *sval, int *scol, hipStream_t s)
+                            const long long *off, double *sval, int *scol, unsigned char *len8, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sell_fill, dim3((n + 255) / 256), dim3(256), 0, s, n, row_ptr, col, val,
-                       off, sval, scol);
+    const int nslices = (n + 63) / 64;
+    hipLaunchKernelGGL(k_sell_fill, dim3(nslices / 4 + 1), dim3(256), 0, s, n, nslices, row_ptr, col, val,
+                       off, sval, scol, len8);
     return hipGetLastError();
 }
 

@@ -41,7 +41,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("fpe_size", ctypes.c_int32),
                 ("early_exit", ctypes.c_int32), ("fpe_fallback", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("tau_history", ctypes.c_void_p)]
+                ("timing", ctypes.c_int32), ("xcd_parts", ctypes.c_int32), ("spmv_block_size", ctypes.c_int32),
+                ("spmv_grid_size", ctypes.c_int32), ("tau_history", ctypes.c_void_p)]
 
 
 class _Result(ctypes.Structure):

@@ -58,7 +58,7 @@ def test_struct_layout_matches_header():
     """Field order and sizes of the ctypes mirrors agree with the C structs."""
     from paper_2005_07282_amd import rpcg
     assert ctypes.sizeof(rpcg._Csr) == 32
-    assert ctypes.sizeof(rpcg._Opts) == 48
+    assert ctypes.sizeof(rpcg._Opts) == 56
     assert rpcg._Result.iterations.offset == 4 and rpcg._Result.tau0.offset == 8
 
 
