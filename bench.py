@@ -34,6 +34,34 @@ def k1_bytes(n, nnz):
     return 12 * nnz + 4 * (n + 1) + 16 * n
 
 
+K1_SOURCES = ("pcg_spmv_dot.hip", "reduce.hpp", "numerics.hpp", "kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_160cube_hbm_traffic.md")
+
+
+def k1_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in K1_SOURCES:
+        with open(os.path.join(ROOT, "paper_2005_07282_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def k1_traffic():
+    """HBM bytes per SpMV+dot launch from the committed counter summary, or None
+    if it is missing or was taken on different kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    for line in text.splitlines():
+        if line.startswith("k_pcg_spmv_dot source_hash="):
+            kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+            if kv.get("source_hash") == k1_source_hash():
+                return int(kv["traffic_bytes"])
+    return None
+
+
 def iteration_bytes(n, nnz):
     """Algorithmic bytes of one fused PCG iteration (three kernels)."""
     return k1_bytes(n, nnz) + 64 * n + 24 * n
@@ -49,6 +77,9 @@ def main():
     ap.add_argument("--exdot-reps", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="short run for hardware counters: a few exblas iterations on the N^3 operator "
+                         "and a 1 GiB device-to-device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); "
@@ -81,6 +112,16 @@ def main():
     bd = torch.from_numpy(b).to(dev)
     log(f"[bench] n={n} nnz={nnz} ({time.time() - t:.1f}s)")
 
+    if args.profile_pass:
+        src = torch.zeros(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        x, info = rpcg.pcg_solve(Ad, bd, mode="exblas", maxit=5, tol=1e-8, history=False)
+        torch.cuda.synchronize()
+        log(f"[bench] profile pass: copy of {src.numel() * 8} bytes, {info['iterations']} exblas iterations")
+        return
+
     def solve(mode, maxit, timing=0):
         torch.cuda.synchronize()
         x, info = rpcg.pcg_solve(Ad, bd, mode=mode, maxit=maxit, tol=1e-8, timing=timing, history=False)
@@ -92,7 +133,8 @@ def main():
         log(f"[bench] PCG {mode}: warmup {args.warmup} iterations")
         solve(mode, max(1, args.warmup))
         log(f"[bench] PCG {mode}: timing {args.steps} iterations")
-        x, info = solve(mode, args.steps, timing=1 if mode == "exblas" else 0)
+        # every mode is timed with the same per-kernel HIP events
+        x, info = solve(mode, args.steps, timing=1)
         if info["iterations"] != args.steps:
             log(f"[bench] note: {mode} stopped after {info['iterations']} iterations")
         res[mode] = info
@@ -170,6 +212,7 @@ def main():
                          f"{os.cpu_count()} host cores visible"}
         log(f"[bench]   oracle {cpu['value']} it/s")
 
+    traffic = k1_traffic() if N == 160 else None
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -204,7 +247,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(k1_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "k_pcg_spmv_dot<exblas,4>",
             "bytes_per_launch": k1_bytes(n, nnz),
         },

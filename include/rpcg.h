@@ -79,7 +79,8 @@ typedef struct {
 typedef struct {
     double tol;            /* stop when <r,r> <= RN(RN(tol*tol) * <b,b>) (Fig. 1 tau_max; default 1e-8, Section 5.1) */
     int32_t maxit;         /* default 2000 */
-    int32_t fpe_size;      /* expansion length p, 1..8 (Section 4.2: tunable); default 4 */
+    int32_t fpe_size;      /* expansion length p, 1..8 (Section 4.2: tunable); 0 = auto (default):
+                              4 in FPE mode, 3 in EXBLAS mode (whose result does not depend on it) */
     int32_t early_exit;    /* stop propagating zero errors (Section 4.2); default 1 */
     int32_t fpe_fallback;  /* FPE mode: what an expansion cannot hold (an escape, the
                               capacity warning of Section 4.3) is kept exactly in a long
@@ -94,6 +95,8 @@ typedef struct {
                               XCD (0 = auto = 1, no split). Results do not depend on it. */
     int32_t spmv_block_size; /* solver SpMV kernel: threads per workgroup (0 = auto) */
     int32_t spmv_grid_size;  /* solver SpMV kernel: workgroups (0 = auto) */
+    int32_t no_col16;        /* 1: keep 32-bit column indices in the solver's matrix copy even
+                                when every |column - row| fits 16 bits (default 0) */
     double *tau_history;   /* optional DEVICE array of maxit+1 doubles: tau^(0..L) */
 } rpcg_opts;
 

@@ -93,7 +93,7 @@ static int ensure_ws(rpcg_ctx *c, int groups)
 static bool valid_opts(const rpcg_opts &o)
 {
     if (!(o.tol >= 0.0) || o.maxit < 0) return false;
-    if (o.fpe_size < 1 || o.fpe_size > MAX_FPE) return false;
+    if (o.fpe_size < 0 || o.fpe_size > MAX_FPE) return false;
     if (o.block_size != 0 && (o.block_size < 64 || o.block_size > MAX_BLOCK || o.block_size % 64)) return false;
     if (o.grid_size < 0 || o.grid_size > 65536) return false;
     if (o.xcd_parts < 0 || o.xcd_parts > 64) return false;
@@ -119,6 +119,14 @@ static LaunchCfg make_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long work_
     return cfg;
 }
 
+// Expansion length: 0 = auto. FPE mode: 4. EXBLAS mode: 3 (its results do
+// not depend on the length; 3 was the fastest on the 27-point workload).
+static int resolve_fpe_size(int p, int mode)
+{
+    if (p) return p;
+    return mode == MODE_EXBLAS ? 3 : 4;
+}
+
 // Vector kernels (setup, K2, K3): 512-thread workgroups, at most two per CU,
 // so that the slot merges in the next kernel's prologue stay short.
 static LaunchCfg make_vec_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long n, hipStream_t s)
@@ -135,7 +143,7 @@ static LaunchCfg make_spmv_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long 
     q.block_size = o.spmv_block_size;
     q.grid_size = o.spmv_grid_size;
     LaunchCfg cfg = make_cfg(c, q, std::max(1ll, nslices * 64), 256, s);
-    if (!q.grid_size) cfg.grid = (int)std::max(1ll, std::min((nslices * 64 + cfg.block - 1) / cfg.block, 4ll * c->num_cus));
+    if (!q.grid_size) cfg.grid = (int)std::max(1ll, std::min((nslices * 64 + cfg.block - 1) / cfg.block, 2ll * c->num_cus));
     return cfg;
 }
 
@@ -147,7 +155,7 @@ void rpcg_opts_default(rpcg_opts *o)
     std::memset(o, 0, sizeof(*o));
     o->tol = 1e-8;
     o->maxit = 2000;
-    o->fpe_size = 4;
+    o->fpe_size = 0;
     o->early_exit = 1;
     o->fpe_fallback = 1;
 }
@@ -235,6 +243,7 @@ static int run_exdot(rpcg_ctx *c, int mode, int64_t n, const double *x, const do
     rpcg_opts_default(&o);
     if (opts) o = *opts;
     if (!valid_opts(o)) return RPCG_ERR_INVALID;
+    o.fpe_size = resolve_fpe_size(o.fpe_size, mode);
     RPCG_TRY(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     LaunchCfg cfg = make_cfg(c, o, std::max<int64_t>(1, (n + 7) / 8), 256, s);
@@ -319,6 +328,7 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     rpcg_opts_default(&o);
     if (opts) o = *opts;
     if (!valid_opts(o)) return RPCG_ERR_INVALID;
+    o.fpe_size = resolve_fpe_size(o.fpe_size, mode);
     RPCG_TRY(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const int n = A->n;
@@ -342,22 +352,26 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     long long *off = (long long *)c->sell_off.p;
     RPCG_TRY(hipMemsetAsync(off, 0, sizeof(long long) * (nslices + 1), s));
     int *max_len = &c->info->max_len; // zeroed with the info record above
-    RPCG_TRY(launch_sell_widths(n, A->row_ptr, off + 1, nslices, max_len, s));
+    int *max_delta = &c->info->max_delta;
+    RPCG_TRY(launch_sell_widths(n, A->row_ptr, A->col_idx, off + 1, nslices, max_len, max_delta, s));
     RPCG_TRY(launch_sell_scan(off, nslices, s));
     long long padded = 0;
-    int max_len_h = 0;
+    int max_len_h = 0, max_delta_h = 0;
     RPCG_TRY(hipMemcpyAsync(&padded, off + nslices, sizeof padded, hipMemcpyDeviceToHost, s));
     RPCG_TRY(hipMemcpyAsync(&max_len_h, max_len, sizeof max_len_h, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipMemcpyAsync(&max_delta_h, max_delta, sizeof max_delta_h, hipMemcpyDeviceToHost, s));
     RPCG_TRY(hipStreamSynchronize(s));
+    const bool col16 = max_delta_h <= 32767 && !o.no_col16;
     RPCG_TRY(c->sell_val.ensure(sizeof(double) * std::max(1ll, padded)));
-    RPCG_TRY(c->sell_col.ensure(sizeof(int) * std::max(1ll, padded)));
+    RPCG_TRY(c->sell_col.ensure((col16 ? sizeof(short) : sizeof(int)) * std::max(1ll, padded)));
     unsigned char *len8 = nullptr;
     if (max_len_h < 256) {
         RPCG_TRY(c->sell_len.ensure((size_t)std::max(1, n)));
         len8 = (unsigned char *)c->sell_len.p;
     }
     RPCG_TRY(launch_sell_fill(n, A->row_ptr, A->col_idx, A->val, off, (double *)c->sell_val.p,
-                              (int *)c->sell_col.p, len8, s));
+                              col16 ? nullptr : (int *)c->sell_col.p, col16 ? (short *)c->sell_col.p : nullptr,
+                              len8, s));
     RPCG_TRY(c->vecs.ensure(sizeof(double) * 5 * (size_t)std::max(1, n)));
     double *vb = (double *)c->vecs.p;
     PcgVecs v;
@@ -376,7 +390,8 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     M.nslices = nslices;
     M.off = off;
     M.val = (const double *)c->sell_val.p;
-    M.col = (const int *)c->sell_col.p;
+    M.col = col16 ? nullptr : (const int *)c->sell_col.p;
+    M.col16 = col16 ? (const short *)c->sell_col.p : nullptr;
     M.row_ptr = A->row_ptr;
     M.len8 = len8;
 

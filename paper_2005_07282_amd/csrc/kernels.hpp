@@ -35,7 +35,7 @@ struct DotInfo {
     unsigned pad0;
     int flags;
     int max_len;   // longest row (SELL construction scratch)
-    int pad;
+    int max_delta; // largest |column - row| (SELL construction scratch)
     long long escapes;
     long long fallbacks;
 };
@@ -75,6 +75,7 @@ struct SellMat {
     const int *col;
     const int *row_ptr;   // the caller's CSR row pointers (row lengths)
     const unsigned char *len8; // row lengths as bytes when every row has < 256 entries, else null
+    const short *col16;   // when non-null: columns as col - min(row, n-1) in 16 bits (col unused)
 };
 
 struct LaunchCfg {
@@ -102,11 +103,11 @@ hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const doub
 hipError_t launch_csr_check(int n, int nnz, const int *row_ptr, const int *col, int *bad, hipStream_t s);
 
 // SELL construction: width of each slice, offsets (prefix sums), fill.
-hipError_t launch_sell_widths(int n, const int *row_ptr, long long *off_plus1, int nslices,
-                              int *max_len, hipStream_t s);
+hipError_t launch_sell_widths(int n, const int *row_ptr, const int *col, long long *off_plus1, int nslices,
+                              int *max_len, int *max_delta, hipStream_t s);
 hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
 hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
-                            const long long *off, double *sval, int *scol, unsigned char *len8,
+                            const long long *off, double *sval, int *scol, short *scol16, unsigned char *len8,
                             hipStream_t s);
 
 struct PcgVecs {

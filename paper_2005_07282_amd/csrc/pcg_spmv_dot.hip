@@ -22,7 +22,16 @@ __device__ __forceinline__ long long uniform_ll(long long v)
 // `xcd_parts` contiguous ranges and workgroup b works in range b % xcd_parts
 // (workgroups are dispatched round-robin over the XCDs), so the rows whose d
 // entries an XCD gathers stay together in that XCD's L2.
-template <int MODE, int P>
+// Column of entry k (index kk into the slice arrays): 32-bit absolute, or
+// 16-bit offset from min(row, n-1).
+template <bool COL16>
+__device__ __forceinline__ int sell_col(const SellMat &A, long long kk, int rbase)
+{
+    if constexpr (COL16) return rbase + (int)A.col16[kk];
+    else return A.col[kk];
+}
+
+template <int MODE, int P, bool COL16>
 __global__ void __launch_bounds__(MAX_BLOCK)
 k_pcg_spmv_dot(SellMat A, PcgVecs v, PcgState *st, SlotView sv, bool ee, bool capture, int xcd_parts)
 {
@@ -51,20 +60,21 @@ k_pcg_spmv_dot(SellMat A, PcgVecs v, PcgState *st, SlotView sv, bool ee, bool ca
         const int width = __builtin_amdgcn_readfirstlane((int)((A.off[s + 1] - base) >> 6));
         const long long i = s * 64 + lane;
         const bool row = i < A.n;
+        const int rbase = row ? (int)i : A.n - 1;
         const int len = !row ? 0 : (A.len8 ? (int)A.len8[i] : A.row_ptr[i + 1] - A.row_ptr[i]);
-        const double *__restrict__ pv = A.val + base + lane;
-        const int *__restrict__ pc = A.col + base + lane;
+        const long long kb = base + lane;
+        const double *__restrict__ pv = A.val + kb;
         double sum = 0.0;
         // every position up to the slice width holds a valid column (padding
-        // entries and the lanes past the last row point at column 0 / the row
-        // itself), so loads and gathers of a full batch need no branch; the
+        // entries and the lanes past the last row point at a row of the
+        // matrix), so loads and gathers of a full batch need no branch; the
         // fma applies only to the row's own entries, in storage order
         int k0 = 0;
         for (; k0 + SPMV_BATCH <= width; k0 += SPMV_BATCH) {
             int c[SPMV_BATCH];
             double a[SPMV_BATCH], g[SPMV_BATCH];
 #pragma unroll
-            for (int u = 0; u < SPMV_BATCH; ++u) c[u] = pc[64 * (k0 + u)];
+            for (int u = 0; u < SPMV_BATCH; ++u) c[u] = sell_col<COL16>(A, kb + 64 * (k0 + u), rbase);
 #pragma unroll
             for (int u = 0; u < SPMV_BATCH; ++u) a[u] = pv[64 * (k0 + u)];
 #pragma unroll
@@ -76,7 +86,7 @@ k_pcg_spmv_dot(SellMat A, PcgVecs v, PcgState *st, SlotView sv, bool ee, bool ca
             }
         }
         for (; k0 < width; ++k0) {
-            const double t = __builtin_fma(pv[64 * k0], d[pc[64 * k0]], sum);
+            const double t = __builtin_fma(pv[64 * k0], d[sell_col<COL16>(A, kb + 64 * k0, rbase)], sum);
             sum = (k0 < len) ? t : sum;
         }
         if (row) {
@@ -94,7 +104,10 @@ hipError_t launch_pcg_spmv_dot(int mode, const SellMat &A, const PcgVecs &v, Pcg
     SlotView sv{ws, stride};
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
         constexpr int M = decltype(m)::value, PP = decltype(p)::value;
-        k_pcg_spmv_dot<M, PP><<<c.grid, c.block, 0, c.stream>>>(A, v, st, sv, c.early_exit, c.fallback, parts);
+        if (A.col16)
+            k_pcg_spmv_dot<M, PP, true><<<c.grid, c.block, 0, c.stream>>>(A, v, st, sv, c.early_exit, c.fallback, parts);
+        else
+            k_pcg_spmv_dot<M, PP, false><<<c.grid, c.block, 0, c.stream>>>(A, v, st, sv, c.early_exit, c.fallback, parts);
     });
     return hipGetLastError();
 }

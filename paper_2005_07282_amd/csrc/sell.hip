@@ -25,15 +25,22 @@ __global__ void k_csr_check(int n, int nnz, const int *__restrict__ rp, const in
     }
 }
 
-__global__ void k_sell_widths(int n, const int *__restrict__ rp, long long *off_plus1, int nslices, int *max_len)
+// Width of each slice (longest row), the longest row overall and the largest
+// |column - row| (decides whether 16-bit column offsets suffice).
+__global__ void k_sell_widths(int n, const int *__restrict__ rp, const int *__restrict__ col, long long *off_plus1,
+                              int nslices, int *max_len, int *max_delta)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nslices) return;
-    int w = 0;
+    int w = 0, dm = 0;
     int i0 = s * 64, i1 = min(n, i0 + 64);
-    for (int i = i0; i < i1; ++i) w = max(w, rp[i + 1] - rp[i]);
+    for (int i = i0; i < i1; ++i) {
+        w = max(w, rp[i + 1] - rp[i]);
+        for (int k = rp[i]; k < rp[i + 1]; ++k) dm = max(dm, abs(col[k] - i));
+    }
     off_plus1[s] = 64ll * w;
     atomicMax(max_len, w);
+    atomicMax(max_delta, dm);
 }
 
 // In-place inclusive prefix sum of off[1..nslices] with off[0] = 0, one workgroup of 1024.
@@ -63,7 +70,8 @@ __global__ void __launch_bounds__(1024) k_sell_scan(long long *off, int nslices)
 // SpMV can load and gather a whole slice width without bounds branches.
 __global__ void k_sell_fill(int n, int nslices, const int *__restrict__ rp, const int *__restrict__ col,
                             const double *__restrict__ val, const long long *__restrict__ off,
-                            double *__restrict__ sval, int *__restrict__ scol, unsigned char *__restrict__ len8)
+                            double *__restrict__ sval, int *__restrict__ scol, short *__restrict__ scol16,
+                            unsigned char *__restrict__ len8)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= 64ll * nslices) return;
@@ -73,11 +81,13 @@ __global__ void k_sell_fill(int n, int nslices, const int *__restrict__ rp, cons
     bool row = i < n;
     int r0 = row ? rp[i] : 0, len = row ? rp[i + 1] - r0 : 0;
     int pad_col = row ? (int)i : 0;
+    int rbase = row ? (int)i : n - 1; // 16-bit offsets are relative to min(row, n-1)
     if (len8 && row) len8[i] = (unsigned char)len;
     for (int k = 0; k < width; ++k) {
         bool in = k < len;
         sval[base + 64ll * k] = in ? val[r0 + k] : 0.0;
-        scol[base + 64ll * k] = in ? col[r0 + k] : pad_col;
+        if (scol16) scol16[base + 64ll * k] = in ? (short)(col[r0 + k] - rbase) : (short)0;
+        else scol[base + 64ll * k] = in ? col[r0 + k] : pad_col;
     }
 }
 
@@ -93,12 +103,12 @@ hipError_t launch_csr_check(int n, int nnz, const int *row_ptr, const int *col, 
     return hipGetLastError();
 }
 
-hipError_t launch_sell_widths(int n, const int *row_ptr, long long *off_plus1, int nslices, int *max_len,
-                              hipStream_t s)
+hipError_t launch_sell_widths(int n, const int *row_ptr, const int *col, long long *off_plus1, int nslices,
+                              int *max_len, int *max_delta, hipStream_t s)
 {
     if (nslices == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sell_widths, dim3((nslices + 255) / 256), dim3(256), 0, s, n, row_ptr,
-                       off_plus1, nslices, max_len);
+    hipLaunchKernelGGL(k_sell_widths, dim3((nslices + 255) / 256), dim3(256), 0, s, n, row_ptr, col,
+                       off_plus1, nslices, max_len, max_delta);
     return hipGetLastError();
 }
 
@@ -109,12 +119,13 @@ hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s)
 }
 
 hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
-                            const long long *off, double *sval, int *scol, unsigned char *len8, hipStream_t s)
+                            const long long *off, double *sval, int *scol, short *scol16, unsigned char *len8,
+                            hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int nslices = (n + 63) / 64;
     hipLaunchKernelGGL(k_sell_fill, dim3(nslices / 4 + 1), dim3(256), 0, s, n, nslices, row_ptr, col, val,
-                       off, sval, scol, len8);
+                       off, sval, scol, scol16, len8);
     return hipGetLastError();
 }
 

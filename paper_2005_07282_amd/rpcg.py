@@ -42,7 +42,7 @@ class _Opts(ctypes.Structure):
                 ("early_exit", ctypes.c_int32), ("fpe_fallback", ctypes.c_int32),
                 ("block_size", ctypes.c_int32), ("grid_size", ctypes.c_int32),
                 ("timing", ctypes.c_int32), ("xcd_parts", ctypes.c_int32), ("spmv_block_size", ctypes.c_int32),
-                ("spmv_grid_size", ctypes.c_int32), ("tau_history", ctypes.c_void_p)]
+                ("spmv_grid_size", ctypes.c_int32), ("no_col16", ctypes.c_int32), ("tau_history", ctypes.c_void_p)]
 
 
 class _Result(ctypes.Structure):

@@ -67,15 +67,18 @@ def test_w1_bitexact(R, w1, mode):
 
 
 LAUNCH = [(64, 1), (64, 37), (128, 256), (256, 0), (512, 13), (1024, 64), (256, 2048)]
+SPMV_LAUNCH = [(256, 0), (64, 3), (1024, 7), (128, 999), (512, 64), (256, 1), (64, 4096)]
 
 
 @pytest.mark.parametrize("mode", ["exblas", "fpe"])
 def test_w1_launch_config_invariance(R, w1, mode):
     A, b, xs, ref = w1
-    for block, grid in LAUNCH:
+    for (block, grid), (sb, sg) in zip(LAUNCH, SPMV_LAUNCH):
         for p in ((3, 4, 8) if mode == "fpe" else (1, 4)):
-            print(f"pcg 32^3 {mode} block={block} grid={grid} p={p}", flush=True)
-            x, info = _solve(R, A, b, mode, block_size=block, grid_size=grid, fpe_size=p)
+            narrow = (block + grid + p) % 2
+            print(f"pcg 32^3 {mode} block={block} grid={grid} spmv={sb}x{sg} p={p} no_col16={narrow}", flush=True)
+            x, info = _solve(R, A, b, mode, block_size=block, grid_size=grid, fpe_size=p,
+                             spmv_block_size=sb, spmv_grid_size=sg, no_col16=narrow)
             assert info["iterations"] == ref["iters"], (block, grid, p)
             assert _eq(info["hist"].numpy(), ref["hist"]), (block, grid, p)
             assert _eq(x, ref["x"]), (block, grid, p)
@@ -133,6 +136,31 @@ def test_other_systems_bitexact(R, orc, case):
         assert info["iterations"] == ref["iters"], (case, mode)
         assert _eq(info["hist"].numpy(), ref["hist"])
         assert _eq(x.cpu().numpy(), ref["x"])
+
+
+def test_permuted_matrix_wide_columns(R, orc):
+    """A symmetric permutation P A P^T of the 27-point operator (still SPD) moves
+    entries far from the diagonal (|col - row| > 32767), so the solver keeps
+    32-bit column indices; results still match the oracle bit for bit."""
+    A0 = stencil27_csr(35)
+    n = A0.n
+    perm = np.random.default_rng(3).permutation(n)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    rows = np.repeat(np.arange(n), np.diff(A0.row_ptr))
+    nr, nc = inv[rows], inv[A0.col_idx]
+    order = np.lexsort((nc, nr))
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, nr + 1, 1)
+    A = CSRHost(n, np.cumsum(rp).astype(np.int32), nc[order].astype(np.int32), A0.val[order])
+    assert np.max(np.abs(A.col_idx.astype(np.int64) - np.repeat(np.arange(n), np.diff(A.row_ptr)))) > 32767
+    b = uniform_pm1(8, n)
+    ref = orc.pcg(A, b, tol=1e-8)
+    for mode in ("exblas", "fpe"):
+        x, info = _solve(R, A, b, mode)
+        assert info["iterations"] == ref["iters"]
+        assert _eq(info["hist"].numpy(), ref["hist"])
+        assert _eq(x, ref["x"])
 
 
 def test_status_cases(R, orc):

@@ -47,7 +47,7 @@ def test_opts_default_and_status_strings(L):
     from paper_2005_07282_amd import rpcg
     o = rpcg._Opts()
     L.rpcg_opts_default(ctypes.byref(o))
-    assert o.tol == 1e-8 and o.maxit == 2000 and o.fpe_size == 4
+    assert o.tol == 1e-8 and o.maxit == 2000 and o.fpe_size == 0
     assert o.early_exit == 1 and o.fpe_fallback == 1 and o.tau_history is None
     for s in (0, 1, 2, -1, -2, -3, -4, -5, -6):
         assert rpcg.status_string(s) != "unknown status"
@@ -58,7 +58,7 @@ def test_struct_layout_matches_header():
     """Field order and sizes of the ctypes mirrors agree with the C structs."""
     from paper_2005_07282_amd import rpcg
     assert ctypes.sizeof(rpcg._Csr) == 32
-    assert ctypes.sizeof(rpcg._Opts) == 56
+    assert ctypes.sizeof(rpcg._Opts) == 64
     assert rpcg._Result.iterations.offset == 4 and rpcg._Result.tau0.offset == 8
 
 
