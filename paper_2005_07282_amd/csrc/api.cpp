@@ -340,27 +340,24 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s);
     int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
     if (rc != RPCG_OK) return rc;
-    // the matrix is checked before anything indexes through it
-    int *bad = &c->info->flags;
+    // one pass over the CSR checks its structure and measures the slices;
+    // nothing indexes through the matrix before the check has passed
     RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
-    RPCG_TRY(launch_csr_check(n, A->nnz, A->row_ptr, A->col_idx, bad, s));
-    int bad_h = 0;
-    RPCG_TRY(hipMemcpyAsync(&bad_h, bad, sizeof bad_h, hipMemcpyDeviceToHost, s));
-    RPCG_TRY(hipStreamSynchronize(s));
-    if (bad_h) return RPCG_ERR_INVALID;
     RPCG_TRY(c->sell_off.ensure(sizeof(long long) * (nslices + 1)));
     long long *off = (long long *)c->sell_off.p;
     RPCG_TRY(hipMemsetAsync(off, 0, sizeof(long long) * (nslices + 1), s));
-    int *max_len = &c->info->max_len; // zeroed with the info record above
+    int *bad = &c->info->flags;
+    int *max_len = &c->info->max_len;
     int *max_delta = &c->info->max_delta;
-    RPCG_TRY(launch_sell_widths(n, A->row_ptr, A->col_idx, off + 1, nslices, max_len, max_delta, s));
+    RPCG_TRY(launch_csr_scan(n, A->nnz, A->row_ptr, A->col_idx, off + 1, bad, max_len, max_delta, s));
     RPCG_TRY(launch_sell_scan(off, nslices, s));
     long long padded = 0;
-    int max_len_h = 0, max_delta_h = 0;
+    DotInfo scan_info;
     RPCG_TRY(hipMemcpyAsync(&padded, off + nslices, sizeof padded, hipMemcpyDeviceToHost, s));
-    RPCG_TRY(hipMemcpyAsync(&max_len_h, max_len, sizeof max_len_h, hipMemcpyDeviceToHost, s));
-    RPCG_TRY(hipMemcpyAsync(&max_delta_h, max_delta, sizeof max_delta_h, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipMemcpyAsync(&scan_info, c->info, sizeof scan_info, hipMemcpyDeviceToHost, s));
     RPCG_TRY(hipStreamSynchronize(s));
+    if (scan_info.flags) return RPCG_ERR_INVALID;
+    const int max_len_h = scan_info.max_len, max_delta_h = scan_info.max_delta;
     const bool col16 = max_delta_h <= 32767 && !o.no_col16;
     RPCG_TRY(c->sell_val.ensure(sizeof(double) * std::max(1ll, padded)));
     RPCG_TRY(c->sell_col.ensure((col16 ? sizeof(short) : sizeof(int)) * std::max(1ll, padded)));
@@ -396,7 +393,7 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     M.len8 = len8;
 
     const int stride = c->ws_groups;
-    RPCG_TRY(launch_pcg_setup(mode, M, A->col_idx, A->val, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_rows));
+    RPCG_TRY(launch_pcg_setup(mode, M, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_sl));
     RPCG_TRY(hipStreamSynchronize(s));
     auto t1 = clk::now();
 

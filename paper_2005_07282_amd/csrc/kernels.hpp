@@ -99,12 +99,11 @@ hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s)
 hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
                            const double *x, double *y, hipStream_t s);
 
-// Structural check of a caller's CSR (sets *bad to nonzero if malformed).
-hipError_t launch_csr_check(int n, int nnz, const int *row_ptr, const int *col, int *bad, hipStream_t s);
+// CSR structural check (*bad set if malformed), slice widths (off_plus1),
+// longest row and largest |column - row|, one wavefront per 64-row slice.
+hipError_t launch_csr_scan(int n, int nnz, const int *row_ptr, const int *col, long long *off_plus1, int *bad,
+                           int *max_len, int *max_delta, hipStream_t s);
 
-// SELL construction: width of each slice, offsets (prefix sums), fill.
-hipError_t launch_sell_widths(int n, const int *row_ptr, const int *col, long long *off_plus1, int nslices,
-                              int *max_len, int *max_delta, hipStream_t s);
 hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
 hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
                             const long long *off, double *sval, int *scol, short *scol16, unsigned char *len8,
@@ -118,9 +117,8 @@ struct PcgVecs {
 };
 
 // Setup (state init, partials, one-workgroup finalize) into ws3[0..2].
-hipError_t launch_pcg_setup(int mode, const SellMat &A, const int *col, const double *val,
-                            const PcgVecs &v, PcgState *st, const DotWs *ws3, int stride, double tol,
-                            int maxit, const LaunchCfg &cfg);
+hipError_t launch_pcg_setup(int mode, const SellMat &A, const PcgVecs &v, PcgState *st, const DotWs *ws3,
+                            int stride, double tol, int maxit, const LaunchCfg &cfg);
 // Iteration l: K1 writes its partials to `ws`; K2 merges them (Gd slots) and
 // writes two dots into ws2[0..1]; K3 merges those (G slots).
 hipError_t launch_pcg_spmv_dot(int mode, const SellMat &A, const PcgVecs &v, PcgState *st,

@@ -1,6 +1,7 @@
 // Jacobi-PCG setup kernels: preconditioner, initial residual and dots
 // (Fig. 1/Fig. 2 initialisation; Section 4.3 Jacobi: inverse diagonal once).
 #include "reduce.hpp"
+#include "sell_spmv.hpp"
 
 namespace rpcg {
 
@@ -13,12 +14,11 @@ __global__ void k_state_init(PcgState *st, int maxit)
 }
 
 // dinv = RN(1/a_ii), r = RN(b - A x0), z = RN(dinv r), d = z, and the
-// workgroup partials of <z,r>, <r,r>, <b,b>.
-template <int MODE, int P>
+// workgroup partials of <z,r>, <r,r>, <b,b>. One wavefront per 64-row slice
+// of the sliced-ELL copy, as in the iteration's SpMV.
+template <int MODE, int P, bool COL16>
 __global__ void __launch_bounds__(MAX_BLOCK)
-k_pcg_setup(int n, const int *__restrict__ rp, const int *__restrict__ col,
-            const double *__restrict__ val, PcgVecs v, PcgState *st, SlotView w0, SlotView w1, SlotView w2,
-            bool ee, bool capture)
+k_pcg_setup(SellMat A, PcgVecs v, PcgState *st, SlotView w0, SlotView w1, SlotView w2, bool ee, bool capture)
 {
     __shared__ RedShared sh;
     zero_acc(sh.acc[0]); zero_acc(sh.acc[1]); zero_acc(sh.acc[2]);
@@ -26,28 +26,32 @@ k_pcg_setup(int n, const int *__restrict__ rp, const int *__restrict__ col,
     LaneDot<MODE, P> Lb, Lt, Lbb;
     Lb.init(); Lt.init(); Lbb.init();
     int flags = 0;
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        double acc = 0.0, aii = 0.0;
+    const int lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(wave_id());
+    const long long wstride = (long long)gridDim.x * num_waves();
+    for (long long s = (long long)blockIdx.x * num_waves() + wave; s < A.nslices; s += wstride) {
+        const long long base = uniform_ll(A.off[s]);
+        const int width = __builtin_amdgcn_readfirstlane((int)((A.off[s + 1] - base) >> 6));
+        const long long i = s * 64 + lane;
+        const int len = sell_len(A, i);
+        double aii = 0.0;
         bool found = false;
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-            int c = col[k];
-            acc = __builtin_fma(val[k], v.x[c], acc);
-            if (c == i) { aii = val[k]; found = true; }
+        const double acc = sell_row<COL16, true>(A, base, width, i, len, v.x, &aii, &found);
+        if (i < A.n) {
+            if (!found || !(aii > 0.0)) flags |= FLAG_NOT_SPD;
+            const double bi = v.b[i];
+            if (!is_finite_bits(bi) || !is_finite_bits(v.x[i])) flags |= FLAG_NONFINITE;
+            const double di = 1.0 / aii;
+            const double ri = bi - acc;
+            const double zi = di * ri;
+            v.dinv[i] = di;
+            v.r[i] = ri;
+            v.z[i] = zi;
+            v.d[i] = zi;
+            Lb.add(zi, ri, sh.acc[0], ee, capture);
+            Lt.add(ri, ri, sh.acc[1], ee, capture);
+            Lbb.add(bi, bi, sh.acc[2], ee, capture);
         }
-        if (!found || !(aii > 0.0)) flags |= FLAG_NOT_SPD;
-        double bi = v.b[i];
-        if (!is_finite_bits(bi) || !is_finite_bits(v.x[i])) flags |= FLAG_NONFINITE;
-        double di = 1.0 / aii;
-        double ri = bi - acc;
-        double zi = di * ri;
-        v.dinv[i] = di;
-        v.r[i] = ri;
-        v.z[i] = zi;
-        v.d[i] = zi;
-        Lb.add(zi, ri, sh.acc[0], ee, capture);
-        Lt.add(ri, ri, sh.acc[1], ee, capture);
-        Lbb.add(bi, bi, sh.acc[2], ee, capture);
     }
     if (flags) atomicOr(&st->flags, flags);
     block_finish<MODE, P>(Lb, sh.acc[0], w0, blockIdx.x, ee, capture, &st->flags, sh);
@@ -85,9 +89,8 @@ k_pcg_fin_setup(int G, PcgVecs v, PcgState *st, SlotView w0, SlotView w1, SlotVi
     }
 }
 
-hipError_t launch_pcg_setup(int mode, const SellMat &A, const int *col, const double *val,
-                            const PcgVecs &v, PcgState *st, const DotWs *ws3, int stride, double tol, int maxit,
-                            const LaunchCfg &c)
+hipError_t launch_pcg_setup(int mode, const SellMat &A, const PcgVecs &v, PcgState *st, const DotWs *ws3,
+                            int stride, double tol, int maxit, const LaunchCfg &c)
 {
     SlotView s0{ws3[0], stride}, s1{ws3[1], stride}, s2{ws3[2], stride};
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, c.stream, st, maxit);
@@ -95,8 +98,10 @@ hipError_t launch_pcg_setup(int mode, const SellMat &A, const int *col, const do
     if (e != hipSuccess) return e;
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
         constexpr int M = decltype(m)::value, PP = decltype(p)::value;
-        k_pcg_setup<M, PP><<<c.grid, c.block, 0, c.stream>>>(A.n, A.row_ptr, col, val, v, st, s0, s1, s2,
-                                                             c.early_exit, c.fallback);
+        if (A.col16)
+            k_pcg_setup<M, PP, true><<<c.grid, c.block, 0, c.stream>>>(A, v, st, s0, s1, s2, c.early_exit, c.fallback);
+        else
+            k_pcg_setup<M, PP, false><<<c.grid, c.block, 0, c.stream>>>(A, v, st, s0, s1, s2, c.early_exit, c.fallback);
         k_pcg_fin_setup<M, PP><<<1, MAX_BLOCK, 0, c.stream>>>(c.grid, v, st, s0, s1, s2, tol, c.early_exit,
                                                               c.fallback);
     });

@@ -1,46 +1,81 @@
 // Conversion of the caller's CSR matrix into the sliced-ELL layout used by
 // the solver's SpMV (rows and their entry order unchanged).
+//
+// Both passes give one wavefront to each slice of 64 rows: lane j owns row
+// 64s+j, and the lanes stride together through the slice's contiguous CSR
+// range, so every global read is coalesced. The row of entry e is found by a
+// binary search over the slice's row starts, which sit one per lane.
 #include "kernels.hpp"
 
 namespace rpcg {
 
-// ---------------------------------------------------------------------------
-// SELL-64 construction
+__device__ __forceinline__ int lane_of() { return threadIdx.x & 63; }
 
-// Structural check of a CSR matrix: row_ptr[0] = 0, row_ptr[n] = nnz,
-// non-decreasing, and every column index in [0, n). Sets *bad on failure.
-// Every read stays inside row_ptr[0..n] and col[0..nnz).
-__global__ void k_csr_check(int n, int nnz, const int *__restrict__ rp, const int *__restrict__ col, int *bad)
+// Row (0..63 within the slice) of CSR entry e: the last of the first
+// `nrows` lanes whose row start is <= e (row starts are non-decreasing and
+// lane 0's start is <= e). Binary lifting with a fixed six steps, so every
+// lane takes part in every shuffle.
+__device__ __forceinline__ int slice_row_of(int start, long long e, int nrows)
 {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        int a = rp[i], b = rp[i + 1];
-        bool ok = a >= 0 && a <= b && b <= nnz;
-        if (i == 0 && a != 0) ok = false;
-        if (i == n - 1 && b != nnz) ok = false;
-        if (ok)
-            for (int k = a; k < b; ++k)
-                if (col[k] < 0 || col[k] >= n) { ok = false; break; }
-        if (!ok) atomicOr(bad, 1);
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int cand = lo + step;
+        const int sc = __shfl(start, min(cand, nrows - 1), 64);
+        if (cand < nrows && sc <= e) lo = cand;
     }
+    return lo;
 }
 
-// Width of each slice (longest row), the longest row overall and the largest
-// |column - row| (decides whether 16-bit column offsets suffice).
-__global__ void k_sell_widths(int n, const int *__restrict__ rp, const int *__restrict__ col, long long *off_plus1,
-                              int nslices, int *max_len, int *max_delta)
+// Pass 1 (one wavefront per slice): structural check of the CSR (row_ptr[0] =
+// 0, row_ptr[n] = nnz, non-decreasing, columns in [0, n)), slice widths,
+// the longest row and the largest |column - row|.
+__global__ void k_csr_scan(int n, int nnz, int nslices, const int *__restrict__ rp, const int *__restrict__ col,
+                           long long *off_plus1, int *bad, int *max_len, int *max_delta)
 {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslices) return;
-    int w = 0, dm = 0;
-    int i0 = s * 64, i1 = min(n, i0 + 64);
-    for (int i = i0; i < i1; ++i) {
-        w = max(w, rp[i + 1] - rp[i]);
-        for (int k = rp[i]; k < rp[i + 1]; ++k) dm = max(dm, abs(col[k] - i));
+    const int lane = lane_of();
+    const long long s = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (s >= nslices) return; // whole wavefronts leave together
+    const long long i = s * 64 + lane;
+    const bool row = i < n;
+    const int nrows = (int)min(64ll, (long long)n - s * 64);
+    int a = 0, b = 0;
+    if (row) { a = rp[i]; b = rp[i + 1]; }
+    bool ok = !row || (a >= 0 && a <= b && b <= nnz);
+    if (row && i == 0 && a != 0) ok = false;
+    if (row && i == n - 1 && b != nnz) ok = false;
+    const int len = row ? b - a : 0;
+    int w = len;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
+    const bool all_ok = __ballot(!ok) == 0;
+    if (lane == 0) {
+        off_plus1[s] = 64ll * w;
+        atomicMax(max_len, w);
     }
-    off_plus1[s] = 64ll * w;
-    atomicMax(max_len, w);
-    atomicMax(max_delta, dm);
+    if (!all_ok) {
+        if (lane == 0) atomicOr(bad, 1);
+        return;
+    }
+    // rows are consistent: the slice's entries are [start of row 0, end of the last row)
+    const int e0 = __shfl(a, 0, 64), e1 = __shfl(b, nrows - 1, 64);
+    int dmax = 0;
+    bool cok = true;
+    // uniform trip count: every lane takes part in the shuffles of the search
+    for (long long t = e0; t < e1; t += 64) {
+        const long long e = t + lane;
+        const bool in = e < e1;
+        const int r = slice_row_of(a, in ? e : t, nrows);
+        if (in) {
+            const int c = col[e];
+            if (c < 0 || c >= n) cok = false;
+            dmax = max(dmax, abs(c - (int)(s * 64 + r)));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dmax = max(dmax, __shfl_xor(dmax, off, 64));
+    if (__ballot(!cok) != 0 && lane == 0) atomicOr(bad, 1);
+    if (lane == 0) atomicMax(max_delta, dmax);
 }
 
 // In-place inclusive prefix sum of off[1..nslices] with off[0] = 0, one workgroup of 1024.
@@ -65,50 +100,61 @@ __global__ void __launch_bounds__(1024) k_sell_scan(long long *off, int nslices)
     if (t == 0) off[0] = 0;
 }
 
-// One thread per (slice, lane) position, including the lanes past the last
-// row of the last slice: every stored position gets a valid column, so the
-// SpMV can load and gather a whole slice width without bounds branches.
+// Pass 2 (one wavefront per slice): padding first (value 0, a valid column:
+// the row itself, or row n-1 for the lanes past the last row), then every
+// CSR entry e of the slice goes to position off[s] + 64 k + j, where j is its
+// row in the slice and k its rank in the row. Columns are stored as 32-bit
+// indices, or (scol16) as 16-bit offsets from min(row, n-1).
 __global__ void k_sell_fill(int n, int nslices, const int *__restrict__ rp, const int *__restrict__ col,
                             const double *__restrict__ val, const long long *__restrict__ off,
                             double *__restrict__ sval, int *__restrict__ scol, short *__restrict__ scol16,
                             unsigned char *__restrict__ len8)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 64ll * nslices) return;
-    long long s = i >> 6, j = i & 63;
-    long long base = off[s] + j;
-    int width = (int)((off[s + 1] - off[s]) >> 6);
-    bool row = i < n;
-    int r0 = row ? rp[i] : 0, len = row ? rp[i + 1] - r0 : 0;
-    int pad_col = row ? (int)i : 0;
-    int rbase = row ? (int)i : n - 1; // 16-bit offsets are relative to min(row, n-1)
+    const int lane = lane_of();
+    const long long s = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (s >= nslices) return;
+    const long long i = s * 64 + lane;
+    const bool row = i < n;
+    const int nrows = (int)min(64ll, (long long)n - s * 64);
+    const long long base = off[s];
+    const int width = (int)((off[s + 1] - base) >> 6);
+    const int a = row ? rp[i] : 0;
+    const int len = row ? rp[i + 1] - a : 0;
+    const int rbase = row ? (int)i : n - 1;
     if (len8 && row) len8[i] = (unsigned char)len;
-    for (int k = 0; k < width; ++k) {
-        bool in = k < len;
-        sval[base + 64ll * k] = in ? val[r0 + k] : 0.0;
-        if (scol16) scol16[base + 64ll * k] = in ? (short)(col[r0 + k] - rbase) : (short)0;
-        else scol[base + 64ll * k] = in ? col[r0 + k] : pad_col;
+    for (int k = len; k < width; ++k) {
+        const long long p = base + 64ll * k + lane;
+        sval[p] = 0.0;
+        if (scol16) scol16[p] = 0;
+        else scol[p] = rbase;
+    }
+    const int e0 = __shfl(a, 0, 64), e1 = __shfl(a + len, nrows - 1, 64);
+    for (long long t = e0; t < e1; t += 64) { // uniform trip count (shuffles below)
+        const long long e = t + lane;
+        const bool in = e < e1;
+        const int r = slice_row_of(a, in ? e : t, nrows);
+        const int ar = __shfl(a, r, 64);
+        if (in) {
+            const int k = (int)(e - ar);
+            const long long p = base + 64ll * k + r;
+            const int c = col[e];
+            sval[p] = val[e];
+            if (scol16) scol16[p] = (short)(c - (int)(s * 64 + r));
+            else scol[p] = c;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Launch functions
 
-hipError_t launch_csr_check(int n, int nnz, const int *row_ptr, const int *col, int *bad, hipStream_t s)
+hipError_t launch_csr_scan(int n, int nnz, const int *row_ptr, const int *col, long long *off_plus1, int *bad,
+                           int *max_len, int *max_delta, hipStream_t s)
 {
-    if (n == 0) return hipSuccess;
-    long long grid = ((long long)n + 255) / 256;
-    if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_csr_check, dim3((unsigned)grid), dim3(256), 0, s, n, nnz, row_ptr, col, bad);
-    return hipGetLastError();
-}
-
-hipError_t launch_sell_widths(int n, const int *row_ptr, const int *col, long long *off_plus1, int nslices,
-                              int *max_len, int *max_delta, hipStream_t s)
-{
+    const int nslices = (n + 63) / 64;
     if (nslices == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sell_widths, dim3((nslices + 255) / 256), dim3(256), 0, s, n, row_ptr, col,
-                       off_plus1, nslices, max_len, max_delta);
+    hipLaunchKernelGGL(k_csr_scan, dim3((nslices + 3) / 4), dim3(256), 0, s, n, nnz, nslices, row_ptr, col,
+                       off_plus1, bad, max_len, max_delta);
     return hipGetLastError();
 }
 
@@ -124,7 +170,7 @@ hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const dou
 {
     if (n == 0) return hipSuccess;
     const int nslices = (n + 63) / 64;
-    hipLaunchKernelGGL(k_sell_fill, dim3(nslices / 4 + 1), dim3(256), 0, s, n, nslices, row_ptr, col, val,
+    hipLaunchKernelGGL(k_sell_fill, dim3((nslices + 3) / 4), dim3(256), 0, s, n, nslices, row_ptr, col, val,
                        off, sval, scol, scol16, len8);
     return hipGetLastError();
 }
