@@ -54,6 +54,17 @@ def lib():
         L.rpcg_oracle_pcg.restype = ctypes.c_int
         L.rpcg_oracle_pcg.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                                       P, P, P, P, P]
+        L.rpcg_oracle_exdot_f32.restype = ctypes.c_float
+        L.rpcg_oracle_exdot_f32.argtypes = [ctypes.c_int64, P, P]
+        L.rpcg_oracle_spmv_f32.restype = None
+        L.rpcg_oracle_spmv_f32.argtypes = [ctypes.c_int32, P, P, P, P, P]
+        L.rpcg_oracle_pcg_f32.restype = ctypes.c_int
+        L.rpcg_oracle_pcg_f32.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, P, P]
+        L.rpcg_oracle_ir_scale.restype = ctypes.c_int
+        L.rpcg_oracle_ir_scale.argtypes = [ctypes.c_double]
+        L.rpcg_oracle_ir.restype = ctypes.c_int
+        L.rpcg_oracle_ir.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_int32, P, P, P]
         _lib = L
     return _lib
 
@@ -149,3 +160,56 @@ def pcg(A, b, x0=None, tol=1e-8, maxit=2000, trace=False):
         out["trace_d"] = td.reshape(maxit + 1, n)[:L + 1]
         out["trace_x"] = tx.reshape(maxit + 1, n)[:L + 1]
     return out
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def exdot_f32(x, y) -> np.float32:
+    """Exact dot product of binary32 vectors rounded once to binary32."""
+    x, y = _f32(x), _f32(y)
+    assert x.shape == y.shape
+    return np.float32(lib().rpcg_oracle_exdot_f32(x.size, _p(x), _p(y)))
+
+
+def spmv_f32(A, x):
+    """binary32 fmaf chains; A.val is taken as binary32 (exact for the stencils used)."""
+    x = _f32(x)
+    y = np.empty(A.n, dtype=np.float32)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f32(A.val)
+    lib().rpcg_oracle_spmv_f32(A.n, _p(rp), _p(ci), _p(va), _p(x), _p(y))
+    return y
+
+
+def pcg_f32(A, b, x0=None, tol=1e-4, maxit=2000):
+    """Jacobi-PCG entirely in binary32. Returns dict(x, iters, hist, status)."""
+    n = A.n
+    b = _f32(b)
+    x = np.zeros(n, dtype=np.float32) if x0 is None else _f32(x0).copy()
+    hist = np.zeros(maxit + 1, dtype=np.float64)
+    iters = ctypes.c_int32(0)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f32(A.val)
+    st = lib().rpcg_oracle_pcg_f32(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit),
+                                   _p(hist), ctypes.byref(iters))
+    L = iters.value
+    return dict(x=x, iters=L, hist=hist[:L + 1].copy(), status=st)
+
+
+def ir_scale(rr: float) -> int:
+    return lib().rpcg_oracle_ir_scale(float(rr))
+
+
+def ir(A, b, x0=None, tol=1e-10, maxit_out=50, tol_in=1e-4, maxit_in=2000):
+    """Mixed-precision refinement (binary32 inner PCG, binary64 outer loop).
+    Returns dict(x, outer, inner, hist (rr per outer step), status)."""
+    n = A.n
+    b = _f64(b)
+    x = np.zeros(n, dtype=np.float64) if x0 is None else _f64(x0).copy()
+    hist = np.zeros(maxit_out + 1, dtype=np.float64)
+    outer, inner = ctypes.c_int32(0), ctypes.c_int32(0)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f32(A.val)
+    st = lib().rpcg_oracle_ir(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit_out),
+                              float(tol_in), int(maxit_in), _p(hist), ctypes.byref(outer), ctypes.byref(inner))
+    k = outer.value
+    return dict(x=x, outer=k, inner=inner.value, hist=hist[:k + 1].copy(), status=st)

@@ -131,9 +131,13 @@ static int limbs_bit(const uint32_t *D, int k)
     return (D[k / 32] >> (k % 32)) & 1;
 }
 
-/* Round (-1)^neg * D * 2^-ORC_BIAS to the nearest double, ties to even.
- * Zero gives +0.0; magnitudes at or above 2^1024 - 2^970 give infinity. */
-static double round_magnitude(const uint32_t *D, int neg)
+/* Round (-1)^neg * D * 2^-ORC_BIAS to the nearest number with `prec`
+ * significant bits, exponents down to a last-bit weight of 2^qmin
+ * (subnormals) and overflow to infinity from 2^emax_inf - 2^(emax_inf-prec-1)
+ * on (IEEE 754 round to nearest, ties to even). binary64: prec 53, qmin
+ * -1074, emax_inf 1024. binary32: prec 24, qmin -149, emax_inf 128.
+ * Zero gives +0. The value is returned as a double (exact for binary32). */
+static double round_magnitude_fmt(const uint32_t *D, int neg, int prec, int qmin, int emax_inf)
 {
     int top = -1;
     for (int k = ORC_LIMBS - 1; k >= 0 && top < 0; --k)
@@ -141,10 +145,10 @@ static double round_magnitude(const uint32_t *D, int neg)
             if ((D[k] >> b) & 1) { top = 32 * k + b; break; }
     if (top < 0) return 0.0;
     int emsb = top - ORC_BIAS;               /* value in [2^emsb, 2^(emsb+1)) */
-    if (emsb >= 1024) return neg ? -INFINITY : INFINITY;
-    int q = emsb - 52;                       /* weight of the last kept bit */
-    if (q < -1074) q = -1074;                /* subnormal range */
-    int qb = q + ORC_BIAS;                   /* its bit index, >= 1074 */
+    if (emsb >= emax_inf) return neg ? -INFINITY : INFINITY;
+    int q = emsb - (prec - 1);               /* weight of the last kept bit */
+    if (q < qmin) q = qmin;                  /* subnormal range */
+    int qb = q + ORC_BIAS;                   /* its bit index */
     uint64_t I = 0;
     for (int k = top; k >= qb; --k) I = (I << 1) | (uint64_t)limbs_bit(D, k);
     int half = limbs_bit(D, qb - 1);
@@ -152,21 +156,32 @@ static double round_magnitude(const uint32_t *D, int neg)
     int sticky = 0, lim = qb - 1;            /* bits [0, lim) */
     for (int k = 0; k < lim / 32 && !sticky; ++k) sticky = D[k] != 0;
     if (!sticky && lim % 32) sticky = (D[lim / 32] & ((UINT32_C(1) << (lim % 32)) - 1)) != 0;
-    if (half && (sticky || (I & 1))) I += 1; /* I <= 2^53 */
-    double r = ldexp((double)I, q);          /* exact, or inf on overflow */
+    if (half && (sticky || (I & 1))) I += 1; /* I <= 2^prec */
+    double r = ldexp((double)I, q);          /* exact; 2^emax_inf when rounding up at the top */
+    if (r >= ldexp(1.0, emax_inf)) r = INFINITY;
     return neg ? -r : r;
 }
 
-static double acc_round(const orc_acc *a)
+static double round_magnitude(const uint32_t *D, int neg)
+{
+    return round_magnitude_fmt(D, neg, 53, -1074, 1024);
+}
+
+static double acc_round_fmt(const orc_acc *a, int prec, int qmin, int emax_inf)
 {
     if (a->nonfinite) return NAN;
     uint32_t D[ORC_LIMBS];
     int c = limbs_cmp(a->pos, a->neg);
     if (c == 0) return 0.0;
-    if (c > 0) { limbs_sub(D, a->pos, a->neg); return round_magnitude(D, 0); }
+    if (c > 0) { limbs_sub(D, a->pos, a->neg); return round_magnitude_fmt(D, 0, prec, qmin, emax_inf); }
     limbs_sub(D, a->neg, a->pos);
-    return round_magnitude(D, 1);
+    return round_magnitude_fmt(D, 1, prec, qmin, emax_inf);
 }
+
+static double acc_round(const orc_acc *a) { return acc_round_fmt(a, 53, -1074, 1024); }
+
+/* binary32 rounding of the exact value */
+static float acc_round_f32(const orc_acc *a) { return (float)acc_round_fmt(a, 24, -149, 128); }
 
 /* ---- exported API ------------------------------------------------------ */
 
@@ -331,5 +346,153 @@ int rpcg_oracle_pcg(int32_t n, const int32_t *row_ptr, const int32_t *col,
     if (status == ORC_OK && tau > thr) status = ORC_WARN_MAXIT;
 out:
     free(dinv); free(r); free(z); free(d); free(w);
+    return status;
+}
+
+/* ---- binary32 routines of the mixed-precision refinement ------------------
+ * The inner solver of the refinement runs entirely in binary32: SpMV by fmaf
+ * chains, exact dot products rounded once to binary32, fmaf updates, Jacobi
+ * with the binary32 inverse diagonal. The outer loop keeps x, b and the
+ * residual in binary64: residual rows accumulated exactly and rounded once,
+ * exact norms, and the correction added as x + (double)c (scaled by a power
+ * of two). */
+
+/* Correctly rounded (binary32) exact dot product of two binary32 vectors. */
+float rpcg_oracle_exdot_f32(int64_t n, const float *x, const float *y)
+{
+    orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
+    acc_clear(a);
+    for (int64_t i = 0; i < n; ++i) acc_add_product(a, (double)x[i], (double)y[i]);
+    float r = acc_round_f32(a);
+    free(a);
+    return r;
+}
+
+/* y = A x in binary32: acc = +0; acc = fmaf(val_k, x[col_k], acc) per row. */
+void rpcg_oracle_spmv_f32(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                          const float *val, const float *x, float *y)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        float acc = 0.0f;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            acc = fmaf(val[k], x[col[k]], acc);
+        y[i] = acc;
+    }
+}
+
+/* Jacobi-PCG in binary32, the loop of rpcg_oracle_pcg with every operation
+ * in binary32: thr = RN32(RN32(tol32*tol32) * <b,b>), tol32 = RN32(tol).
+ * hist (optional, maxit+1) receives tau^(0..L) widened to double. */
+int rpcg_oracle_pcg_f32(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                        const float *val, const float *b, float *x,
+                        double tol, int32_t maxit, double *hist, int32_t *iters)
+{
+    *iters = 0;
+    if (n < 0 || maxit < 0) return ORC_ERR_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    float *dinv = malloc(sizeof(float) * nn), *r = malloc(sizeof(float) * nn);
+    float *z = malloc(sizeof(float) * nn), *d = malloc(sizeof(float) * nn);
+    float *w = malloc(sizeof(float) * nn);
+    int status = ORC_OK;
+    for (int32_t i = 0; i < n && status == ORC_OK; ++i) {
+        float aii = 0.0f; int found = 0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) { aii = val[k]; found = 1; }
+        if (!found || !(aii > 0.0f)) status = ORC_ERR_NOT_SPD;
+        else dinv[i] = 1.0f / aii;
+    }
+    for (int32_t i = 0; i < n && status == ORC_OK; ++i)
+        if (!isfinite(b[i]) || !isfinite(x[i])) status = ORC_ERR_NONFINITE;
+    if (status != ORC_OK) goto out;
+    rpcg_oracle_spmv_f32(n, row_ptr, col, val, x, w);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
+    for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+    for (int32_t i = 0; i < n; ++i) d[i] = z[i];
+    float beta = rpcg_oracle_exdot_f32(n, z, r);
+    float tau = rpcg_oracle_exdot_f32(n, r, r);
+    float bb = rpcg_oracle_exdot_f32(n, b, b);
+    float tol32 = (float)tol;
+    float thr = (tol32 * tol32) * bb;
+    if (hist) hist[0] = tau;
+    if (!isfinite(tau) || !isfinite(bb)) { status = ORC_ERR_NONFINITE; goto out; }
+    int32_t l = 0;
+    while (tau > thr && l < maxit) {
+        float beta_old = beta;
+        rpcg_oracle_spmv_f32(n, row_ptr, col, val, d, w);
+        float delta = rpcg_oracle_exdot_f32(n, d, w);
+        if (!(delta > 0.0f)) { status = isfinite(delta) ? ORC_ERR_BREAKDOWN : ORC_ERR_NONFINITE; break; }
+        float rho = beta / delta;
+        for (int32_t i = 0; i < n; ++i) x[i] = fmaf(rho, d[i], x[i]);
+        for (int32_t i = 0; i < n; ++i) r[i] = fmaf(-rho, w[i], r[i]);
+        for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        beta = rpcg_oracle_exdot_f32(n, z, r);
+        tau = rpcg_oracle_exdot_f32(n, r, r);
+        float gamma = beta / beta_old;
+        for (int32_t i = 0; i < n; ++i) d[i] = fmaf(gamma, d[i], z[i]);
+        l += 1;
+        if (hist) hist[l] = tau;
+        if (!isfinite(tau)) { status = ORC_ERR_NONFINITE; break; }
+    }
+    *iters = l;
+    if (status == ORC_OK && tau > thr) status = ORC_WARN_MAXIT;
+out:
+    free(dinv); free(r); free(z); free(d); free(w);
+    return status;
+}
+
+/* Power-of-two scale of the residual for the binary32 inner solve: the
+ * inner right-hand side is RN32(r * 2^-s) with s = floor(E / 2), where
+ * <r,r> = m 2^E, m in [1, 2) (binary64 exponent of rr), so that the scaled
+ * residual has a norm near 1. */
+int rpcg_oracle_ir_scale(double rr)
+{
+    int E;
+    frexp(rr, &E);                /* rr = f 2^E, f in [0.5, 1) */
+    E -= 1;                       /* rr = m 2^E, m in [1, 2) */
+    return E >= 0 ? E / 2 : -((-E + 1) / 2);
+}
+
+/* Mixed-precision iterative refinement. A is given with binary32 values
+ * (val32); the outer residual widens them exactly to binary64.
+ *   x: in x0, out: final iterate (binary64)
+ *   outer loop k = 0, 1, ...: r = b - A x (rows exact, rounded once);
+ *     rr = <r,r> (exact); hist[k] = rr; stop if rr <= RN(RN(tol*tol) <b,b>)
+ *     or k = maxit_out; s = rpcg_oracle_ir_scale(rr);
+ *     c = PCG32(A32, RN32(r 2^-s), x0 = 0, tol_in, maxit_in);
+ *     x = RN(x + (double)c 2^s)
+ *   *outer: corrections applied; *inner: total inner iterations.
+ * Returns the outer status (OK, WARN_MAXIT) or the first inner error. */
+int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val32,
+                   const double *b, double *x, double tol, int32_t maxit_out, double tol_in,
+                   int32_t maxit_in, double *hist, int32_t *outer, int32_t *inner)
+{
+    *outer = 0; *inner = 0;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t nnz = n > 0 ? row_ptr[n] : 0;
+    double *val64 = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    double *r = malloc(sizeof(double) * nn);
+    float *rf = malloc(sizeof(float) * nn), *c = malloc(sizeof(float) * nn);
+    for (int32_t k = 0; k < nnz; ++k) val64[k] = (double)val32[k];
+    double bb = rpcg_oracle_exdot(n, b, b);
+    double thr = (tol * tol) * bb;
+    int status = ORC_OK;
+    for (int32_t k = 0;; ++k) {
+        rpcg_oracle_true_residual(n, row_ptr, col, val64, b, x, r);
+        double rr = rpcg_oracle_exdot(n, r, r);
+        if (hist) hist[k] = rr;
+        if (!isfinite(rr)) { status = ORC_ERR_NONFINITE; break; }
+        if (rr <= thr) break;
+        if (k == maxit_out) { status = ORC_WARN_MAXIT; break; }
+        int sc = rpcg_oracle_ir_scale(rr);
+        for (int32_t i = 0; i < n; ++i) rf[i] = (float)ldexp(r[i], -sc);
+        for (int32_t i = 0; i < n; ++i) c[i] = 0.0f;
+        int32_t it = 0;
+        int st = rpcg_oracle_pcg_f32(n, row_ptr, col, val32, rf, c, tol_in, maxit_in, NULL, &it);
+        *inner += it;
+        if (st < 0) { status = st; break; }
+        for (int32_t i = 0; i < n; ++i) x[i] = x[i] + ldexp((double)c[i], sc);
+        *outer = k + 1;
+    }
+    free(val64); free(r); free(rf); free(c);
     return status;
 }

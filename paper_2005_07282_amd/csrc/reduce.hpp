@@ -173,7 +173,7 @@ __device__ inline long long block_sum_ll(long long v, RedShared &sh)
 // `a` (pairwise tree over the wavefronts). Every thread must call. Returns
 // the escapes of all merges (valid in thread 0).
 template <int P>
-__device__ int block_fpe_merge(double (&a)[P], bool ee, bool capture, long long *acc, int &flags,
+__device__ __forceinline__ int block_fpe_merge(double (&a)[P], bool ee, bool capture, long long *acc, int &flags,
                                RedShared &sh)
 {
     long long esc = wave_fpe_merge<P>(a, ee, capture, acc, flags);
@@ -219,7 +219,7 @@ struct SlotView {
 
 // Write the workgroup partial of one dot into slot g. All threads call.
 template <int MODE, int P>
-__device__ void block_finish(LaneDot<MODE, P> &L, long long *acc, const SlotView &sv, int g, bool ee,
+__device__ __forceinline__ void block_finish(LaneDot<MODE, P> &L, long long *acc, const SlotView &sv, int g, bool ee,
                              bool capture, int *gflags, RedShared &sh)
 {
     if constexpr (MODE == MODE_PLAIN) {
@@ -367,7 +367,7 @@ __device__ __forceinline__ long long sum_row(const long long *row, int G)
 }
 
 template <int MODE, int P>
-__device__ double merge_slots(const SlotView &sv, int G, bool ee, bool capture, long long *acc,
+__device__ __forceinline__ double merge_slots(const SlotView &sv, int G, bool ee, bool capture, long long *acc,
                               long long *esc_out, int *flags_out, RedShared &sh, int slot_val)
 {
     *esc_out = 0;

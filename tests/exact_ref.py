@@ -49,3 +49,30 @@ def dot_fsum(x, y) -> float:
 
 def fma_exact(a: float, b: float, c: float) -> float:
     return rn(Fraction(a) * Fraction(b) + Fraction(c))
+
+
+def rn_fmt(v: Fraction, prec: int, qmin: int, emax_inf: int) -> float:
+    """Nearest value with `prec` significant bits, last-bit weight >= 2^qmin,
+    ties to even, overflow to infinity at 2^emax_inf (binary32: 24, -149, 128)."""
+    if v == 0:
+        return 0.0
+    neg = v < 0
+    a = -v if neg else v
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    q = max(e - (prec - 1), qmin)
+    scaled = a / (Fraction(2) ** q)
+    I = scaled.numerator // scaled.denominator
+    rem = scaled - I
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and I % 2 == 1):
+        I += 1
+    val = Fraction(I) * Fraction(2) ** q
+    if val >= Fraction(2) ** emax_inf:
+        return -math.inf if neg else math.inf
+    f = val.numerator / val.denominator
+    return -f if neg else f
+
+
+def rn32(v: Fraction) -> float:
+    return rn_fmt(v, 24, -149, 128)
