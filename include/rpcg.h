@@ -164,6 +164,85 @@ int rpcg_pcg_solve(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr *A /* host stru
                    const double *b, double *x, const rpcg_opts *opts, rpcg_result *res,
                    void *stream);
 
+/* ---- Binary32 solver and mixed-precision refinement ----
+ * Extensions of the paper's method (whose solver is binary64 throughout):
+ * the same Jacobi-PCG iteration with every value and every rounding in
+ * binary32, and an iterative-refinement loop that wraps it in binary64. The
+ * reproducible reductions carry over unchanged: the product of two binary32
+ * values is exact in binary64, so the exact dot of binary32 vectors is the
+ * exact sum of those products rounded once, directly to binary32. */
+
+/* CSR with binary32 values (same conventions as rpcg_csr). */
+typedef struct {
+    int32_t n;
+    int32_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const float *val;
+} rpcg_csr_f32;
+
+/* Jacobi-PCG (Fig. 1 / Fig. 2) entirely in binary32: dinv = RN32(1/a_ii),
+ * SpMV rows as binary32 fma chains, the updates as binary32 fma, dots exact
+ * and rounded once to binary32, rho, gamma and the stopping threshold
+ * RN32(RN32(t*t) <b,b>) with t = RN32(tol) in binary32. b, x: n floats
+ * (x: in x^(0), out: final iterate). tau_history (optional, device, maxit+1
+ * doubles) and the scalars of `res` hold the binary32 values widened.
+ * Options, statuses and waiting behaviour as rpcg_pcg_solve. */
+int rpcg_pcg_solve_f32(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr_f32 *A /* host struct */,
+                       const float *b, float *x, const rpcg_opts *opts, rpcg_result *res,
+                       void *stream);
+
+/* Options of the refinement. Fill with rpcg_ir_opts_default() first. */
+typedef struct {
+    double tol;            /* outer: stop when <r,r> <= RN(RN(tol*tol) <b,b>) with r = b - A x
+                              formed in binary64 (default 1e-10) */
+    int32_t maxit;         /* outer corrections at most (default 50) */
+    int32_t pad0;
+    double *rr_history;    /* optional DEVICE array of maxit+1 doubles: <r,r> of every outer step */
+    rpcg_opts inner;       /* the binary32 inner solves: tol (default 1e-4), maxit (default 2000),
+                              expansion and launch options; its tau_history must be NULL */
+} rpcg_ir_opts;
+
+/* Host-side result record of the refinement. */
+typedef struct {
+    int32_t status;            /* same value as the return code */
+    int32_t outer;             /* corrections applied */
+    int32_t inner_iterations;  /* summed over the inner solves */
+    int32_t last_inner_status; /* status of the last inner solve */
+    double rr0;                /* <r,r> at x^(0) */
+    double rr_final;           /* <r,r> at the returned x */
+    double threshold;          /* RN(RN(tol*tol) <b,b>) */
+    int64_t fpe_escapes;       /* summed over the inner solves (FPE mode) */
+    double setup_ms;           /* wall time: matrix copies and <b,b> */
+    double total_ms;           /* wall time of the whole call */
+    double inner_ms;           /* wall time of the inner solves (their setup included) */
+    double outer_ms;           /* wall time of the binary64 steps (residual, scaling, update) */
+    double k_residual_ms;      /* HIP-event time of the residual kernels (inner.timing = 1) */
+    double k_spmv_dot_ms;      /* inner.timing = 1: summed kernel times of the inner loops */
+    double k_update_ms;
+    double k_direction_ms;
+    int32_t k_launches;        /* inner.timing = 1: inner iterations whose kernels were timed */
+    int32_t pad1;
+} rpcg_ir_result;
+
+void rpcg_ir_opts_default(rpcg_ir_opts *opts /* host */);
+
+/* Mixed-precision iterative refinement for A x = b. A: binary64 CSR as for
+ * rpcg_pcg_solve; the inner solves use its values rounded to nearest
+ * binary32. b, x: n doubles (x: in x^(0), out: final iterate).
+ * Outer step k = 0, 1, ...: r = b - A x with every row summed exactly (a
+ * long accumulator, Section 2.1) and rounded once; rr = <r,r> exact and
+ * rounded once (Section 4.1); stop when rr <= RN(RN(tol*tol) <b,b>), or with
+ * RPCG_WARN_MAXIT when k = maxit. Otherwise s = floor(e / 2) where
+ * rr = m 2^e, 1 <= m < 2; the inner binary32 solve (rpcg_pcg_solve_f32
+ * semantics, `mode` selects its dot products) runs on rf = RN32(r 2^-s) from
+ * c = 0; x = RN(x + c 2^s). An inner solve that stops at its maxit is
+ * accepted; an inner error ends the call with that error. The outer dots are
+ * always exact (EXBLAS) whatever `mode` is. Waits for completion. */
+int rpcg_ir_solve(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr *A /* host struct */,
+                  const double *b, double *x, const rpcg_ir_opts *opts, rpcg_ir_result *res,
+                  void *stream);
+
 /* Long-accumulator interface (Section 4.3, Listing 3: the per-process
  * accumulator that is summed as integers across processes, then rounded).
  * The accumulator is RPCG_ACC_DIGITS signed 64-bit digits; digit k has weight

@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        if not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
             build()
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
@@ -201,14 +201,15 @@ def ir_scale(rr: float) -> int:
 
 
 def ir(A, b, x0=None, tol=1e-10, maxit_out=50, tol_in=1e-4, maxit_in=2000):
-    """Mixed-precision refinement (binary32 inner PCG, binary64 outer loop).
+    """Mixed-precision refinement (binary32 inner PCG on the values rounded to
+    binary32, binary64 outer loop on the values as given).
     Returns dict(x, outer, inner, hist (rr per outer step), status)."""
     n = A.n
     b = _f64(b)
     x = np.zeros(n, dtype=np.float64) if x0 is None else _f64(x0).copy()
     hist = np.zeros(maxit_out + 1, dtype=np.float64)
     outer, inner = ctypes.c_int32(0), ctypes.c_int32(0)
-    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f32(A.val)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val)
     st = lib().rpcg_oracle_ir(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit_out),
                               float(tol_in), int(maxit_in), _p(hist), ctypes.byref(outer), ctypes.byref(inner))
     k = outer.value

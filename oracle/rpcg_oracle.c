@@ -452,27 +452,28 @@ int rpcg_oracle_ir_scale(double rr)
     return E >= 0 ? E / 2 : -((-E + 1) / 2);
 }
 
-/* Mixed-precision iterative refinement. A is given with binary32 values
- * (val32); the outer residual widens them exactly to binary64.
+/* Mixed-precision iterative refinement. A is given with binary64 values
+ * (val); the inner solves use them rounded to nearest binary32, the outer
+ * residual uses them as given.
  *   x: in x0, out: final iterate (binary64)
  *   outer loop k = 0, 1, ...: r = b - A x (rows exact, rounded once);
  *     rr = <r,r> (exact); hist[k] = rr; stop if rr <= RN(RN(tol*tol) <b,b>)
- *     or k = maxit_out; s = rpcg_oracle_ir_scale(rr);
- *     c = PCG32(A32, RN32(r 2^-s), x0 = 0, tol_in, maxit_in);
+ *     or k = maxit; s = rpcg_oracle_ir_scale(rr);
+ *     c = PCG32(RN32(A), RN32(r 2^-s), x0 = 0, tol_in, maxit_in);
  *     x = RN(x + (double)c 2^s)
  *   *outer: corrections applied; *inner: total inner iterations.
  * Returns the outer status (OK, WARN_MAXIT) or the first inner error. */
-int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const float *val32,
+int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val64,
                    const double *b, double *x, double tol, int32_t maxit_out, double tol_in,
                    int32_t maxit_in, double *hist, int32_t *outer, int32_t *inner)
 {
     *outer = 0; *inner = 0;
     size_t nn = (size_t)(n > 0 ? n : 1);
     int32_t nnz = n > 0 ? row_ptr[n] : 0;
-    double *val64 = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    float *val32 = malloc(sizeof(float) * (size_t)(nnz > 0 ? nnz : 1));
     double *r = malloc(sizeof(double) * nn);
     float *rf = malloc(sizeof(float) * nn), *c = malloc(sizeof(float) * nn);
-    for (int32_t k = 0; k < nnz; ++k) val64[k] = (double)val32[k];
+    for (int32_t k = 0; k < nnz; ++k) val32[k] = (float)val64[k];
     double bb = rpcg_oracle_exdot(n, b, b);
     double thr = (tol * tol) * bb;
     int status = ORC_OK;
@@ -493,6 +494,6 @@ int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
         for (int32_t i = 0; i < n; ++i) x[i] = x[i] + ldexp((double)c[i], sc);
         *outer = k + 1;
     }
-    free(val64); free(r); free(rf); free(c);
+    free(val32); free(r); free(rf); free(c);
     return status;
 }

@@ -18,12 +18,19 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librpcg.so")
-SOURCES = ["exdot.hip", "sell.hip", "pcg_setup.hip", "pcg_spmv_dot.hip", "pcg_update.hip", "api.cpp"]
+# (source, object suffix, extra flags): the templated solver kernels are built
+# once per value type so the compiles run in parallel
+_TYPED = ["pcg_setup.hip", "pcg_spmv_dot.hip", "pcg_update.hip"]
+SOURCES = ([("exdot.hip", "", []), ("sell.hip", "", []), ("ir.hip", "", []), ("api.cpp", "", [])] +
+           [(f, "." + t, [f"-DRPCG_VALUE_TYPE={t}"]) for f in _TYPED for t in ("double", "float")])
 ARCH = os.environ.get("RPCG_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     "-ffp-contract=off", "-fno-fast-math",
+    # binary32 division correctly rounded and binary32 subnormals kept, as
+    # IEEE 754 binary32 arithmetic requires (the binary32 solver relies on it)
+    "-fhip-fp32-correctly-rounded-divide-sqrt", "-fno-gpu-flush-denormals-to-zero",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
@@ -42,17 +49,17 @@ def build(verbose: bool = False) -> str:
     os.makedirs(objdir, exist_ok=True)
     procs = []
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src + ".o")
+    for src, suffix, extra in SOURCES:
+        obj = os.path.join(objdir, src + suffix + ".o")
         objs.append(obj)
         lang = ["-x", "hip"]
-        cmd = [hipcc(), *lang, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c",
+        cmd = [hipcc(), *lang, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c",
                os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), file=sys.stderr)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
-    for src, p in procs:
+    for src, p in procs:  # noqa: B007
         out, _ = p.communicate()
         text = out.decode(errors="replace")
         if p.returncode != 0:

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rpcg.h"
@@ -47,14 +48,20 @@ struct rpcg_ctx {
     Buffer scalars;           // DotInfo + PcgState
     DotInfo *info = nullptr;
     PcgState *st = nullptr;
-    Buffer sell_off, sell_val, sell_col, sell_len;
-    Buffer vecs;              // r, z, d, w, dinv
+    IrState *ist = nullptr;
+    Buffer sell_off, sell_val, sell_val32, sell_col, sell_len;
+    Buffer vecs;              // r, z, d, w, dinv of the solver
+    Buffer ir_vecs;           // refinement: r (binary64), rf and c (binary32)
     Buffer beta_hist;         // beta of every iteration
     int *host_done = nullptr; // pinned: polled flags
     PcgState *host_state = nullptr;
+    IrState *host_ir = nullptr;
     std::vector<hipEvent_t> events;
+    std::vector<hipEvent_t> ir_events;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
+
+static_assert(sizeof(DotInfo) <= 256 && sizeof(PcgState) <= 256 && sizeof(IrState) <= 256, "scalar layout");
 
 static int hip_status(hipError_t e)
 {
@@ -194,10 +201,12 @@ int rpcg_create(rpcg_ctx **out, int device)
     if (rc == RPCG_OK) {
         c->info = (DotInfo *)c->scalars.p;
         c->st = (PcgState *)((char *)c->scalars.p + 256);
+        c->ist = (IrState *)((char *)c->scalars.p + 512);
         rc = hip_status(hipMemset(c->scalars.p, 0, 1024));
     }
     if (rc == RPCG_OK) rc = hip_status(hipHostMalloc((void **)&c->host_done, 64 * sizeof(int), hipHostMallocDefault));
     if (rc == RPCG_OK) rc = hip_status(hipHostMalloc((void **)&c->host_state, sizeof(PcgState), hipHostMallocDefault));
+    if (rc == RPCG_OK) rc = hip_status(hipHostMalloc((void **)&c->host_ir, sizeof(IrState), hipHostMallocDefault));
     if (rc == RPCG_OK) rc = hip_status(hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming));
     if (rc == RPCG_OK) rc = hip_status(hipEventCreateWithFlags(&c->poll_ev[1], hipEventDisableTiming));
     if (rc == RPCG_OK) rc = ensure_ws(c, 8 * c->num_cus);
@@ -215,13 +224,17 @@ void rpcg_destroy(rpcg_ctx *c)
     c->scalars.release();
     c->sell_off.release();
     c->sell_val.release();
+    c->sell_val32.release();
     c->sell_col.release();
     c->sell_len.release();
     c->vecs.release();
+    c->ir_vecs.release();
     c->beta_hist.release();
     if (c->host_done) hipHostFree(c->host_done);
     if (c->host_state) hipHostFree(c->host_state);
+    if (c->host_ir) hipHostFree(c->host_ir);
     for (hipEvent_t e : c->events) hipEventDestroy(e);
+    for (hipEvent_t e : c->ir_events) hipEventDestroy(e);
     for (hipEvent_t e : c->poll_ev) if (e) hipEventDestroy(e);
     delete c;
 }
@@ -303,53 +316,51 @@ int rpcg_spmv(rpcg_ctx *c, const rpcg_csr *A, const double *x, double *y, void *
     return RPCG_OK;
 }
 
+} // extern "C"
+
 // events per timed iteration: boundaries around K1 | K2 | K3
 static const int EV_PER_IT = 4;
 
-static int ensure_events(rpcg_ctx *c, size_t need)
+static int ensure_events(std::vector<hipEvent_t> &evs, size_t need)
 {
-    while (c->events.size() < need) {
+    while (evs.size() < need) {
         hipEvent_t e;
         RPCG_TRY(hipEventCreate(&e));
-        c->events.push_back(e);
+        evs.push_back(e);
     }
     return RPCG_OK;
 }
 
-int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const double *b, double *x,
-                   const rpcg_opts *opts, rpcg_result *res, void *stream)
+static double ms_since(std::chrono::steady_clock::time_point t)
 {
-    using clk = std::chrono::steady_clock;
-    int mode = (int)mode_in;
-    if (res) std::memset(res, 0, sizeof(*res));
-    if (!c || !valid_csr(A) || (A->n > 0 && (!b || !x))) return RPCG_ERR_INVALID;
-    if (mode != MODE_PLAIN && mode != MODE_FPE && mode != MODE_EXBLAS) return RPCG_ERR_INVALID;
-    rpcg_opts o;
-    rpcg_opts_default(&o);
-    if (opts) o = *opts;
-    if (!valid_opts(o)) return RPCG_ERR_INVALID;
-    o.fpe_size = resolve_fpe_size(o.fpe_size, mode);
-    RPCG_TRY(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
-    const int n = A->n;
-    auto t0 = clk::now();
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
+}
 
-    // workspace: SELL-64 copy of A and five work vectors
+// The solver's sliced-ELL copy of a CSR matrix (see SellMat).
+struct SellBuilt {
+    int nslices = 0;
+    bool col16 = false;
+    const long long *off = nullptr;
+    const double *val64 = nullptr; // binary64 values, if requested
+    const float *val32 = nullptr;  // binary32 values, if requested
+    const int *col = nullptr;
+    const short *col16p = nullptr;
+    const unsigned char *len8 = nullptr;
+};
+
+// One pass over the CSR checks its structure and measures the slices
+// (nothing indexes through the matrix before the check has passed), then the
+// copy is filled. Source values: v64 or v32; kept as binary64 (out64) and/or
+// rounded to binary32 (out32). Waits for the stream.
+static int build_sell(rpcg_ctx *c, int n, int nnz, const int *rp, const int *col, const double *v64,
+                      const float *v32, bool out64, bool out32, bool no_col16, hipStream_t s, SellBuilt *out)
+{
     const int nslices = (n + 63) / 64;
-    LaunchCfg cfg_rows = make_vec_cfg(c, o, std::max(1, n), s);
-    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s);
-    int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
-    if (rc != RPCG_OK) return rc;
-    // one pass over the CSR checks its structure and measures the slices;
-    // nothing indexes through the matrix before the check has passed
     RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
     RPCG_TRY(c->sell_off.ensure(sizeof(long long) * (nslices + 1)));
     long long *off = (long long *)c->sell_off.p;
     RPCG_TRY(hipMemsetAsync(off, 0, sizeof(long long) * (nslices + 1), s));
-    int *bad = &c->info->flags;
-    int *max_len = &c->info->max_len;
-    int *max_delta = &c->info->max_delta;
-    RPCG_TRY(launch_csr_scan(n, A->nnz, A->row_ptr, A->col_idx, off + 1, bad, max_len, max_delta, s));
+    RPCG_TRY(launch_csr_scan(n, nnz, rp, col, off + 1, &c->info->flags, &c->info->max_len, &c->info->max_delta, s));
     RPCG_TRY(launch_sell_scan(off, nslices, s));
     long long padded = 0;
     DotInfo scan_info;
@@ -357,21 +368,68 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     RPCG_TRY(hipMemcpyAsync(&scan_info, c->info, sizeof scan_info, hipMemcpyDeviceToHost, s));
     RPCG_TRY(hipStreamSynchronize(s));
     if (scan_info.flags) return RPCG_ERR_INVALID;
-    const int max_len_h = scan_info.max_len, max_delta_h = scan_info.max_delta;
-    const bool col16 = max_delta_h <= 32767 && !o.no_col16;
-    RPCG_TRY(c->sell_val.ensure(sizeof(double) * std::max(1ll, padded)));
-    RPCG_TRY(c->sell_col.ensure((col16 ? sizeof(short) : sizeof(int)) * std::max(1ll, padded)));
+    const bool col16 = scan_info.max_delta <= 32767 && !no_col16;
+    const size_t np = (size_t)std::max(1ll, padded);
+    double *s64 = nullptr;
+    float *s32 = nullptr;
+    if (out64) { RPCG_TRY(c->sell_val.ensure(sizeof(double) * np)); s64 = (double *)c->sell_val.p; }
+    if (out32) { RPCG_TRY(c->sell_val32.ensure(sizeof(float) * np)); s32 = (float *)c->sell_val32.p; }
+    RPCG_TRY(c->sell_col.ensure((col16 ? sizeof(short) : sizeof(int)) * np));
     unsigned char *len8 = nullptr;
-    if (max_len_h < 256) {
+    if (scan_info.max_len < 256) {
         RPCG_TRY(c->sell_len.ensure((size_t)std::max(1, n)));
         len8 = (unsigned char *)c->sell_len.p;
     }
-    RPCG_TRY(launch_sell_fill(n, A->row_ptr, A->col_idx, A->val, off, (double *)c->sell_val.p,
-                              col16 ? nullptr : (int *)c->sell_col.p, col16 ? (short *)c->sell_col.p : nullptr,
-                              len8, s));
-    RPCG_TRY(c->vecs.ensure(sizeof(double) * 5 * (size_t)std::max(1, n)));
-    double *vb = (double *)c->vecs.p;
-    PcgVecs v;
+    RPCG_TRY(launch_sell_fill(n, rp, col, v64, v32, off, s64, s32, col16 ? nullptr : (int *)c->sell_col.p,
+                              col16 ? (short *)c->sell_col.p : nullptr, len8, s));
+    out->nslices = nslices;
+    out->col16 = col16;
+    out->off = off;
+    out->val64 = s64;
+    out->val32 = s32;
+    out->col = col16 ? nullptr : (const int *)c->sell_col.p;
+    out->col16p = col16 ? (const short *)c->sell_col.p : nullptr;
+    out->len8 = len8;
+    return RPCG_OK;
+}
+
+template <typename T>
+static SellMat<T> sell_mat(const SellBuilt &B, const T *val, int n, const int *row_ptr)
+{
+    SellMat<T> M;
+    M.n = n;
+    M.nslices = B.nslices;
+    M.off = B.off;
+    M.val = val;
+    M.col = B.col;
+    M.col16 = B.col16p;
+    M.row_ptr = row_ptr;
+    M.len8 = B.len8;
+    M.val64 = B.val64;
+    return M;
+}
+
+struct PcgRun {
+    PcgState S;
+    int status = 0;
+    int launched = 0;
+    double setup_ms = 0, loop_ms = 0;
+    double k_ms[3] = {0, 0, 0};
+    int k_launches = 0;
+};
+
+// Jacobi-PCG on a built matrix copy: setup, then batches of K1/K2/K3 with the
+// device `done` flag polled one batch behind, so the host never waits on the
+// iteration it launches. Waits for the stream.
+template <typename T>
+static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x, const rpcg_opts &o,
+                   const LaunchCfg &cfg_rows, const LaunchCfg &cfg_sl, hipStream_t s, PcgRun *out)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const int n = M.n;
+    RPCG_TRY(c->vecs.ensure(sizeof(T) * 5 * (size_t)std::max(1, n)));
+    T *vb = (T *)c->vecs.p;
+    PcgVecs<T> v;
     v.b = b;
     v.x = x;
     v.r = vb;
@@ -382,26 +440,18 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
     v.hist = o.tau_history;
     RPCG_TRY(c->beta_hist.ensure(sizeof(double) * ((size_t)o.maxit + 1)));
     v.beta_hist = (double *)c->beta_hist.p;
-    SellMat M;
-    M.n = n;
-    M.nslices = nslices;
-    M.off = off;
-    M.val = (const double *)c->sell_val.p;
-    M.col = col16 ? nullptr : (const int *)c->sell_col.p;
-    M.col16 = col16 ? (const short *)c->sell_col.p : nullptr;
-    M.row_ptr = A->row_ptr;
-    M.len8 = len8;
-
     const int stride = c->ws_groups;
-    RPCG_TRY(launch_pcg_setup(mode, M, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_sl));
+    RPCG_TRY(launch_pcg_setup<T>(mode, M, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_sl));
     RPCG_TRY(hipStreamSynchronize(s));
-    auto t1 = clk::now();
+    out->setup_ms = ms_since(t0);
+    auto t1 = std::chrono::steady_clock::now();
 
-    // iteration loop: batches of K1/K2/K3, polling the device `done` flag one
-    // batch behind so the host never waits on the iteration it launches
     const bool timing = o.timing != 0;
     const int batch = 8;
-    if (timing) { rc = ensure_events(c, (size_t)EV_PER_IT * std::max(1, o.maxit)); if (rc) return rc; }
+    if (timing) {
+        int rc = ensure_events(c->events, (size_t)EV_PER_IT * std::max(1, o.maxit));
+        if (rc) return rc;
+    }
     int launched = 0;
     volatile int *hd = c->host_done;
     hd[0] = hd[1] = 0;
@@ -411,11 +461,11 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
             const int l = launched + it;
             hipEvent_t *ev = timing ? &c->events[(size_t)l * EV_PER_IT] : nullptr;
             if (ev) RPCG_TRY(hipEventRecord(ev[0], s));
-            RPCG_TRY(launch_pcg_spmv_dot(mode, M, v, c->st, c->ws[0], stride, cfg_sl));
+            RPCG_TRY(launch_pcg_spmv_dot<T>(mode, M, v, c->st, c->ws[0], stride, cfg_sl));
             if (ev) RPCG_TRY(hipEventRecord(ev[1], s));
-            RPCG_TRY(launch_pcg_update(mode, l, n, v, c->st, c->ws[0], cfg_sl.grid, c->ws + 1, stride, cfg_rows));
+            RPCG_TRY(launch_pcg_update<T>(mode, l, n, v, c->st, c->ws[0], cfg_sl.grid, c->ws + 1, stride, cfg_rows));
             if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
-            RPCG_TRY(launch_pcg_direction(mode, l, n, v, c->st, c->ws + 1, cfg_rows.grid, stride, cfg_rows));
+            RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws + 1, cfg_rows.grid, stride, cfg_rows));
             if (ev) RPCG_TRY(hipEventRecord(ev[3], s));
         }
         launched += cnt;
@@ -428,44 +478,267 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode_in, const rpcg_csr *A, const doub
         }
     }
     RPCG_TRY(hipStreamSynchronize(s));
-    auto t2 = clk::now();
+    out->loop_ms = ms_since(t1);
     RPCG_TRY(hipMemcpy(c->host_state, c->st, sizeof(PcgState), hipMemcpyDeviceToHost));
     const PcgState &S = *c->host_state;
+    out->S = S;
+    out->launched = launched;
     int status;
     if (S.status < 0) status = S.status;
     else if (!(S.tau <= S.thr)) status = RPCG_WARN_MAXIT;
     else if ((S.flags & FLAG_INEXACT) || (mode == MODE_FPE && S.escapes > 0 && !o.fpe_fallback))
         status = RPCG_WARN_FPE_INEXACT;
     else status = RPCG_OK;
+    out->status = status;
+    if (timing) {
+        // the first L iterations did the work; later launches were no-ops
+        const int L = std::min(S.iter, launched);
+        for (int i = 0; i < L; ++i)
+            for (int k = 0; k < 3; ++k) {
+                float ms = 0.f;
+                hipEvent_t *ev = &c->events[(size_t)i * EV_PER_IT];
+                if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) out->k_ms[k] += ms;
+            }
+        out->k_launches = L;
+    }
+    return RPCG_OK;
+}
+
+static void fill_result(rpcg_result *res, const PcgRun &run, double build_ms, const LaunchCfg &cfg_rows, bool timing)
+{
+    if (!res) return;
+    const PcgState &S = run.S;
+    res->status = run.status;
+    res->iterations = S.iter;
+    res->tau0 = S.tau0;
+    res->tau_final = S.tau;
+    res->threshold = S.thr;
+    res->fpe_escapes = S.escapes;
+    res->fallbacks = S.fallbacks;
+    res->setup_ms = build_ms + run.setup_ms;
+    res->loop_ms = run.loop_ms;
+    res->grid_size = cfg_rows.grid;
+    res->block_size = cfg_rows.block;
+    if (timing) {
+        res->k_spmv_dot_ms = run.k_ms[0];
+        res->k_update_ms = run.k_ms[1];
+        res->k_direction_ms = run.k_ms[2];
+        res->k_launches = run.k_launches;
+    }
+}
+
+static bool valid_csr_f32(const rpcg_csr_f32 *A)
+{
+    if (!A || A->n < 0 || A->nnz < 0) return false;
+    if (A->n > 0 && (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))) return false;
+    return true;
+}
+
+// Common body of the binary64 and binary32 solves.
+template <typename T>
+static int pcg_solve_any(rpcg_ctx *c, int mode, int n, int nnz, const int *rp, const int *col, const double *v64,
+                         const float *v32, const T *b, T *x, const rpcg_opts *opts, rpcg_result *res, void *stream)
+{
+    if (mode != MODE_PLAIN && mode != MODE_FPE && mode != MODE_EXBLAS) return RPCG_ERR_INVALID;
+    rpcg_opts o;
+    rpcg_opts_default(&o);
+    if (opts) o = *opts;
+    if (!valid_opts(o)) return RPCG_ERR_INVALID;
+    o.fpe_size = resolve_fpe_size(o.fpe_size, mode);
+    RPCG_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    const int nslices = (n + 63) / 64;
+    LaunchCfg cfg_rows = make_vec_cfg(c, o, std::max(1, n), s);
+    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s);
+    int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
+    if (rc != RPCG_OK) return rc;
+    constexpr bool F32 = std::is_same<T, float>::value;
+    SellBuilt B;
+    rc = build_sell(c, n, nnz, rp, col, v64, v32, !F32, F32, o.no_col16 != 0, s, &B);
+    if (rc != RPCG_OK) return rc;
+    const double build_ms = ms_since(t0);
+    const T *val;
+    if constexpr (F32) val = B.val32;
+    else val = B.val64;
+    SellMat<T> M = sell_mat<T>(B, val, n, rp);
+    M.val64 = nullptr;
+    PcgRun run;
+    rc = run_pcg<T>(c, mode, M, b, x, o, cfg_rows, cfg_sl, s, &run);
+    if (rc != RPCG_OK) return rc;
+    fill_result(res, run, build_ms, cfg_rows, o.timing != 0);
+    return run.status;
+}
+
+extern "C" {
+
+int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode, const rpcg_csr *A, const double *b, double *x,
+                   const rpcg_opts *opts, rpcg_result *res, void *stream)
+{
+    if (res) std::memset(res, 0, sizeof(*res));
+    if (!c || !valid_csr(A) || (A->n > 0 && (!b || !x))) return RPCG_ERR_INVALID;
+    int rc = pcg_solve_any<double>(c, (int)mode, A->n, A->nnz, A->row_ptr, A->col_idx, A->val, nullptr, b, x, opts,
+                                   res, stream);
+    if (res) res->status = rc;
+    return rc;
+}
+
+int rpcg_pcg_solve_f32(rpcg_ctx *c, rpcg_mode mode, const rpcg_csr_f32 *A, const float *b, float *x,
+                       const rpcg_opts *opts, rpcg_result *res, void *stream)
+{
+    if (res) std::memset(res, 0, sizeof(*res));
+    if (!c || !valid_csr_f32(A) || (A->n > 0 && (!b || !x))) return RPCG_ERR_INVALID;
+    int rc = pcg_solve_any<float>(c, (int)mode, A->n, A->nnz, A->row_ptr, A->col_idx, nullptr, A->val, b, x, opts,
+                                  res, stream);
+    if (res) res->status = rc;
+    return rc;
+}
+
+void rpcg_ir_opts_default(rpcg_ir_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 1e-10;
+    o->maxit = 50;
+    rpcg_opts_default(&o->inner);
+    o->inner.tol = 1e-4;
+}
+
+// Residual kernel: two wavefronts per workgroup, at most two workgroups per CU
+// (each holds 64 long accumulators per wavefront in LDS).
+static LaunchCfg make_res_cfg(const rpcg_ctx *c, long long nslices, hipStream_t s)
+{
+    LaunchCfg cfg{};
+    cfg.block = 128;
+    cfg.grid = (int)std::max(1ll, std::min((nslices + 1) / 2, 2ll * c->num_cus));
+    cfg.early_exit = true;
+    cfg.fpe_size = 3;
+    cfg.fallback = true;
+    cfg.xcd_parts = 1;
+    cfg.stream = s;
+    return cfg;
+}
+
+static int ir_body(rpcg_ctx *c, int mode, const rpcg_csr *A, const double *b, double *x, const rpcg_ir_opts &io,
+                   rpcg_ir_result *res, hipStream_t s)
+{
+    auto t_start = std::chrono::steady_clock::now();
+    const int n = A->n;
+    rpcg_opts o = io.inner;
+    o.fpe_size = resolve_fpe_size(o.fpe_size, mode);
+    const int nslices = (n + 63) / 64;
+    LaunchCfg cfg_rows = make_vec_cfg(c, o, std::max(1, n), s);
+    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s);
+    LaunchCfg cfg_res = make_res_cfg(c, nslices, s);
+    rpcg_opts dflt;
+    rpcg_opts_default(&dflt);
+    dflt.fpe_size = 3;
+    LaunchCfg cfg_dot = make_cfg(c, dflt, std::max(1, (n + 7) / 8), 256, s);
+    int rc = ensure_ws(c, std::max(std::max(cfg_rows.grid, cfg_sl.grid), std::max(cfg_res.grid, cfg_dot.grid)));
+    if (rc != RPCG_OK) return rc;
+    SellBuilt B;
+    rc = build_sell(c, n, A->nnz, A->row_ptr, A->col_idx, A->val, nullptr, true, true, o.no_col16 != 0, s, &B);
+    if (rc != RPCG_OK) return rc;
+    SellMat<float> M = sell_mat<float>(B, B.val32, n, A->row_ptr);
+    const size_t nn = (size_t)std::max(1, n);
+    RPCG_TRY(c->ir_vecs.ensure(nn * (sizeof(double) + 2 * sizeof(float))));
+    double *r = (double *)c->ir_vecs.p;
+    float *rf = (float *)(r + nn);
+    float *cv = rf + nn;
+    const int stride = c->ws_groups;
+    IrState *ist = c->ist;
+    RPCG_TRY(hipMemsetAsync(ist, 0, sizeof(IrState), s));
+    RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
+    RPCG_TRY(launch_exdot(MODE_EXBLAS, n, b, b, &ist->bb, c->ws[0], stride, c->info, cfg_dot));
+    RPCG_TRY(hipStreamSynchronize(s));
+    const double setup_ms = ms_since(t_start);
+    const bool timing = o.timing != 0;
+    if (timing) {
+        rc = ensure_events(c->ir_events, 2 * ((size_t)io.maxit + 1));
+        if (rc) return rc;
+    }
+    int status = RPCG_OK, outer = 0, inner_its = 0, last_inner = RPCG_OK;
+    bool inexact = false;
+    long long escapes = 0;
+    double inner_ms = 0, outer_ms = 0, kres_ms = 0, kms[3] = {0, 0, 0};
+    int klaunch = 0;
+    double rr0 = 0;
+    IrState *H = c->host_ir;
+    for (int k = 0;; ++k) {
+        auto to = std::chrono::steady_clock::now();
+        hipEvent_t *ev = timing ? &c->ir_events[2 * (size_t)k] : nullptr;
+        if (ev) RPCG_TRY(hipEventRecord(ev[0], s));
+        RPCG_TRY(launch_ir_residual(M, b, x, r, ist, c->ws[0], stride, cfg_res));
+        if (ev) RPCG_TRY(hipEventRecord(ev[1], s));
+        RPCG_TRY(launch_ir_prepare(k, io.maxit, io.tol, n, r, rf, cv, io.rr_history, ist, c->ws[0], cfg_res.grid,
+                                   stride, cfg_rows));
+        RPCG_TRY(hipMemcpyAsync(H, ist, sizeof(IrState), hipMemcpyDeviceToHost, s));
+        RPCG_TRY(hipStreamSynchronize(s));
+        outer_ms += ms_since(to);
+        if (ev) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess) kres_ms += ms;
+        }
+        if (k == 0) rr0 = H->rr;
+        if (H->flags & FLAG_INEXACT) inexact = true;
+        if (H->stop) { status = H->status; break; }
+        auto ti = std::chrono::steady_clock::now();
+        PcgRun run;
+        rc = run_pcg<float>(c, mode, M, rf, cv, o, cfg_rows, cfg_sl, s, &run);
+        if (rc != RPCG_OK) return rc;
+        inner_ms += ms_since(ti);
+        inner_its += run.S.iter;
+        escapes += run.S.escapes;
+        last_inner = run.status;
+        for (int j = 0; j < 3; ++j) kms[j] += run.k_ms[j];
+        klaunch += run.k_launches;
+        if (run.status < 0) { status = run.status; break; }
+        if (run.status == RPCG_WARN_FPE_INEXACT) inexact = true;
+        auto tu = std::chrono::steady_clock::now();
+        RPCG_TRY(launch_ir_update(n, x, cv, ist, cfg_rows));
+        RPCG_TRY(hipStreamSynchronize(s));
+        outer_ms += ms_since(tu);
+        ++outer;
+    }
+    if (status == RPCG_OK && inexact) status = RPCG_WARN_FPE_INEXACT;
     if (res) {
         res->status = status;
-        res->iterations = S.iter;
-        res->tau0 = S.tau0;
-        res->tau_final = S.tau;
-        res->threshold = S.thr;
-        res->fpe_escapes = S.escapes;
-        res->fallbacks = S.fallbacks;
-        res->setup_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
-        res->loop_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
-        res->grid_size = cfg_rows.grid;
-        res->block_size = cfg_rows.block;
+        res->outer = outer;
+        res->inner_iterations = inner_its;
+        res->last_inner_status = last_inner;
+        res->rr0 = rr0;
+        res->rr_final = H->rr;
+        res->threshold = H->thr;
+        res->fpe_escapes = escapes;
+        res->setup_ms = setup_ms;
+        res->total_ms = ms_since(t_start);
+        res->inner_ms = inner_ms;
+        res->outer_ms = outer_ms;
         if (timing) {
-            // the first L iterations did the work; later launches were no-ops
-            int L = std::min(S.iter, launched);
-            double sums[3] = {0, 0, 0};
-            for (int i = 0; i < L; ++i)
-                for (int k = 0; k < 3; ++k) {
-                    float ms = 0.f;
-                    hipEvent_t *ev = &c->events[(size_t)i * EV_PER_IT];
-                    if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) sums[k] += ms;
-                }
-            res->k_spmv_dot_ms = sums[0];
-            res->k_update_ms = sums[1];
-            res->k_direction_ms = sums[2];
-            res->k_launches = L;
+            res->k_residual_ms = kres_ms;
+            res->k_spmv_dot_ms = kms[0];
+            res->k_update_ms = kms[1];
+            res->k_direction_ms = kms[2];
+            res->k_launches = klaunch;
         }
     }
     return status;
+}
+
+int rpcg_ir_solve(rpcg_ctx *c, rpcg_mode mode, const rpcg_csr *A, const double *b, double *x,
+                  const rpcg_ir_opts *opts, rpcg_ir_result *res, void *stream)
+{
+    if (res) std::memset(res, 0, sizeof(*res));
+    if (!c || !valid_csr(A) || (A->n > 0 && (!b || !x))) return RPCG_ERR_INVALID;
+    if ((int)mode != MODE_PLAIN && (int)mode != MODE_FPE && (int)mode != MODE_EXBLAS) return RPCG_ERR_INVALID;
+    rpcg_ir_opts io;
+    rpcg_ir_opts_default(&io);
+    if (opts) io = *opts;
+    if (!(io.tol >= 0.0) || io.maxit < 0 || io.inner.tau_history || !valid_opts(io.inner)) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    int rc = ir_body(c, (int)mode, A, b, x, io, res, (hipStream_t)stream);
+    if (res) res->status = rc;
+    return rc;
 }
 
 } // extern "C"

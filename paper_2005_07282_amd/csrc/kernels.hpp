@@ -65,17 +65,22 @@ struct PcgState {
 // Sliced-ELL copy of the matrix with slice height 64 (one wavefront): entry
 // k of row 64*s + j sits at off[s] + 64*k + j, so lane j of a wavefront
 // walks its row while each load of the wavefront is one contiguous 512-byte
-// (values) or 256-byte (columns) segment. Rows keep their CSR order and
-// length; padding entries are never read.
+// (binary64 values), 256-byte (binary32 values or 32-bit columns) or
+// 128-byte (16-bit columns) segment. Rows keep their CSR order and length;
+// padding entries hold the value 0 and a valid column. T is the type the
+// solver computes in; val64 optionally holds the caller's binary64 values in
+// the same layout (used by the refinement's residual next to binary32 val).
+template <typename T>
 struct SellMat {
     int n;
     int nslices;
     const long long *off; // [nslices + 1]
-    const double *val;
+    const T *val;
     const int *col;
     const int *row_ptr;   // the caller's CSR row pointers (row lengths)
     const unsigned char *len8; // row lengths as bytes when every row has < 256 entries, else null
     const short *col16;   // when non-null: columns as col - min(row, n-1) in 16 bits (col unused)
+    const double *val64;  // optional binary64 values (same layout), else null
 };
 
 struct LaunchCfg {
@@ -105,27 +110,68 @@ hipError_t launch_csr_scan(int n, int nnz, const int *row_ptr, const int *col, l
                            int *max_len, int *max_delta, hipStream_t s);
 
 hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
-hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
-                            const long long *off, double *sval, int *scol, short *scol16, unsigned char *len8,
-                            hipStream_t s);
+// Fill the sliced-ELL arrays from the CSR. The source values are binary64
+// (val64_in) or binary32 (val32_in, exactly one of the two non-null); sval64
+// receives them as binary64, sval32 rounded to nearest binary32; either
+// output may be null.
+hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val64_in,
+                            const float *val32_in, const long long *off, double *sval64, float *sval32, int *scol,
+                            short *scol16, unsigned char *len8, hipStream_t s);
 
+template <typename T>
 struct PcgVecs {
-    const double *b;
-    double *x, *r, *z, *d, *w, *dinv;
-    double *hist;      // optional [maxit + 1]: tau history
-    double *beta_hist; // [maxit + 1]: beta of every iteration
+    const T *b;
+    T *x, *r, *z, *d, *w, *dinv;
+    double *hist;      // optional [maxit + 1]: tau history (widened to binary64)
+    double *beta_hist; // [maxit + 1]: beta of every iteration (widened to binary64)
 };
 
+// The PCG launchers exist for T = double (the paper's solver) and T = float
+// (the binary32 inner solver of the mixed-precision refinement). Scalars in
+// PcgState are held as binary64; binary32 values widen to it exactly.
+
 // Setup (state init, partials, one-workgroup finalize) into ws3[0..2].
-hipError_t launch_pcg_setup(int mode, const SellMat &A, const PcgVecs &v, PcgState *st, const DotWs *ws3,
+template <typename T>
+hipError_t launch_pcg_setup(int mode, const SellMat<T> &A, const PcgVecs<T> &v, PcgState *st, const DotWs *ws3,
                             int stride, double tol, int maxit, const LaunchCfg &cfg);
 // Iteration l: K1 writes its partials to `ws`; K2 merges them (Gd slots) and
 // writes two dots into ws2[0..1]; K3 merges those (G slots).
-hipError_t launch_pcg_spmv_dot(int mode, const SellMat &A, const PcgVecs &v, PcgState *st,
+template <typename T>
+hipError_t launch_pcg_spmv_dot(int mode, const SellMat<T> &A, const PcgVecs<T> &v, PcgState *st,
                                const DotWs &ws, int stride, const LaunchCfg &cfg);
-hipError_t launch_pcg_update(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs &wsd, int Gd,
+template <typename T>
+hipError_t launch_pcg_update(int mode, int l, int n, const PcgVecs<T> &v, PcgState *st, const DotWs &wsd, int Gd,
                              const DotWs *ws2, int stride, const LaunchCfg &cfg);
-hipError_t launch_pcg_direction(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs *ws2, int G,
+template <typename T>
+hipError_t launch_pcg_direction(int mode, int l, int n, const PcgVecs<T> &v, PcgState *st, const DotWs *ws2, int G,
                                 int stride, const LaunchCfg &cfg);
+
+// ---- mixed-precision refinement (binary64 outer loop) ----
+
+// Outer-loop state on the device.
+struct IrState {
+    double rr;      // <r, r> of the current outer step (exact, rounded once)
+    double bb;      // <b, b>
+    double thr;     // RN(RN(tol*tol) * <b,b>)
+    int k;          // outer step whose residual was last formed
+    int stop;       // nonzero: converged, out of outer steps or failed
+    int status;     // outer status (rpcg codes)
+    int scale;      // s of the current correction: inner rhs = RN32(r 2^-s)
+    int flags;
+    int pad;
+    long long escapes;
+};
+
+// r = RN(b - A x) with every row summed exactly (binary64 values A.val64 of
+// the sliced-ELL copy), and the workgroup partials of <r, r> into ws (exact
+// dot, expansion length 3).
+hipError_t launch_ir_residual(const SellMat<float> &A, const double *b, const double *x, double *r, IrState *ist,
+                              const DotWs &ws, int stride, const LaunchCfg &cfg);
+// Merge <r, r> (G slots), record rr_hist[k], decide whether to stop, and for
+// a further correction the inner right-hand side rf = RN32(r 2^-s) and c = 0.
+hipError_t launch_ir_prepare(int k, int maxit, double tol, int n, const double *r, float *rf, float *c,
+                             double *rr_hist, IrState *ist, const DotWs &ws, int G, int stride, const LaunchCfg &cfg);
+// x = RN(x + c 2^s).
+hipError_t launch_ir_update(int n, double *x, const float *c, const IrState *ist, const LaunchCfg &cfg);
 
 } // namespace rpcg

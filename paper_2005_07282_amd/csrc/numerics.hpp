@@ -187,4 +187,102 @@ __host__ __device__ inline double acc_round(long long *acc)
     return __builtin_bit_cast(double, bits);
 }
 
+// ---------------------------------------------------------------------------
+// Lane-private long accumulator with a tracked window: word k lives at
+// w[k * STRIDE] (one column of a [ACC_DIGITS][STRIDE] array, so the lanes of
+// a wavefront own neighbouring columns), every word starts at zero, and only
+// the words [lo, hi] are touched by additions. Rounding visits the window and
+// the few words the carries reach, and leaves every word at zero again.
+template <int STRIDE>
+struct WindowAcc {
+    long long *w;
+    int lo, hi;
+
+    __host__ __device__ __forceinline__ void init(long long *col)
+    {
+        w = col;
+        lo = ACC_DIGITS;
+        hi = -1;
+    }
+
+    // v finite and nonzero
+    __host__ __device__ __forceinline__ void add(double v)
+    {
+        AccChunks c = acc_chunks(v);
+        w[c.k * STRIDE] += c.c0;
+        w[(c.k + 1) * STRIDE] += c.c1;
+        w[(c.k + 2) * STRIDE] += c.c2;
+        lo = c.k < lo ? c.k : lo;
+        hi = c.k + 2 > hi ? c.k + 2 : hi;
+    }
+
+    __host__ __device__ __forceinline__ unsigned long long word(int k) const
+    {
+        return (k >= 0 && k < ACC_DIGITS) ? (unsigned long long)(unsigned)w[k * STRIDE] : 0ull;
+    }
+
+    // Correctly rounded binary64 value (ties to even, +0 for an exact zero,
+    // infinity at or above 2^1024 - 2^970 in magnitude; same rule as
+    // acc_round), then clear.
+    __host__ __device__ inline double round_and_clear()
+    {
+        if (hi < 0) return 0.0;
+        // carry propagation from the lowest touched word; above `hi` the
+        // carry settles to 0 (non-negative value) or -1 (negative value)
+        long long c = 0;
+        int kend = ACC_DIGITS - 1;
+        for (int k = lo; k < ACC_DIGITS; ++k) {
+            const long long t = w[k * STRIDE] + c;
+            w[k * STRIDE] = t & 0xFFFFFFFFll;
+            c = t >> 32;
+            if (k >= hi && (c == 0 || c == -1)) { kend = k; break; }
+        }
+        const bool neg = c < 0;
+        if (neg) {
+            // magnitude = 2^(32 (kend+1)) - U: two's complement of the window
+            // (words below lo are zero, so the +1 enters at lo)
+            unsigned long long borrow = 1;
+            for (int k = lo; k <= kend; ++k) {
+                const unsigned long long t = ((~(unsigned long long)w[k * STRIDE]) & 0xFFFFFFFFull) + borrow;
+                w[k * STRIDE] = (long long)(t & 0xFFFFFFFFull);
+                borrow = t >> 32;
+            }
+            if (borrow && kend + 1 < ACC_DIGITS) { ++kend; w[kend * STRIDE] = (long long)borrow; }
+        }
+        int h = kend;
+        while (h >= lo && w[h * STRIDE] == 0) --h;
+        double result = 0.0;
+        if (h >= lo) {
+            const int msb = 63 - __builtin_clzll((unsigned long long)w[h * STRIDE]);
+            const int B = 32 * h + msb;
+            const int E = B + ACC_EXP0;
+            if (E >= 1024) {
+                result = neg ? -__builtin_inf() : __builtin_inf();
+            } else {
+                int q = E - 52;
+                if (q < -1074) q = -1074;
+                const int Q = q - ACC_EXP0;
+                const int kq = Q >> 5, sq = Q & 31;
+                const unsigned long long lo64 = word(kq) | (word(kq + 1) << 32);
+                const unsigned long long r = (lo64 >> sq) | (sq ? (word(kq + 2) << (64 - sq)) : 0ull);
+                const int len = B - Q + 1;
+                unsigned long long I = r & ((1ull << len) - 1);
+                const int R = Q - 1, kr = R >> 5, sr = R & 31;
+                const unsigned long long wr = word(kr);
+                const bool half = (wr >> sr) & 1ull;
+                bool sticky = (wr & ((1ull << sr) - 1)) != 0;
+                for (int k = lo; k < kr && !sticky; ++k) sticky = w[k * STRIDE] != 0;
+                if (half && (sticky || (I & 1ull))) I += 1;
+                unsigned long long bits = ((unsigned long long)(q + 1074) << 52) + I;
+                if (neg) bits |= 1ull << 63;
+                result = __builtin_bit_cast(double, bits);
+            }
+        }
+        for (int k = lo; k <= kend; ++k) w[k * STRIDE] = 0;
+        lo = ACC_DIGITS;
+        hi = -1;
+        return result;
+    }
+};
+
 } // namespace rpcg

@@ -1,4 +1,5 @@
-// Jacobi-PCG iteration, first kernel: SpMV fused with the first dot (S1, S2).
+// Jacobi-PCG iteration, first kernel: SpMV fused with the first dot (S1, S2),
+// for binary64 (T = double) and the binary32 inner solver (T = float).
 #include "reduce.hpp"
 #include "sell_spmv.hpp"
 
@@ -11,9 +12,9 @@ namespace rpcg {
 // `xcd_parts` contiguous ranges and workgroup b works in range b % xcd_parts
 // (workgroups are dispatched round-robin over the XCDs), so the rows whose d
 // entries an XCD gathers stay together in that XCD's L2.
-template <int MODE, int P, bool COL16>
+template <int MODE, int P, bool COL16, typename T>
 __global__ void __launch_bounds__(MAX_BLOCK)
-k_pcg_spmv_dot(SellMat A, PcgVecs v, PcgState *st, SlotView sv, bool ee, bool capture, int xcd_parts)
+k_pcg_spmv_dot(SellMat<T> A, PcgVecs<T> v, PcgState *st, SlotView sv, bool ee, bool capture, int xcd_parts)
 {
     __shared__ RedShared sh;
     if (st->done) return;
@@ -23,7 +24,7 @@ k_pcg_spmv_dot(SellMat A, PcgVecs v, PcgState *st, SlotView sv, bool ee, bool ca
     LaneDot<MODE, P> L;
     L.init();
     const int lane = lane_id();
-    const double *__restrict__ d = v.d;
+    const T *__restrict__ d = v.d;
     const int W = num_waves();
     // range of slices handled by this workgroup's group of workgroups
     const int part = blockIdx.x % xcd_parts;
@@ -40,7 +41,7 @@ k_pcg_spmv_dot(SellMat A, PcgVecs v, PcgState *st, SlotView sv, bool ee, bool ca
         const int width = __builtin_amdgcn_readfirstlane((int)((A.off[s + 1] - base) >> 6));
         const long long i = s * 64 + lane;
         const int len = sell_len(A, i);
-        const double sum = sell_row<COL16, false>(A, base, width, i, len, d, nullptr, nullptr);
+        const T sum = sell_row<T, COL16, false>(A, base, width, i, len, d, nullptr, nullptr);
         if (i < A.n) {
             v.w[i] = sum;
             L.add(d[i], sum, acc, ee, capture);
@@ -49,7 +50,8 @@ k_pcg_spmv_dot(SellMat A, PcgVecs v, PcgState *st, SlotView sv, bool ee, bool ca
     block_finish<MODE, P>(L, acc, sv, blockIdx.x, ee, capture, &st->flags, sh);
 }
 
-hipError_t launch_pcg_spmv_dot(int mode, const SellMat &A, const PcgVecs &v, PcgState *st,
+template <typename T>
+hipError_t launch_pcg_spmv_dot(int mode, const SellMat<T> &A, const PcgVecs<T> &v, PcgState *st,
                                const DotWs &ws, int stride, const LaunchCfg &c)
 {
     const int parts = (c.grid >= 64 && c.xcd_parts > 1) ? c.xcd_parts : 1;
@@ -57,11 +59,21 @@ hipError_t launch_pcg_spmv_dot(int mode, const SellMat &A, const PcgVecs &v, Pcg
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
         constexpr int M = decltype(m)::value, PP = decltype(p)::value;
         if (A.col16)
-            k_pcg_spmv_dot<M, PP, true><<<c.grid, c.block, 0, c.stream>>>(A, v, st, sv, c.early_exit, c.fallback, parts);
+            k_pcg_spmv_dot<M, PP, true, T><<<c.grid, c.block, 0, c.stream>>>(A, v, st, sv, c.early_exit,
+                                                                            c.fallback, parts);
         else
-            k_pcg_spmv_dot<M, PP, false><<<c.grid, c.block, 0, c.stream>>>(A, v, st, sv, c.early_exit, c.fallback, parts);
+            k_pcg_spmv_dot<M, PP, false, T><<<c.grid, c.block, 0, c.stream>>>(A, v, st, sv, c.early_exit,
+                                                                             c.fallback, parts);
     });
     return hipGetLastError();
 }
+
+// Built once per value type (the library compiles this file with
+// -DRPCG_VALUE_TYPE=double and with -DRPCG_VALUE_TYPE=float).
+#ifndef RPCG_VALUE_TYPE
+#error "define RPCG_VALUE_TYPE (double or float)"
+#endif
+template hipError_t launch_pcg_spmv_dot<RPCG_VALUE_TYPE>(int, const SellMat<RPCG_VALUE_TYPE> &, const PcgVecs<RPCG_VALUE_TYPE> &, PcgState *,
+                                                const DotWs &, int, const LaunchCfg &);
 
 } // namespace rpcg

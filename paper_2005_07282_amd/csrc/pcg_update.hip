@@ -11,21 +11,22 @@
 // writes for later iterations (beta history, tau history, done flag) are
 // never read by another workgroup of the same kernel.
 #include "reduce.hpp"
+#include "sell_spmv.hpp"
 
 namespace rpcg {
 
-template <int MODE, int P>
+template <int MODE, int P, typename T>
 __global__ void __launch_bounds__(MAX_BLOCK)
-k_pcg_update(int l, int n, PcgVecs v, PcgState *st, SlotView sd, int Gd, SlotView wb, SlotView wt, bool ee,
+k_pcg_update(int l, int n, PcgVecs<T> v, PcgState *st, SlotView sd, int Gd, SlotView wb, SlotView wt, bool ee,
              bool capture)
 {
     __shared__ RedShared sh;
-    if (st->done) return;
+    if (wg_read_flag(&st->done, sh)) return;
     // S2: delta = <d, w> rounded once; rho = beta_l / delta
     long long esc_d = 0;
-    const double delta = merge_slots<MODE, P>(sd, Gd, ee, capture, sh.acc[0], &esc_d, &st->flags, sh, 0);
-    const bool bad = (st->flags & FLAG_NONFINITE) || !is_finite_bits(delta);
-    const bool breakdown = !(delta > 0.0);
+    const T delta = merge_slots<MODE, P, T>(sd, Gd, ee, capture, sh.acc[0], &esc_d, &st->flags, sh, 0);
+    const bool bad = (st->flags & FLAG_NONFINITE) || !is_finite_bits((double)delta);
+    const bool breakdown = !(delta > T(0));
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->escapes += esc_d;
         if (capture && esc_d > 0) st->fallbacks += 1;
@@ -34,7 +35,7 @@ k_pcg_update(int l, int n, PcgVecs v, PcgState *st, SlotView sd, int Gd, SlotVie
         else if (breakdown) { st->status = -5; st->done = 1; }
     }
     if (bad || breakdown) return;
-    const double rho = v.beta_hist[l] / delta;
+    const T rho = (T)v.beta_hist[l] / delta;
     if (blockIdx.x == 0 && threadIdx.x == 0) st->rho = rho;
 
     zero_acc(sh.acc[0]);
@@ -45,10 +46,10 @@ k_pcg_update(int l, int n, PcgVecs v, PcgState *st, SlotView sd, int Gd, SlotVie
     Lt.init();
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        double di = v.d[i], wi = v.w[i];
-        v.x[i] = __builtin_fma(rho, di, v.x[i]);         // S3
-        double ri = __builtin_fma(-rho, wi, v.r[i]);      // S4
-        double zi = v.dinv[i] * ri;                       // S5
+        const T di = v.d[i], wi = v.w[i];
+        v.x[i] = fma_t(rho, di, v.x[i]);                  // S3
+        const T ri = fma_t(-rho, wi, v.r[i]);             // S4
+        const T zi = v.dinv[i] * ri;                      // S5
         v.r[i] = ri;
         v.z[i] = zi;
         Lb.add(zi, ri, sh.acc[0], ee, capture);           // S6
@@ -62,27 +63,27 @@ k_pcg_update(int l, int n, PcgVecs v, PcgState *st, SlotView sd, int Gd, SlotVie
 // the loads are in flight while the merge runs.
 constexpr int DIR_PREFETCH = 8;
 
-template <int MODE, int P>
+template <int MODE, int P, typename T>
 __global__ void __launch_bounds__(MAX_BLOCK)
-k_pcg_direction(int l, int n, PcgVecs v, PcgState *st, SlotView wb, SlotView wt, int G, bool ee, bool capture)
+k_pcg_direction(int l, int n, PcgVecs<T> v, PcgState *st, SlotView wb, SlotView wt, int G, bool ee, bool capture)
 {
     __shared__ RedShared sh;
-    if (st->done) return;
+    if (wg_read_flag(&st->done, sh)) return;
     const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    double dv[DIR_PREFETCH], zv[DIR_PREFETCH];
+    T dv[DIR_PREFETCH], zv[DIR_PREFETCH];
 #pragma unroll
     for (int j = 0; j < DIR_PREFETCH; ++j) {
         const long long i = i0 + j * stride;
-        dv[j] = i < n ? v.d[i] : 0.0;
-        zv[j] = i < n ? v.z[i] : 0.0;
+        dv[j] = i < n ? v.d[i] : T(0);
+        zv[j] = i < n ? v.z[i] : T(0);
     }
     long long eb = 0, et = 0;
-    const double beta = merge_slots<MODE, P>(wb, G, ee, capture, sh.acc[0], &eb, &st->flags, sh, 0);
-    const double tau = merge_slots<MODE, P>(wt, G, ee, capture, sh.acc[1], &et, &st->flags, sh, 1);
-    const bool bad = (st->flags & FLAG_NONFINITE) || !is_finite_bits(beta) || !is_finite_bits(tau);
+    const T beta = merge_slots<MODE, P, T>(wb, G, ee, capture, sh.acc[0], &eb, &st->flags, sh, 0);
+    const T tau = merge_slots<MODE, P, T>(wt, G, ee, capture, sh.acc[1], &et, &st->flags, sh, 1);
+    const bool bad = (st->flags & FLAG_NONFINITE) || !is_finite_bits((double)beta) || !is_finite_bits((double)tau);
     const int it = l + 1;
-    const bool stop = bad || tau <= st->thr || it >= st->maxit;
+    const bool stop = bad || (double)tau <= st->thr || it >= st->maxit;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->escapes += eb + et;
         if (capture) st->fallbacks += (eb > 0) + (et > 0);
@@ -98,39 +99,51 @@ k_pcg_direction(int l, int n, PcgVecs v, PcgState *st, SlotView wb, SlotView wt,
         if (stop) st->done = 1;
     }
     if (stop) return;
-    const double gamma = beta / v.beta_hist[l];
+    const T gamma = beta / (T)v.beta_hist[l];
     if (blockIdx.x == 0 && threadIdx.x == 0) st->gamma = gamma;
 #pragma unroll
     for (int j = 0; j < DIR_PREFETCH; ++j) {
         const long long i = i0 + j * stride;
-        if (i < n) v.d[i] = __builtin_fma(gamma, dv[j], zv[j]);   // S7
+        if (i < n) v.d[i] = fma_t(gamma, dv[j], zv[j]);   // S7
     }
     for (long long i = i0 + DIR_PREFETCH * stride; i < n; i += stride)
-        v.d[i] = __builtin_fma(gamma, v.d[i], v.z[i]);
+        v.d[i] = fma_t(gamma, v.d[i], v.z[i]);
 }
 
-hipError_t launch_pcg_update(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs &wsd, int Gd,
+template <typename T>
+hipError_t launch_pcg_update(int mode, int l, int n, const PcgVecs<T> &v, PcgState *st, const DotWs &wsd, int Gd,
                              const DotWs *ws2, int stride, const LaunchCfg &c)
 {
     SlotView sd{wsd, stride}, sb{ws2[0], stride}, stt{ws2[1], stride};
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
         constexpr int M = decltype(m)::value, PP = decltype(p)::value;
-        k_pcg_update<M, PP><<<c.grid, c.block, 0, c.stream>>>(l, n, v, st, sd, Gd, sb, stt, c.early_exit,
-                                                              c.fallback);
+        k_pcg_update<M, PP, T><<<c.grid, c.block, 0, c.stream>>>(l, n, v, st, sd, Gd, sb, stt, c.early_exit,
+                                                                 c.fallback);
     });
     return hipGetLastError();
 }
 
-hipError_t launch_pcg_direction(int mode, int l, int n, const PcgVecs &v, PcgState *st, const DotWs *ws2, int G,
+template <typename T>
+hipError_t launch_pcg_direction(int mode, int l, int n, const PcgVecs<T> &v, PcgState *st, const DotWs *ws2, int G,
                                 int stride, const LaunchCfg &c)
 {
     SlotView sb{ws2[0], stride}, stt{ws2[1], stride};
     dispatch(mode, c.fpe_size, [&](auto m, auto p) {
         constexpr int M = decltype(m)::value, PP = decltype(p)::value;
-        k_pcg_direction<M, PP><<<c.grid, c.block, 0, c.stream>>>(l, n, v, st, sb, stt, G, c.early_exit,
-                                                                 c.fallback);
+        k_pcg_direction<M, PP, T><<<c.grid, c.block, 0, c.stream>>>(l, n, v, st, sb, stt, G, c.early_exit,
+                                                                    c.fallback);
     });
     return hipGetLastError();
 }
+
+// Built once per value type (the library compiles this file with
+// -DRPCG_VALUE_TYPE=double and with -DRPCG_VALUE_TYPE=float).
+#ifndef RPCG_VALUE_TYPE
+#error "define RPCG_VALUE_TYPE (double or float)"
+#endif
+template hipError_t launch_pcg_update<RPCG_VALUE_TYPE>(int, int, int, const PcgVecs<RPCG_VALUE_TYPE> &, PcgState *, const DotWs &,
+                                              int, const DotWs *, int, const LaunchCfg &);
+template hipError_t launch_pcg_direction<RPCG_VALUE_TYPE>(int, int, int, const PcgVecs<RPCG_VALUE_TYPE> &, PcgState *,
+                                                 const DotWs *, int, int, const LaunchCfg &);
 
 } // namespace rpcg

@@ -44,9 +44,18 @@ struct RedShared {
     double part[MAX_WAVES * MAX_FPE];
     int rng[2];
     int esc;
-    int pad;
+    int flag;
     double val[3];
 };
+
+// Workgroup-uniform read of a flag that workgroup 0 of the same kernel may
+// set while this workgroup runs: one thread reads, every thread sees its value.
+__device__ __forceinline__ bool wg_read_flag(const int *p, RedShared &sh)
+{
+    if (threadIdx.x == 0) sh.flag = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    return sh.flag != 0;
+}
 
 __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags)
 {
@@ -103,6 +112,27 @@ struct LaneDot {
                 if (left != 0.0) { ++esc; if (capture) acc_add_lds(acc, left, flags); }
                 left = fpe_accumulate<P>(e, t, ee);
                 if (left != 0.0) { ++esc; if (capture) acc_add_lds(acc, left, flags); }
+            }
+        }
+    }
+
+    // binary32 operands: the product has at most 48 significant bits and an
+    // exponent of at least -298, so it is exact in binary64 and enters the
+    // expansion as one term (no TwoProd error term).
+    __device__ __forceinline__ void add(float x, float y, long long *acc, bool ee, bool capture)
+    {
+        const double p = (double)x * (double)y;
+        if constexpr (MODE == MODE_PLAIN) {
+            s += p;
+        } else {
+            double left = fpe_accumulate<P>(a, p, ee);
+            if (left != 0.0) {
+                if constexpr (MODE == MODE_FPE) {
+                    ++esc;
+                    if (capture) acc_add_lds(acc, left, flags);
+                } else {
+                    acc_add_lds(acc, left, flags);
+                }
             }
         }
     }
@@ -299,8 +329,18 @@ __device__ __forceinline__ long long wave_word(long long a, long long b, int k)
     return v;
 }
 
-__device__ inline double wave_acc_round(const long long *acc)
+// Rounding format: significand bits, weight of the last bit of the smallest
+// subnormal, and the exponent at which values overflow (2^EMAX_INF).
+template <typename T> struct Fmt;
+template <> struct Fmt<double> { static constexpr int PREC = 53, QMIN = -1074, EMAX_INF = 1024; };
+template <> struct Fmt<float> { static constexpr int PREC = 24, QMIN = -149, EMAX_INF = 128; };
+
+// Correctly rounded (nearest, ties to even) value of the accumulator in
+// format T, computed by one full wavefront; every lane returns it.
+template <typename T = double>
+__device__ inline T wave_acc_round(const long long *acc)
 {
+    constexpr int PREC = Fmt<T>::PREC, QMIN = Fmt<T>::QMIN, EMAX_INF = Fmt<T>::EMAX_INF;
     const int l = lane_id();
     long long a = (2 * l < ACC_DIGITS) ? acc[2 * l] : 0;
     long long b = (2 * l + 1 < ACC_DIGITS) ? acc[2 * l + 1] : 0;
@@ -315,22 +355,22 @@ __device__ inline double wave_acc_round(const long long *acc)
     int h = -1;
     if (mb) h = 2 * (63 - __builtin_clzll(mb)) + 1;
     if (ma) h = max(h, 2 * (63 - __builtin_clzll(ma)));
-    if (h < 0) return 0.0;
+    if (h < 0) return T(0);
     const unsigned long long dh = (unsigned long long)wave_word(a, b, h);
     const int msb = 63 - __builtin_clzll(dh);
     const int B = 32 * h + msb;  // bit index of the leading one
     const int E = B + ACC_EXP0;  // value in [2^E, 2^(E+1))
-    if (E >= 1024) return neg ? -__builtin_inf() : __builtin_inf();
-    int q = E - 52;
-    if (q < -1074) q = -1074;
-    const int Q = q - ACC_EXP0;  // bit index of the last kept bit, >= 14
+    if (E >= EMAX_INF) return neg ? -__builtin_inf() : __builtin_inf();
+    int q = E - (PREC - 1);
+    if (q < QMIN) q = QMIN;
+    const int Q = q - ACC_EXP0;  // bit index of the last kept bit
     const int kq = Q >> 5, sq = Q & 31;
     const unsigned long long w0 = (unsigned)wave_word(a, b, kq);
     const unsigned long long w1 = (unsigned)wave_word(a, b, kq + 1);
     const unsigned long long w2 = (unsigned)wave_word(a, b, kq + 2);
     const unsigned long long lo64 = w0 | (w1 << 32);
     const unsigned long long r = (lo64 >> sq) | (sq ? (w2 << (64 - sq)) : 0ull);
-    const int len = B - Q + 1; // <= 53
+    const int len = B - Q + 1; // <= PREC
     unsigned long long I = r & ((1ull << len) - 1);
     // rounding bit Q-1 and sticky bits below it
     const int R = Q - 1, kr = R >> 5, sr = R & 31;
@@ -340,9 +380,17 @@ __device__ inline double wave_acc_round(const long long *acc)
     const bool low = ((2 * l < kr) && a != 0) || ((2 * l + 1 < kr) && b != 0);
     sticky = sticky || (__ballot(low) != 0);
     if (half && (sticky || (I & 1ull))) I += 1;
-    unsigned long long bits = ((unsigned long long)(q + 1074) << 52) + I;
-    if (neg) bits |= 1ull << 63;
-    return __builtin_bit_cast(double, bits);
+    // exponent field (q - QMIN) above the significand; a carry of I into the
+    // next power of two moves into the exponent field, up to infinity
+    if constexpr (PREC == 53) {
+        unsigned long long bits = ((unsigned long long)(q - QMIN) << 52) + I;
+        if (neg) bits |= 1ull << 63;
+        return __builtin_bit_cast(double, bits);
+    } else {
+        unsigned bits = ((unsigned)(q - QMIN) << 23) + (unsigned)I;
+        if (neg) bits |= 1u << 31;
+        return __builtin_bit_cast(float, bits);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -366,12 +414,12 @@ __device__ __forceinline__ long long sum_row(const long long *row, int G)
     return wave_sum_down(t);
 }
 
-template <int MODE, int P>
-__device__ __forceinline__ double merge_slots(const SlotView &sv, int G, bool ee, bool capture, long long *acc,
+template <int MODE, int P, typename T = double>
+__device__ __forceinline__ T merge_slots(const SlotView &sv, int G, bool ee, bool capture, long long *acc,
                               long long *esc_out, int *flags_out, RedShared &sh, int slot_val)
 {
     *esc_out = 0;
-    double r;
+    T r;
     if constexpr (MODE == MODE_PLAIN) {
         // fixed order: wavefront 0 sums the slots lane-strided, then the tree
         if (wave_id() == 0) {
@@ -386,7 +434,7 @@ __device__ __forceinline__ double merge_slots(const SlotView &sv, int G, bool ee
             if (lane_id() == 0) sh.val[slot_val] = t;
         }
         __syncthreads();
-        r = sh.val[slot_val];
+        r = (T)sh.val[slot_val];
         __syncthreads();
         return r;
     } else {
@@ -441,11 +489,11 @@ __device__ __forceinline__ double merge_slots(const SlotView &sv, int G, bool ee
         }
         if (flags) atomicOr(flags_out, flags);
         if (wave_id() == 0) {
-            double v = wave_acc_round(acc);
-            if (lane_id() == 0) sh.val[slot_val] = v;
+            T v = wave_acc_round<T>(acc);
+            if (lane_id() == 0) sh.val[slot_val] = (double)v;
         }
         __syncthreads();
-        r = sh.val[slot_val];
+        r = (T)sh.val[slot_val];
         __syncthreads();
         return r;
     }

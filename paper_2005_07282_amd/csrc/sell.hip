@@ -104,11 +104,14 @@ __global__ void __launch_bounds__(1024) k_sell_scan(long long *off, int nslices)
 // the row itself, or row n-1 for the lanes past the last row), then every
 // CSR entry e of the slice goes to position off[s] + 64 k + j, where j is its
 // row in the slice and k its rank in the row. Columns are stored as 32-bit
-// indices, or (scol16) as 16-bit offsets from min(row, n-1).
+// indices, or (scol16) as 16-bit offsets from min(row, n-1). Values (type
+// TIN) are written as binary64 to sval64 and rounded to nearest binary32 into
+// sval32, for whichever of the two is non-null.
+template <typename TIN>
 __global__ void k_sell_fill(int n, int nslices, const int *__restrict__ rp, const int *__restrict__ col,
-                            const double *__restrict__ val, const long long *__restrict__ off,
-                            double *__restrict__ sval, int *__restrict__ scol, short *__restrict__ scol16,
-                            unsigned char *__restrict__ len8)
+                            const TIN *__restrict__ val, const long long *__restrict__ off,
+                            double *__restrict__ sval64, float *__restrict__ sval32, int *__restrict__ scol,
+                            short *__restrict__ scol16, unsigned char *__restrict__ len8)
 {
     const int lane = lane_of();
     const long long s = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -124,7 +127,8 @@ __global__ void k_sell_fill(int n, int nslices, const int *__restrict__ rp, cons
     if (len8 && row) len8[i] = (unsigned char)len;
     for (int k = len; k < width; ++k) {
         const long long p = base + 64ll * k + lane;
-        sval[p] = 0.0;
+        if (sval64) sval64[p] = 0.0;
+        if (sval32) sval32[p] = 0.0f;
         if (scol16) scol16[p] = 0;
         else scol[p] = rbase;
     }
@@ -138,7 +142,9 @@ __global__ void k_sell_fill(int n, int nslices, const int *__restrict__ rp, cons
             const int k = (int)(e - ar);
             const long long p = base + 64ll * k + r;
             const int c = col[e];
-            sval[p] = val[e];
+            const double v = (double)val[e]; // exact for either input type
+            if (sval64) sval64[p] = v;
+            if (sval32) sval32[p] = (float)v;
             if (scol16) scol16[p] = (short)(c - (int)(s * 64 + r));
             else scol[p] = c;
         }
@@ -164,14 +170,20 @@ hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val,
-                            const long long *off, double *sval, int *scol, short *scol16, unsigned char *len8,
-                            hipStream_t s)
+hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val64_in,
+                            const float *val32_in, const long long *off, double *sval64, float *sval32, int *scol,
+                            short *scol16, unsigned char *len8, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    if ((val64_in == nullptr) == (val32_in == nullptr)) return hipErrorInvalidValue;
     const int nslices = (n + 63) / 64;
-    hipLaunchKernelGGL(k_sell_fill, dim3((nslices + 3) / 4), dim3(256), 0, s, n, nslices, row_ptr, col, val,
-                       off, sval, scol, scol16, len8);
+    const dim3 grid((nslices + 3) / 4), block(256);
+    if (val64_in)
+        hipLaunchKernelGGL(k_sell_fill<double>, grid, block, 0, s, n, nslices, row_ptr, col, val64_in, off, sval64,
+                           sval32, scol, scol16, len8);
+    else
+        hipLaunchKernelGGL(k_sell_fill<float>, grid, block, 0, s, n, nslices, row_ptr, col, val32_in, off, sval64,
+                           sval32, scol, scol16, len8);
     return hipGetLastError();
 }
 

@@ -55,6 +55,21 @@ class _Result(ctypes.Structure):
                 ("grid_size", ctypes.c_int32), ("block_size", ctypes.c_int32)]
 
 
+class _IrOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("rr_history", ctypes.c_void_p), ("inner", _Opts)]
+
+
+class _IrResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("outer", ctypes.c_int32), ("inner_iterations", ctypes.c_int32),
+                ("last_inner_status", ctypes.c_int32), ("rr0", ctypes.c_double), ("rr_final", ctypes.c_double),
+                ("threshold", ctypes.c_double), ("fpe_escapes", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("inner_ms", ctypes.c_double), ("outer_ms", ctypes.c_double),
+                ("k_residual_ms", ctypes.c_double), ("k_spmv_dot_ms", ctypes.c_double),
+                ("k_update_ms", ctypes.c_double), ("k_direction_ms", ctypes.c_double),
+                ("k_launches", ctypes.c_int32), ("pad1", ctypes.c_int32)]
+
+
 _lib = None
 _ctx = {}
 
@@ -83,6 +98,14 @@ def lib():
         L.rpcg_pcg_solve.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_Opts),
                                      ctypes.POINTER(_Result), P]
         L.rpcg_pcg_solve.restype = ctypes.c_int
+        L.rpcg_pcg_solve_f32.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_Opts),
+                                         ctypes.POINTER(_Result), P]
+        L.rpcg_pcg_solve_f32.restype = ctypes.c_int
+        L.rpcg_ir_opts_default.argtypes = [ctypes.POINTER(_IrOpts)]
+        L.rpcg_ir_opts_default.restype = None
+        L.rpcg_ir_solve.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_IrOpts),
+                                    ctypes.POINTER(_IrResult), P]
+        L.rpcg_ir_solve.restype = ctypes.c_int
         L.rpcg_exdot_partial.argtypes = [P, I64, P, P, P, P]
         L.rpcg_exdot_partial.restype = ctypes.c_int
         L.rpcg_acc_round.argtypes = [P, P, P, P]
@@ -93,7 +116,8 @@ def lib():
 
 
 EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot",
-            "rpcg_spmv", "rpcg_pcg_solve", "rpcg_exdot_partial", "rpcg_acc_round"]
+            "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
+            "rpcg_exdot_partial", "rpcg_acc_round"]
 
 
 def status_string(s: int) -> str:
@@ -148,7 +172,8 @@ def _result_dict(r: _Result) -> dict:
 
 @dataclass
 class CSR:
-    """A CSR matrix whose arrays live on the GPU (int32 indices, float64 values)."""
+    """A CSR matrix whose arrays live on the GPU (int32 indices; float64
+    values, or float32 values for the binary32 solver)."""
     n: int
     row_ptr: torch.Tensor
     col_idx: torch.Tensor
@@ -159,15 +184,17 @@ class CSR:
         return int(self.col_idx.numel())
 
     @staticmethod
-    def from_host(A, device="cuda") -> "CSR":
+    def from_host(A, device="cuda", dtype=torch.float64) -> "CSR":
+        """Copy a host CSR to the GPU; dtype=torch.float32 rounds the values
+        to nearest binary32 on the host (a storage conversion)."""
         return CSR(int(A.n), torch.as_tensor(A.row_ptr, dtype=torch.int32).to(device),
                    torch.as_tensor(A.col_idx, dtype=torch.int32).to(device),
-                   torch.as_tensor(A.val, dtype=torch.float64).to(device))
+                   torch.as_tensor(A.val, dtype=torch.float64).to(dtype).to(device))
 
-    def _c(self) -> _Csr:
+    def _c(self, dtype=torch.float64) -> _Csr:
         _check(self.row_ptr, torch.int32, "row_ptr")
         _check(self.col_idx, torch.int32, "col_idx")
-        _check(self.val, torch.float64, "val")
+        _check(self.val, dtype, "val")
         if self.row_ptr.numel() != self.n + 1 or self.val.numel() != self.col_idx.numel():
             raise ValueError("inconsistent CSR sizes")
         return _Csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.val.data_ptr())
@@ -253,4 +280,69 @@ def pcg_solve(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str
         info["hist"] = hist[: r.iterations + 1].cpu()
     if rc < 0 and raise_on_error:
         raise RpcgError(rc, "rpcg_pcg_solve")
+    return x, info
+
+
+def pcg_solve_f32(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str = "exblas",
+                  history: bool = True, raise_on_error: bool = True, **opts):
+    """Jacobi-PCG in binary32 (A.val float32, b float32). Returns (x, info);
+    info['hist'] holds tau^(0..L) widened to float64 when history=True."""
+    _check(b, torch.float32, "b")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    _check(x, torch.float32, "x")
+    o = _opts(**opts)
+    hist = None
+    if history and o.tau_history is None:
+        hist = torch.zeros(o.maxit + 1, dtype=torch.float64, device=b.device)
+        o.tau_history = hist.data_ptr()
+    c = A._c(torch.float32)
+    r = _Result()
+    rc = lib().rpcg_pcg_solve_f32(context(b.device.index), MODES[mode], ctypes.byref(c), b.data_ptr(),
+                                  x.data_ptr(), ctypes.byref(o), ctypes.byref(r), _stream(b.device))
+    info = _result_dict(r)
+    info["status"] = rc
+    if hist is not None:
+        info["hist"] = hist[: r.iterations + 1].cpu()
+    if rc < 0 and raise_on_error:
+        raise RpcgError(rc, "rpcg_pcg_solve_f32")
+    return x, info
+
+
+def ir_solve(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str = "exblas",
+             tol: float = 1e-10, maxit: int = 50, tol_inner: float = 1e-4, maxit_inner: int = 2000,
+             history: bool = True, raise_on_error: bool = True, **inner):
+    """Mixed-precision refinement (binary32 inner Jacobi-PCG, binary64 outer
+    residual and update). tol/maxit are the outer ones, tol_inner/maxit_inner
+    those of every inner solve; `inner` takes the other rpcg_opts fields of the
+    inner solves (expansion length, launch shapes, timing). Returns (x, info);
+    info['rr_hist'] holds <r,r> of every outer step when history=True."""
+    _check(b, torch.float64, "b")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    _check(x, torch.float64, "x")
+    o = _IrOpts()
+    lib().rpcg_ir_opts_default(ctypes.byref(o))
+    o.tol = tol
+    o.maxit = maxit
+    o.inner.tol = tol_inner
+    o.inner.maxit = maxit_inner
+    for k, v in inner.items():
+        if v is None:
+            continue
+        if k in ("tau_history", "tol", "maxit") or not hasattr(o.inner, k):
+            raise TypeError(f"unknown inner option {k}")
+        setattr(o.inner, k, v)
+    hist = None
+    if history:
+        hist = torch.zeros(maxit + 1, dtype=torch.float64, device=b.device)
+        o.rr_history = hist.data_ptr()
+    c = A._c()
+    r = _IrResult()
+    rc = lib().rpcg_ir_solve(context(b.device.index), MODES[mode], ctypes.byref(c), b.data_ptr(), x.data_ptr(),
+                             ctypes.byref(o), ctypes.byref(r), _stream(b.device))
+    info = {f: getattr(r, f) for f, _ in _IrResult._fields_ if not f.startswith("pad")}
+    info["status"] = rc
+    if hist is not None:
+        info["rr_hist"] = hist[: r.outer + 1].cpu()
+    if rc < 0 and raise_on_error:
+        raise RpcgError(rc, "rpcg_ir_solve")
     return x, info

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "rpcg.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(rpcg_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(rpcg_[a-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -29,7 +29,8 @@ def L():
 def test_header_lists_the_entry_points():
     names = _declared()
     for n in ("rpcg_exdot", "rpcg_spmv", "rpcg_pcg_solve", "rpcg_create", "rpcg_destroy",
-              "rpcg_exdot_partial", "rpcg_acc_round", "rpcg_opts_default", "rpcg_status_string"):
+              "rpcg_exdot_partial", "rpcg_acc_round", "rpcg_opts_default", "rpcg_status_string",
+              "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve"):
         assert n in names
 
 
@@ -54,12 +55,33 @@ def test_opts_default_and_status_strings(L):
     assert rpcg.status_string(99) == "unknown status"
 
 
-def test_struct_layout_matches_header():
-    """Field order and sizes of the ctypes mirrors agree with the C structs."""
+def test_struct_layout_matches_header(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what a C
+    compiler makes of include/rpcg.h."""
+    import subprocess
     from paper_2005_07282_amd import rpcg
-    assert ctypes.sizeof(rpcg._Csr) == 32
-    assert ctypes.sizeof(rpcg._Opts) == 64
-    assert rpcg._Result.iterations.offset == 4 and rpcg._Result.tau0.offset == 8
+    mirrors = {"rpcg_csr": rpcg._Csr, "rpcg_csr_f32": rpcg._Csr, "rpcg_opts": rpcg._Opts,
+               "rpcg_result": rpcg._Result, "rpcg_ir_opts": rpcg._IrOpts, "rpcg_ir_result": rpcg._IrResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rpcg.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, field, v = line.split()
+            got[(cname, field)] = int(v)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def test_null_arguments_rejected_without_gpu(L):
@@ -69,4 +91,14 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.rpcg_spmv(None, None, None, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_pcg_solve(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_acc_round(None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_pcg_solve_f32(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_ir_solve(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
     L.rpcg_destroy(None)
+
+
+def test_ir_opts_default(L):
+    from paper_2005_07282_amd import rpcg
+    o = rpcg._IrOpts()
+    L.rpcg_ir_opts_default(ctypes.byref(o))
+    assert o.tol == 1e-10 and o.maxit == 50 and o.rr_history is None
+    assert o.inner.tol == 1e-4 and o.inner.maxit == 2000 and o.inner.fpe_fallback == 1

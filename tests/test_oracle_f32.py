@@ -147,3 +147,23 @@ def test_ir_first_step_is_the_f32_solve(orc):
     s = orc.ir_scale(rr)
     inner = orc.pcg_f32(A, np.ldexp(b, -s).astype(np.float32), tol=1e-4)
     assert np.array_equal(res["x"], np.ldexp(inner["x"].astype(np.float64), s))
+
+
+def test_ir_outer_residual_uses_binary64_values(orc):
+    """Values not representable in binary32 (a stencil scaled by 1/3 and an
+    SPD shift): the inner solves see the binary32 rounding of A, but the outer
+    residual is formed with A itself, so the refinement still drives the true
+    binary64 residual below 1e-12; a solve of the rounded system alone would
+    stall near binary32's relative precision (~1e-8)."""
+    N = 8
+    A0 = stencil27_csr(N)
+    val = A0.val / 3.0 + np.where(A0.val > 0, 0.1, 0.0)
+    A = CSRHost(A0.n, A0.row_ptr, A0.col_idx, val)
+    assert np.any(val.astype(np.float32).astype(np.float64) != val)
+    b = orc.spmv(A, np.linspace(-1, 1, A.n))
+    res = orc.ir(A, b, tol=1e-12, tol_in=1e-4)
+    assert res["status"] == 0
+    assert orc.relres_true(A, b, res["x"]) <= 1e-12
+    A32 = CSRHost(A.n, A.row_ptr, A.col_idx, val.astype(np.float32).astype(np.float64))
+    x32 = orc.pcg(A32, b, tol=1e-14, maxit=5000)["x"]
+    assert orc.relres_true(A, b, x32) > 1e-10
