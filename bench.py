@@ -67,6 +67,86 @@ def iteration_bytes(n, nnz):
     return k1_bytes(n, nnz) + 64 * n + 24 * n
 
 
+def run_mixed_precision(N, rpcg, torch, dev):
+    """Mixed-precision refinement on the 27-point operator of an N^3 grid
+    (binary32 inner Jacobi-PCG to 1e-4 with exact binary32 dots, binary64
+    exact residual and update, to 1e-10 relative residual) against plain and
+    exact-dot binary64 PCG to the same tolerance, every solve end to end."""
+    import numpy as np
+    from rpcg_workloads import stencil27_csr, stencil27_rhs_from_int52, uniform_pm1_int52
+    log(f"[bench] mixed precision: generating 27-point operator on {N}^3")
+    A = stencil27_csr(N)
+    K = uniform_pm1_int52(2, A.n)
+    b = stencil27_rhs_from_int52(N, K)
+    xs = K * 2.0 ** -52
+    del K
+    n, nnz = A.n, A.nnz
+    Ad = rpcg.CSR.from_host(A, dev)
+    bd = torch.from_numpy(b).to(dev)
+    del A
+    tol = 1e-10
+
+    def true_rr(x):
+        # exact <r,r> of r = b - A x (rows summed exactly): a refinement call with no correction step
+        _, i = rpcg.ir_solve(Ad, bd, x, tol=tol, maxit=0, history=False, raise_on_error=False)
+        return i["rr0"]
+
+    bb = float(rpcg.exdot(bd, bd)[0].item())
+    log("[bench] mixed precision: warmup")
+    rpcg.ir_solve(Ad, bd, tol=tol, maxit=1, maxit_inner=5, history=False, raise_on_error=False)
+    rpcg.pcg_solve(Ad, bd, mode="plain", tol=tol, maxit=5, history=False, raise_on_error=False)
+    out = {"workload": f"27-point Poisson {N}^3 (n={n}, nnz={nnz}), b = A x*, x* ~ U[-1,1) seed 2, x0 = 0, "
+                       f"relative residual 1e-10",
+           "inner": "binary32 Jacobi-PCG, exact binary32 dots (exblas), tol 1e-4"}
+    sol = {}
+    for mode in ("plain", "exblas"):
+        log(f"[bench] mixed precision: binary64 {mode} PCG to {tol}")
+        torch.cuda.synchronize()
+        x, info = rpcg.pcg_solve(Ad, bd, mode=mode, tol=tol, maxit=6000, history=False, timing=1)
+        torch.cuda.synchronize()
+        sol[mode] = x
+        ms = info["setup_ms"] + info["loop_ms"]
+        out[f"fp64_{mode}"] = {"iterations": info["iterations"], "solve_ms": round(ms, 2),
+                               "setup_ms": round(info["setup_ms"], 2),
+                               "ms_per_iteration": round(info["loop_ms"] / max(1, info["iterations"]), 5),
+                               "k_spmv_dot_ms": round(info["k_spmv_dot_ms"] / max(1, info["k_launches"]), 5),
+                               "true_relres": float(np.sqrt(true_rr(x) / bb))}
+        log(f"[bench]   {info['iterations']} it, {ms:.1f} ms")
+    log("[bench] mixed precision: refinement")
+    torch.cuda.synchronize()
+    x, info = rpcg.ir_solve(Ad, bd, mode="exblas", tol=tol, tol_inner=1e-4, history=True)
+    torch.cuda.synchronize()
+    _, it = rpcg.ir_solve(Ad, bd, mode="exblas", tol=tol, tol_inner=1e-4, history=False, timing=1)
+    xe = sol["exblas"]
+    scale = float(xe.abs().max())
+    xs_d = torch.from_numpy(xs).to(dev)
+    inner_it = max(1, it["k_launches"])
+    k1_32 = it["k_spmv_dot_ms"] / inner_it
+    k1_32_bytes = 8 * nnz + 4 * (n + 1) + 8 * n  # CSR with binary32 values: val + col, row pointers, d, w
+    out["refinement"] = {
+        "outer": info["outer"], "inner_iterations": info["inner_iterations"],
+        "solve_ms": round(info["total_ms"], 2), "setup_ms": round(info["setup_ms"], 2),
+        "inner_ms": round(info["inner_ms"], 2), "outer_ms": round(info["outer_ms"], 2),
+        "rr_history": [float(v) for v in info["rr_hist"].tolist()],
+        "true_relres": float(np.sqrt(info["rr_final"] / bb)),
+        "max_rel_diff_vs_fp64_exblas": float((x - xe).abs().max()) / scale,
+        "max_abs_err_vs_x_star": float((x - xs_d).abs().max()),
+        "inner_ms_per_iteration": round((it["k_spmv_dot_ms"] + it["k_update_ms"] + it["k_direction_ms"])
+                                        / inner_it, 5),
+        "inner_k_spmv_dot_ms": round(k1_32, 5),
+        "inner_k_spmv_dot_GB_s": round(k1_32_bytes / (k1_32 * 1e-3) / 1e9, 1),
+        "k_residual_ms_per_step": round(it["k_residual_ms"] / max(1, it["outer"] + 1), 4),
+    }
+    out["fp64_exblas"]["max_abs_err_vs_x_star"] = float((xe - xs_d).abs().max())
+    out["speedup_vs_fp64_plain"] = round(out["fp64_plain"]["solve_ms"] / info["total_ms"], 3)
+    out["speedup_vs_fp64_exblas"] = round(out["fp64_exblas"]["solve_ms"] / info["total_ms"], 3)
+    log(f"[bench]   refinement: {info['outer']} outer, {info['inner_iterations']} inner, "
+        f"{info['total_ms']:.1f} ms; speedup vs plain fp64 {out['speedup_vs_fp64_plain']}")
+    del Ad, bd, sol, x, xe, xs_d
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +157,8 @@ def main():
     ap.add_argument("--exdot-reps", type=int, default=20)
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ir-grid", type=int, default=256,
+                    help="N of the N^3 grid of the mixed-precision refinement section (0 = skip)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for hardware counters: a few exblas iterations on the N^3 operator "
                          "and a 1 GiB device-to-device copy of known size (counter calibration)")
@@ -212,6 +294,8 @@ def main():
                          f"{os.cpu_count()} host cores visible"}
         log(f"[bench]   oracle {cpu['value']} it/s")
 
+    mixed = run_mixed_precision(args.ir_grid, rpcg, torch, dev) if args.ir_grid > 0 else None
+
     traffic = k1_traffic() if N == 160 else None
     line = {
         "metric": METRIC,
@@ -240,6 +324,7 @@ def main():
                           "direction": round(k3_ms, 5)},
             "exdot_n": ne,
             "exdot": exd,
+            "mixed_precision": mixed,
         },
         "roofline": {
             "bound": "hbm",
