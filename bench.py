@@ -34,7 +34,7 @@ def k1_bytes(n, nnz):
     return 12 * nnz + 4 * (n + 1) + 16 * n
 
 
-K1_SOURCES = ("pcg_spmv_dot.hip", "reduce.hpp", "numerics.hpp", "kernels.hpp")
+K1_SOURCES = ("pcg_spmv_dot.hip", "sell_spmv.hpp", "reduce.hpp", "numerics.hpp", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_160cube_hbm_traffic.md")
 
 
@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ir-grid", type=int, default=256,
                     help="N of the N^3 grid of the mixed-precision refinement section (0 = skip)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="run only the mixed-precision section and print its JSON (for a separate kernel trace)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="short run for hardware counters: a few exblas iterations on the N^3 operator "
                          "and a 1 GiB device-to-device copy of known size (counter calibration)")
@@ -181,6 +183,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     rpcg.context(0)
+    if args.mixed_only:
+        print(json.dumps(run_mixed_precision(args.ir_grid, rpcg, torch, dev)), flush=True)
+        return
 
     N = args.grid
     log(f"[bench] generating 27-point operator on {N}^3")
@@ -333,7 +338,7 @@ def main():
             "unit": "GB/s",
             "frac": round(k1_gbs / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_pcg_spmv_dot<exblas,4>",
+            "kernel": "k_pcg_spmv_dot<exblas, 3, 16-bit column codes, binary64>",
             "bytes_per_launch": k1_bytes(n, nnz),
         },
         "cpu_baseline": cpu,

@@ -49,7 +49,7 @@ struct rpcg_ctx {
     DotInfo *info = nullptr;
     PcgState *st = nullptr;
     IrState *ist = nullptr;
-    Buffer sell_off, sell_val, sell_val32, sell_col, sell_len;
+    Buffer sell_off, sell_val, sell_val32, sell_col, sell_cfirst, sell_len;
     Buffer vecs;              // r, z, d, w, dinv of the solver
     Buffer ir_vecs;           // refinement: r (binary64), rf and c (binary32)
     Buffer beta_hist;         // beta of every iteration
@@ -143,14 +143,18 @@ static LaunchCfg make_vec_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long n
     return cfg;
 }
 
-// SpMV kernel: one wavefront per 64-row slice at a time; own overrides.
-static LaunchCfg make_spmv_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long nslices, hipStream_t s)
+// SpMV kernel: one wavefront per 64-row slice at a time; own overrides. The
+// binary32 kernel keeps fewer bytes in flight per wavefront and wants twice
+// the workgroups of the binary64 one.
+static LaunchCfg make_spmv_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long nslices, hipStream_t s,
+                               bool f32 = false)
 {
     rpcg_opts q = o;
     q.block_size = o.spmv_block_size;
     q.grid_size = o.spmv_grid_size;
     LaunchCfg cfg = make_cfg(c, q, std::max(1ll, nslices * 64), 256, s);
-    if (!q.grid_size) cfg.grid = (int)std::max(1ll, std::min((nslices * 64 + cfg.block - 1) / cfg.block, 2ll * c->num_cus));
+    const long long cap = (f32 ? 4ll : 2ll) * c->num_cus;
+    if (!q.grid_size) cfg.grid = (int)std::max(1ll, std::min((nslices * 64 + cfg.block - 1) / cfg.block, cap));
     return cfg;
 }
 
@@ -226,6 +230,7 @@ void rpcg_destroy(rpcg_ctx *c)
     c->sell_val.release();
     c->sell_val32.release();
     c->sell_col.release();
+    c->sell_cfirst.release();
     c->sell_len.release();
     c->vecs.release();
     c->ir_vecs.release();
@@ -344,23 +349,28 @@ struct SellBuilt {
     const double *val64 = nullptr; // binary64 values, if requested
     const float *val32 = nullptr;  // binary32 values, if requested
     const int *col = nullptr;
-    const short *col16p = nullptr;
+    const unsigned short *col16p = nullptr;
+    const int *cfirst = nullptr;
     const unsigned char *len8 = nullptr;
 };
 
 // One pass over the CSR checks its structure and measures the slices
 // (nothing indexes through the matrix before the check has passed), then the
 // copy is filled. Source values: v64 or v32; kept as binary64 (out64) and/or
-// rounded to binary32 (out32). Waits for the stream.
+// rounded to binary32 (out32). The interleave is that of the solver's value
+// type: two entries for a binary64-only copy, one when binary32 values are
+// kept. Waits for the stream.
 static int build_sell(rpcg_ctx *c, int n, int nnz, const int *rp, const int *col, const double *v64,
                       const float *v32, bool out64, bool out32, bool no_col16, hipStream_t s, SellBuilt *out)
 {
     const int nslices = (n + 63) / 64;
+    const int vec = out32 ? sell_vec<float>() : sell_vec<double>();
     RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
     RPCG_TRY(c->sell_off.ensure(sizeof(long long) * (nslices + 1)));
     long long *off = (long long *)c->sell_off.p;
     RPCG_TRY(hipMemsetAsync(off, 0, sizeof(long long) * (nslices + 1), s));
-    RPCG_TRY(launch_csr_scan(n, nnz, rp, col, off + 1, &c->info->flags, &c->info->max_len, &c->info->max_delta, s));
+    RPCG_TRY(launch_csr_scan(n, nnz, rp, col, vec, off + 1, &c->info->flags, &c->info->max_len,
+                             &c->info->max_delta, s));
     RPCG_TRY(launch_sell_scan(off, nslices, s));
     long long padded = 0;
     DotInfo scan_info;
@@ -375,20 +385,26 @@ static int build_sell(rpcg_ctx *c, int n, int nnz, const int *rp, const int *col
     if (out64) { RPCG_TRY(c->sell_val.ensure(sizeof(double) * np)); s64 = (double *)c->sell_val.p; }
     if (out32) { RPCG_TRY(c->sell_val32.ensure(sizeof(float) * np)); s32 = (float *)c->sell_val32.p; }
     RPCG_TRY(c->sell_col.ensure((col16 ? sizeof(short) : sizeof(int)) * np));
+    int *cfirst = nullptr;
+    if (col16) {
+        RPCG_TRY(c->sell_cfirst.ensure(sizeof(int) * (size_t)std::max(1, nslices)));
+        cfirst = (int *)c->sell_cfirst.p;
+    }
     unsigned char *len8 = nullptr;
     if (scan_info.max_len < 256) {
         RPCG_TRY(c->sell_len.ensure((size_t)std::max(1, n)));
         len8 = (unsigned char *)c->sell_len.p;
     }
-    RPCG_TRY(launch_sell_fill(n, rp, col, v64, v32, off, s64, s32, col16 ? nullptr : (int *)c->sell_col.p,
-                              col16 ? (short *)c->sell_col.p : nullptr, len8, s));
+    RPCG_TRY(launch_sell_fill(n, rp, col, v64, v32, vec, off, s64, s32, col16 ? nullptr : (int *)c->sell_col.p,
+                              col16 ? (unsigned short *)c->sell_col.p : nullptr, cfirst, len8, s));
     out->nslices = nslices;
     out->col16 = col16;
     out->off = off;
     out->val64 = s64;
     out->val32 = s32;
     out->col = col16 ? nullptr : (const int *)c->sell_col.p;
-    out->col16p = col16 ? (const short *)c->sell_col.p : nullptr;
+    out->col16p = col16 ? (const unsigned short *)c->sell_col.p : nullptr;
+    out->cfirst = cfirst;
     out->len8 = len8;
     return RPCG_OK;
 }
@@ -403,6 +419,7 @@ static SellMat<T> sell_mat(const SellBuilt &B, const T *val, int n, const int *r
     M.val = val;
     M.col = B.col;
     M.col16 = B.col16p;
+    M.cfirst = B.cfirst;
     M.row_ptr = row_ptr;
     M.len8 = B.len8;
     M.val64 = B.val64;
@@ -549,11 +566,11 @@ static int pcg_solve_any(rpcg_ctx *c, int mode, int n, int nnz, const int *rp, c
     hipStream_t s = (hipStream_t)stream;
     auto t0 = std::chrono::steady_clock::now();
     const int nslices = (n + 63) / 64;
+    constexpr bool F32 = std::is_same<T, float>::value;
     LaunchCfg cfg_rows = make_vec_cfg(c, o, std::max(1, n), s);
-    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s);
+    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s, F32);
     int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
     if (rc != RPCG_OK) return rc;
-    constexpr bool F32 = std::is_same<T, float>::value;
     SellBuilt B;
     rc = build_sell(c, n, nnz, rp, col, v64, v32, !F32, F32, o.no_col16 != 0, s, &B);
     if (rc != RPCG_OK) return rc;
@@ -628,7 +645,7 @@ static int ir_body(rpcg_ctx *c, int mode, const rpcg_csr *A, const double *b, do
     o.fpe_size = resolve_fpe_size(o.fpe_size, mode);
     const int nslices = (n + 63) / 64;
     LaunchCfg cfg_rows = make_vec_cfg(c, o, std::max(1, n), s);
-    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s);
+    LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s, true);
     LaunchCfg cfg_res = make_res_cfg(c, nslices, s);
     rpcg_opts dflt;
     rpcg_opts_default(&dflt);

@@ -16,6 +16,7 @@ constexpr int IR_BLOCK = 128;            // two wavefronts
 constexpr int IR_WAVES = IR_BLOCK / 64;
 constexpr int RES_FPE = 4;                // expansion length of the row sums
 constexpr int IR_DOT_P = 3;               // expansion length of <r, r>
+constexpr int RES_BATCH = 9;              // row entries loaded together
 
 // Each lane sums its row into an expansion (TwoSum, nothing lost: what does
 // not fit goes into the lane's own long accumulator in LDS), then adds the
@@ -51,8 +52,9 @@ k_ir_residual(SellMat<float> A, const double *__restrict__ b, const double *__re
         const int width = __builtin_amdgcn_readfirstlane((int)((A.off[s + 1] - base) >> 6));
         const long long i = s * 64 + lane;
         const int len = sell_len(A, i);
-        const int rbase = i < A.n ? (int)i : A.n - 1;
-        const long long kb = base + lane;
+        const long long p0 = base + lane; // binary32 layout: no interleave
+        int first = 0, cur = 0;
+        if constexpr (COL16) first = (i < A.n ? (int)i : A.n - 1) + A.cfirst[s];
         double e[RES_FPE];
 #pragma unroll
         for (int j = 0; j < RES_FPE; ++j) e[j] = 0.0;
@@ -61,23 +63,30 @@ k_ir_residual(SellMat<float> A, const double *__restrict__ b, const double *__re
             if (!is_finite_bits(bi)) flags |= FLAG_NONFINITE;
             put(e, bi);
         }
-        for (int k0 = 0; k0 < width; k0 += SPMV_BATCH) {
-            int c[SPMV_BATCH];
-            double a[SPMV_BATCH], g[SPMV_BATCH];
+        for (int k0 = 0; k0 < width; k0 += RES_BATCH) {
+            int c[RES_BATCH];
+            double a[RES_BATCH], g[RES_BATCH];
 #pragma unroll
-            for (int u = 0; u < SPMV_BATCH; ++u) {
+            for (int u = 0; u < RES_BATCH; ++u) {
+                // positions past the width repeat the last entry (its column decodes unchanged: code 0)
                 const int k = min(k0 + u, width - 1);
-                c[u] = sell_col<COL16>(A, kb + 64ll * k, rbase);
+                if constexpr (COL16) {
+                    const unsigned code = k0 + u < width ? __builtin_nontemporal_load(&A.col16[p0 + 64ll * k]) : 0u;
+                    cur = (k0 + u == 0) ? first + (int)(short)code : cur + (int)code;
+                    c[u] = cur;
+                } else {
+                    c[u] = __builtin_nontemporal_load(&A.col[p0 + 64ll * k]);
+                }
             }
 #pragma unroll
-            for (int u = 0; u < SPMV_BATCH; ++u) {
+            for (int u = 0; u < RES_BATCH; ++u) {
                 const int k = min(k0 + u, width - 1);
-                a[u] = __builtin_nontemporal_load(&A.val64[kb + 64ll * k]);
+                a[u] = __builtin_nontemporal_load(&A.val64[p0 + 64ll * k]);
             }
 #pragma unroll
-            for (int u = 0; u < SPMV_BATCH; ++u) g[u] = x[c[u]];
+            for (int u = 0; u < RES_BATCH; ++u) g[u] = x[c[u]];
 #pragma unroll
-            for (int u = 0; u < SPMV_BATCH; ++u) {
+            for (int u = 0; u < RES_BATCH; ++u) {
                 if (k0 + u < len) {
                     double ph, pl;
                     two_prod(-a[u], g[u], ph, pl);
@@ -171,7 +180,7 @@ __global__ void k_ir_update(int n, double *__restrict__ x, const float *__restri
 hipError_t launch_ir_residual(const SellMat<float> &A, const double *b, const double *x, double *r, IrState *ist,
                               const DotWs &ws, int stride, const LaunchCfg &c)
 {
-    if (!A.val64) return hipErrorInvalidValue;
+    if (!A.val64 || sell_vec<float>() != 1) return hipErrorInvalidValue;
     SlotView sv{ws, stride};
     if (A.col16) k_ir_residual<true><<<c.grid, IR_BLOCK, 0, c.stream>>>(A, b, x, r, ist, sv);
     else k_ir_residual<false><<<c.grid, IR_BLOCK, 0, c.stream>>>(A, b, x, r, ist, sv);

@@ -34,8 +34,9 @@ struct DotWs {
 struct DotInfo {
     unsigned pad0;
     int flags;
-    int max_len;   // longest row (SELL construction scratch)
-    int max_delta; // largest |column - row| (SELL construction scratch)
+    int max_len;         // longest row (SELL construction scratch)
+    int pad1;
+    long long max_delta; // column-code range (SELL construction scratch)
     long long escapes;
     long long fallbacks;
 };
@@ -62,14 +63,33 @@ struct PcgState {
     long long fallbacks;
 };
 
-// Sliced-ELL copy of the matrix with slice height 64 (one wavefront): entry
-// k of row 64*s + j sits at off[s] + 64*k + j, so lane j of a wavefront
-// walks its row while each load of the wavefront is one contiguous 512-byte
-// (binary64 values), 256-byte (binary32 values or 32-bit columns) or
-// 128-byte (16-bit columns) segment. Rows keep their CSR order and length;
-// padding entries hold the value 0 and a valid column. T is the type the
-// solver computes in; val64 optionally holds the caller's binary64 values in
-// the same layout (used by the refinement's residual next to binary32 val).
+// Sliced-ELL copy of the matrix with slice height 64 (one wavefront) and
+// V-entry interleave: entry k of row 64*s + j sits at
+//     off[s] + 64*V*(k/V) + V*j + (k%V),
+// so lane j reads V consecutive entries of its row with one vector load while
+// each load of the wavefront is one contiguous segment. Slice widths are
+// multiples of V; rows keep their CSR order and length; padding entries hold
+// the value 0 and a valid column. T is the type the solver computes in and V
+// = sell_vec<T>() (two for binary64: 16-byte loads; one for binary32).
+//
+// Columns: with col16 (16-bit column codes), the column of rank 0 of row
+// i = 64 s + j is min(i, n-1) + cfirst[s] + (signed) code, and the column of
+// rank k >= 1 is the column of rank k-1 plus the (unsigned) code: rows keep
+// ascending columns in 16-bit steps and cfirst[s] is the first-column offset
+// of the slice's longest row. Padding codes are 0 (the column repeats), and
+// rows without entries get a rank-0 code that lands on a valid column.
+// Otherwise col holds the columns as 32-bit indices. val64 optionally holds
+// the caller's binary64 values in the same layout (used by the refinement's
+// residual next to binary32 val).
+#ifndef RPCG_SELL_VEC64
+#define RPCG_SELL_VEC64 2
+#endif
+template <typename T>
+__host__ __device__ constexpr int sell_vec()
+{
+    return sizeof(T) == 8 ? RPCG_SELL_VEC64 : 1;
+}
+
 template <typename T>
 struct SellMat {
     int n;
@@ -79,7 +99,8 @@ struct SellMat {
     const int *col;
     const int *row_ptr;   // the caller's CSR row pointers (row lengths)
     const unsigned char *len8; // row lengths as bytes when every row has < 256 entries, else null
-    const short *col16;   // when non-null: columns as col - min(row, n-1) in 16 bits (col unused)
+    const unsigned short *col16; // when non-null: column codes (col unused)
+    const int *cfirst;    // with col16: [nslices] first-column offset of each slice
     const double *val64;  // optional binary64 values (same layout), else null
 };
 
@@ -104,10 +125,12 @@ hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s)
 hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
                            const double *x, double *y, hipStream_t s);
 
-// CSR structural check (*bad set if malformed), slice widths (off_plus1),
-// longest row and largest |column - row|, one wavefront per 64-row slice.
-hipError_t launch_csr_scan(int n, int nnz, const int *row_ptr, const int *col, long long *off_plus1, int *bad,
-                           int *max_len, int *max_delta, hipStream_t s);
+// CSR structural check (*bad set if malformed), slice widths rounded up to a
+// multiple of vec (off_plus1), longest row, and the range of the 16-bit column
+// codes (*max_delta <= 32767 iff every code fits), one wavefront per 64-row
+// slice.
+hipError_t launch_csr_scan(int n, int nnz, const int *row_ptr, const int *col, int vec, long long *off_plus1,
+                           int *bad, int *max_len, long long *max_delta, hipStream_t s);
 
 hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
 // Fill the sliced-ELL arrays from the CSR. The source values are binary64
@@ -115,8 +138,8 @@ hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
 // receives them as binary64, sval32 rounded to nearest binary32; either
 // output may be null.
 hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val64_in,
-                            const float *val32_in, const long long *off, double *sval64, float *sval32, int *scol,
-                            short *scol16, unsigned char *len8, hipStream_t s);
+                            const float *val32_in, int vec, const long long *off, double *sval64, float *sval32,
+                            int *scol, unsigned short *scol16, int *cfirst, unsigned char *len8, hipStream_t s);
 
 template <typename T>
 struct PcgVecs {

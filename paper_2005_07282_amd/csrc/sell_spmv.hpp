@@ -1,16 +1,22 @@
 // Row loop of the sliced-ELL SpMV shared by the solver kernels: lane j of a
 // wavefront computes row 64s+j of A x as a sequential fma chain over the
-// row's stored entries in their original order (Section 4.3).
+// row's stored entries in their original order (Section 4.3). Layout and
+// column encoding are described with SellMat.
 #pragma once
 
 #include "kernels.hpp"
 
 namespace rpcg {
 
-// Entries of one row loaded per batch: loads of a batch are issued together
-// so the wavefront waits for memory once per batch, not once per entry
-// (9 divides the 27 entries of an interior 27-point row).
-constexpr int SPMV_BATCH = 9;
+// Entries of one row loaded per batch: the loads of a batch are issued
+// together so the wavefront waits for memory once per batch, not once per
+// entry (14 = two batches per interior 27-point row padded to 28 with the
+// two-entry interleave; 9 divides the 27 entries without it).
+template <typename T>
+__host__ __device__ constexpr int spmv_batch()
+{
+    return sell_vec<T>() == 2 ? 14 : 9;
+}
 
 __device__ __forceinline__ long long uniform_ll(long long v)
 {
@@ -19,24 +25,52 @@ __device__ __forceinline__ long long uniform_ll(long long v)
     return (long long)(((unsigned long long)hi << 32) | lo);
 }
 
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef int i2_t __attribute__((ext_vector_type(2)));
+
 // The matrix is streamed once per iteration and is far larger than the
 // caches: its loads are marked non-temporal so that they do not evict the
 // gathered vector from L2.
-template <bool COL16, typename T>
-__device__ __forceinline__ int sell_col(const SellMat<T> &A, long long kk, int rbase)
+//
+// One group = the V consecutive entries k = V*g .. V*g+V-1 of this lane's row
+// at element index p (= off[s] + 64*V*g + V*lane). With 16-bit column codes
+// the columns are decoded in rank order from `cur` (the previous column of
+// the row) and `first` (min(i, n-1) + cfirst[s], the origin of rank 0).
+template <typename T, bool COL16>
+__device__ __forceinline__ void sell_group(const SellMat<T> &A, long long p, int k0, int first, int &cur,
+                                           int (&c)[sell_vec<T>()], T (&a)[sell_vec<T>()])
 {
-    if constexpr (COL16) return rbase + (int)__builtin_nontemporal_load(&A.col16[kk]);
-    else return __builtin_nontemporal_load(&A.col[kk]);
+    constexpr int V = sell_vec<T>();
+    unsigned code[V];
+    if constexpr (V == 2) {
+        const d2_t v = __builtin_nontemporal_load((const d2_t *)(A.val + p));
+        a[0] = v.x;
+        a[1] = v.y;
+        if constexpr (COL16) {
+            const unsigned r = __builtin_nontemporal_load((const unsigned *)(A.col16 + p));
+            code[0] = r & 0xFFFFu;
+            code[1] = r >> 16;
+        } else {
+            const i2_t q = __builtin_nontemporal_load((const i2_t *)(A.col + p));
+            c[0] = q.x;
+            c[1] = q.y;
+        }
+    } else {
+        a[0] = __builtin_nontemporal_load(A.val + p);
+        if constexpr (COL16) code[0] = __builtin_nontemporal_load(A.col16 + p);
+        else c[0] = __builtin_nontemporal_load(A.col + p);
+    }
+    if constexpr (COL16) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            cur = (k0 + v == 0) ? first + (int)(short)code[v] : cur + (int)code[v];
+            c[v] = cur;
+        }
+    }
 }
-
-template <typename T>
-__device__ __forceinline__ T sell_val(const T *pv, long long k)
-{
-    return __builtin_nontemporal_load(&pv[k]);
-}
-
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // Row length of row i (0 for lanes past the last row).
 template <typename T>
@@ -57,39 +91,50 @@ template <typename T, bool COL16, bool DIAG>
 __device__ __forceinline__ T sell_row(const SellMat<T> &A, long long base, int width, long long i, int len,
                                       const T *__restrict__ x, T *aii, bool *found)
 {
+    constexpr int V = sell_vec<T>();
+    constexpr int BG = spmv_batch<T>() / V; // groups per batch
     const int lane = (int)(i & 63);
-    const int rbase = i < A.n ? (int)i : A.n - 1;
-    const long long kb = base + lane;
-    const T *__restrict__ pv = A.val + kb;
+    const long long p0 = base + (long long)V * lane;
+    int first = 0, cur = 0;
+    if constexpr (COL16)
+        first = (i < A.n ? (int)i : A.n - 1) + A.cfirst[__builtin_amdgcn_readfirstlane((int)(i >> 6))];
+    const int groups = width / V;
     T sum = T(0);
-    int k0 = 0;
-    for (; k0 + SPMV_BATCH <= width; k0 += SPMV_BATCH) {
-        int c[SPMV_BATCH];
-        T a[SPMV_BATCH], g[SPMV_BATCH];
+    int g0 = 0;
+    for (; g0 + BG <= groups; g0 += BG) {
+        int c[BG][V];
+        T a[BG][V];
 #pragma unroll
-        for (int u = 0; u < SPMV_BATCH; ++u) c[u] = sell_col<COL16>(A, kb + 64 * (k0 + u), rbase);
+        for (int u = 0; u < BG; ++u) sell_group<T, COL16>(A, p0 + 64ll * V * (g0 + u), V * (g0 + u), first, cur, c[u], a[u]);
+        T g[BG][V];
 #pragma unroll
-        for (int u = 0; u < SPMV_BATCH; ++u) a[u] = sell_val(pv, 64 * (k0 + u));
+        for (int u = 0; u < BG; ++u)
 #pragma unroll
-        for (int u = 0; u < SPMV_BATCH; ++u) g[u] = x[c[u]];
+            for (int v = 0; v < V; ++v) g[u][v] = x[c[u][v]];
 #pragma unroll
-        for (int u = 0; u < SPMV_BATCH; ++u) {
-            const bool in = k0 + u < len;
-            const T t = fma_t(a[u], g[u], sum);
+        for (int u = 0; u < BG; ++u)
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const bool in = V * (g0 + u) + v < len;
+                const T t = fma_t(a[u][v], g[u][v], sum);
+                sum = in ? t : sum;
+                if constexpr (DIAG) {
+                    if (in && c[u][v] == (int)i) { *aii = a[u][v]; *found = true; }
+                }
+            }
+    }
+    for (; g0 < groups; ++g0) {
+        int c[V];
+        T a[V];
+        sell_group<T, COL16>(A, p0 + 64ll * V * g0, V * g0, first, cur, c, a);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const bool in = V * g0 + v < len;
+            const T t = fma_t(a[v], x[c[v]], sum);
             sum = in ? t : sum;
             if constexpr (DIAG) {
-                if (in && c[u] == (int)i) { *aii = a[u]; *found = true; }
+                if (in && c[v] == (int)i) { *aii = a[v]; *found = true; }
             }
-        }
-    }
-    for (; k0 < width; ++k0) {
-        const int c = sell_col<COL16>(A, kb + 64 * k0, rbase);
-        const T a = sell_val(pv, 64 * k0);
-        const bool in = k0 < len;
-        const T t = fma_t(a, x[c], sum);
-        sum = in ? t : sum;
-        if constexpr (DIAG) {
-            if (in && c == (int)i) { *aii = a; *found = true; }
         }
     }
     return sum;
