@@ -243,6 +243,78 @@ int rpcg_ir_solve(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr *A /* host struc
                   const double *b, double *x, const rpcg_ir_opts *opts, rpcg_ir_result *res,
                   void *stream);
 
+/* ---- Batched solves ----
+ * Many independent SPD systems solved together (an extension of the paper's
+ * method): one concatenated sliced-ELL copy, one launch per kernel step for
+ * all systems, iterations captured once into a HIP graph and replayed. In
+ * the exact modes every scalar of a system is the rounded exact value of that
+ * system's data alone, so each system's iteration count, tau history and
+ * solution are bit-identical to rpcg_pcg_solve on that system alone, with the
+ * same options, whatever the other systems, their order or the schedule. */
+
+typedef struct rpcg_batch rpcg_batch;
+
+/* Schedule of the streaming kernels: the choice of the autotuner. It changes
+ * speed only, never results. */
+typedef struct {
+    int32_t policy;           /* 0: each workgroup takes one contiguous chunk of the concatenated
+                                 slices (equal stored entries per chunk); 1: tiles of tile_slices
+                                 slices of one system, systems interleaved, dealt round-robin */
+    int32_t tile_slices;      /* policy 1: slices (64 rows each) per tile, >= 1 */
+    int32_t grid_size;        /* workgroups of the streaming kernels, 1..65536 */
+    int32_t block_size;       /* threads per workgroup: 64..1024, multiple of 64 */
+    int32_t graph_iterations; /* iterations captured per graph, 1..64 */
+    int32_t pad0;
+    double ms_per_iteration;  /* set by rpcg_batch_tune: measured time of one iteration of the batch */
+} rpcg_batch_tuning;
+
+/* Aggregate figures of one batched solve (host memory). */
+typedef struct {
+    int32_t status;           /* most severe per-system status: the lowest error if a system
+                                 failed, else the highest warning, else RPCG_OK */
+    int32_t graph_launches;   /* graph replays */
+    int32_t max_iterations;   /* largest per-system iteration count */
+    int32_t pad0;
+    int64_t total_iterations; /* sum of the per-system iteration counts */
+    double setup_ms;          /* wall time: copies in, setup kernels */
+    double loop_ms;           /* wall time of the replays */
+    double total_ms;          /* wall time of the call */
+} rpcg_batch_stats;
+
+/* Prepare a batch of nsys >= 1 systems. A: host array of nsys CSR structs
+ * (device arrays, as for rpcg_pcg_solve, which must stay valid and unchanged
+ * until rpcg_batch_destroy); every row's columns must be valid indices of its
+ * own system. opts (may be NULL): tol, maxit, expansion length and fallback
+ * for every system (launch fields are ignored: the schedule is the tuning).
+ * The structure of every matrix is checked on the device (RPCG_ERR_INVALID);
+ * the tuning is taken from the context's autotuner results for the same
+ * sizes, else the default. *out receives a handle owned by the caller. */
+int rpcg_batch_create(rpcg_ctx *ctx, rpcg_mode mode, int32_t nsys, const rpcg_csr *A /* host array */,
+                      const rpcg_opts *opts, rpcg_batch **out /* host */, void *stream);
+void rpcg_batch_destroy(rpcg_batch *batch);
+
+int rpcg_batch_get_tuning(const rpcg_batch *batch, rpcg_batch_tuning *out /* host */);
+/* Use this schedule from now on (RPCG_ERR_INVALID if a field is out of range). */
+int rpcg_batch_set_tuning(rpcg_batch *batch, const rpcg_batch_tuning *tuning /* host */);
+
+/* Autotuner: times trial_iterations (1..1000) iterations of the batch from
+ * x = 0 on right-hand sides b (host array of nsys device pointers) for each
+ * candidate schedule, keeps the fastest for this batch and records it in the
+ * context for batches of the same sizes. *chosen (may be NULL) receives it. */
+int rpcg_batch_tune(rpcg_batch *batch, const double *const *b /* host array */, int32_t trial_iterations,
+                    rpcg_batch_tuning *chosen /* host */, void *stream);
+
+/* Solve every system: b, x: host arrays of nsys device pointers (n_s
+ * doubles each; x: in x^(0), out: final iterate). tau_history (may be NULL,
+ * entries may be NULL): host array of device pointers to maxit+1 doubles.
+ * res (may be NULL): host array of nsys results (status, iterations, tau0,
+ * tau_final, threshold, escapes; the timing fields hold the batch's).
+ * stats may be NULL. Waits for completion. Returns the most severe
+ * per-system status (as rpcg_batch_stats.status). */
+int rpcg_batch_solve(rpcg_batch *batch, const double *const *b, double *const *x,
+                     double *const *tau_history, rpcg_result *res, rpcg_batch_stats *stats,
+                     void *stream);
+
 /* Long-accumulator interface (Section 4.3, Listing 3: the per-process
  * accumulator that is summed as integers across processes, then rounded).
  * The accumulator is RPCG_ACC_DIGITS signed 64-bit digits; digit k has weight

@@ -12,69 +12,11 @@
 #include <vector>
 
 #include "../../include/rpcg.h"
+#include "context.hpp"
 #include "kernels.hpp"
 
 using namespace rpcg;
-
-namespace {
-
-struct Buffer {
-    void *p = nullptr;
-    size_t bytes = 0;
-    hipError_t ensure(size_t need)
-    {
-        if (need <= bytes) return hipSuccess;
-        if (p) { hipError_t e = hipFree(p); if (e != hipSuccess) return e; p = nullptr; bytes = 0; }
-        hipError_t e = hipMalloc(&p, need);
-        if (e == hipSuccess) bytes = need;
-        return e;
-    }
-    void release()
-    {
-        if (p) hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-};
-
-} // namespace
-
-struct rpcg_ctx {
-    int device = 0;
-    int num_cus = 256;
-    int ws_groups = 0;        // capacity of the dot workspaces, in workgroups
-    Buffer ws_mem;            // 3 dot workspaces
-    DotWs ws[3];
-    Buffer scalars;           // DotInfo + PcgState
-    DotInfo *info = nullptr;
-    PcgState *st = nullptr;
-    IrState *ist = nullptr;
-    Buffer sell_off, sell_val, sell_val32, sell_col, sell_cfirst, sell_len;
-    Buffer vecs;              // r, z, d, w, dinv of the solver
-    Buffer ir_vecs;           // refinement: r (binary64), rf and c (binary32)
-    Buffer beta_hist;         // beta of every iteration
-    int *host_done = nullptr; // pinned: polled flags
-    PcgState *host_state = nullptr;
-    IrState *host_ir = nullptr;
-    std::vector<hipEvent_t> events;
-    std::vector<hipEvent_t> ir_events;
-    hipEvent_t poll_ev[2] = {nullptr, nullptr};
-};
-
-static_assert(sizeof(DotInfo) <= 256 && sizeof(PcgState) <= 256 && sizeof(IrState) <= 256, "scalar layout");
-
-static int hip_status(hipError_t e)
-{
-    if (e == hipSuccess) return RPCG_OK;
-    if (e == hipErrorOutOfMemory) return RPCG_ERR_OOM;
-    return RPCG_ERR_HIP;
-}
-
-#define RPCG_TRY(expr)                                   \
-    do {                                                 \
-        hipError_t _e = (expr);                          \
-        if (_e != hipSuccess) return hip_status(_e);     \
-    } while (0)
+using namespace rpcg_host;
 
 static int ensure_ws(rpcg_ctx *c, int groups)
 {
@@ -97,19 +39,6 @@ static int ensure_ws(rpcg_ctx *c, int groups)
     return RPCG_OK;
 }
 
-static bool valid_opts(const rpcg_opts &o)
-{
-    if (!(o.tol >= 0.0) || o.maxit < 0) return false;
-    if (o.fpe_size < 0 || o.fpe_size > MAX_FPE) return false;
-    if (o.block_size != 0 && (o.block_size < 64 || o.block_size > MAX_BLOCK || o.block_size % 64)) return false;
-    if (o.grid_size < 0 || o.grid_size > 65536) return false;
-    if (o.xcd_parts < 0 || o.xcd_parts > 64) return false;
-    if (o.spmv_block_size != 0 && (o.spmv_block_size < 64 || o.spmv_block_size > MAX_BLOCK || o.spmv_block_size % 64))
-        return false;
-    if (o.spmv_grid_size < 0 || o.spmv_grid_size > 65536) return false;
-    return true;
-}
-
 static LaunchCfg make_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long work_items, int block_default,
                           hipStream_t s)
 {
@@ -124,14 +53,6 @@ static LaunchCfg make_cfg(const rpcg_ctx *c, const rpcg_opts &o, long long work_
     cfg.xcd_parts = o.xcd_parts ? o.xcd_parts : 1;
     cfg.stream = s;
     return cfg;
-}
-
-// Expansion length: 0 = auto. FPE mode: 4. EXBLAS mode: 3 (its results do
-// not depend on the length; 3 was the fastest on the 27-point workload).
-static int resolve_fpe_size(int p, int mode)
-{
-    if (p) return p;
-    return mode == MODE_EXBLAS ? 3 : 4;
 }
 
 // Vector kernels (setup, K2, K3): 512-thread workgroups, at most two per CU,
@@ -306,13 +227,6 @@ int rpcg_acc_round(rpcg_ctx *c, const int64_t *digits, double *out, void *stream
     return RPCG_OK;
 }
 
-static bool valid_csr(const rpcg_csr *A)
-{
-    if (!A || A->n < 0 || A->nnz < 0) return false;
-    if (A->n > 0 && (!A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->val)))) return false;
-    return true;
-}
-
 int rpcg_spmv(rpcg_ctx *c, const rpcg_csr *A, const double *x, double *y, void *stream)
 {
     if (!c || !valid_csr(A) || (A->n > 0 && (!x || !y)) || (A->n > 0 && x == y)) return RPCG_ERR_INVALID;
@@ -325,21 +239,6 @@ int rpcg_spmv(rpcg_ctx *c, const rpcg_csr *A, const double *x, double *y, void *
 
 // events per timed iteration: boundaries around K1 | K2 | K3
 static const int EV_PER_IT = 4;
-
-static int ensure_events(std::vector<hipEvent_t> &evs, size_t need)
-{
-    while (evs.size() < need) {
-        hipEvent_t e;
-        RPCG_TRY(hipEventCreate(&e));
-        evs.push_back(e);
-    }
-    return RPCG_OK;
-}
-
-static double ms_since(std::chrono::steady_clock::time_point t)
-{
-    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t).count();
-}
 
 // The solver's sliced-ELL copy of a CSR matrix (see SellMat).
 struct SellBuilt {

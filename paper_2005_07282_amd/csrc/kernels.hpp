@@ -197,4 +197,60 @@ hipError_t launch_ir_prepare(int k, int maxit, double tol, int n, const double *
 // x = RN(x + c 2^s).
 hipError_t launch_ir_update(int n, double *x, const float *c, const IrState *ist, const LaunchCfg &cfg);
 
+
+// ---- batched solves (many independent systems per launch) ----
+
+// Per-system constants of a batch. Rows of system s sit at [row0, row0 + n)
+// of the concatenated vectors, its slices at [slice0, slice0 + nslices) of
+// the concatenated sliced-ELL copy (slices never span systems), and its
+// dot partials in slots [slot0, slot1).
+struct BatchSys {
+    long long row0;
+    long long slice0;
+    int n;
+    int nslices;
+    int slot0;
+    int slot1;
+    const int *row_ptr; // the caller's CSR row pointers of the system
+};
+
+// One run of work: slices [s0, s1) of system `sys`, processed by one
+// workgroup, whose dot partials go to slot `slot`.
+struct BatchRun {
+    int sys;
+    int s0;
+    int s1;
+    int slot;
+};
+
+struct BatchArgs {
+    int nsys;
+    const BatchSys *sys;
+    const BatchRun *runs;  // runs of workgroup g: [wg_run[g], wg_run[g + 1])
+    const int *wg_run;
+    // concatenated sliced-ELL copy (binary64 values, two-entry interleave)
+    const long long *off;
+    const double *val;
+    const int *col;
+    const unsigned short *col16;
+    const int *cfirst;
+    const unsigned char *len8; // indexed by concatenated row
+    // concatenated vectors
+    const double *b;
+    double *x, *r, *z, *d, *w, *dinv;
+    PcgState *st;          // [nsys]
+    double *const *hist;   // [nsys] tau histories (maxit + 1 each, entries may be null), or null
+    int *active;           // number of systems not done
+};
+
+// Setup of every system (state, partials of <z,r>, <r,r>, <b,b> into ws3,
+// one workgroup per system to merge them).
+hipError_t launch_batch_setup(int mode, bool col16, const BatchArgs &a, int grid, int block, const DotWs *ws3,
+                              int stride, double tol, int maxit, const LaunchCfg &cfg);
+// One iteration of every system not done: SpMV + <d,w> partials (ws[0]),
+// per-system rho, updates + <z,r>, <r,r> partials (ws[1], ws[2]), per-system
+// stopping test and gamma, direction update.
+hipError_t launch_batch_iteration(int mode, bool col16, const BatchArgs &a, int grid, int block, const DotWs *ws3,
+                                  int stride, const LaunchCfg &cfg);
+
 } // namespace rpcg

@@ -70,6 +70,18 @@ class _IrResult(ctypes.Structure):
                 ("k_launches", ctypes.c_int32), ("pad1", ctypes.c_int32)]
 
 
+class _BatchTuning(ctypes.Structure):
+    _fields_ = [("policy", ctypes.c_int32), ("tile_slices", ctypes.c_int32), ("grid_size", ctypes.c_int32),
+                ("block_size", ctypes.c_int32), ("graph_iterations", ctypes.c_int32), ("pad0", ctypes.c_int32),
+                ("ms_per_iteration", ctypes.c_double)]
+
+
+class _BatchStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("graph_launches", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("total_iterations", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+                ("loop_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
 _lib = None
 _ctx = {}
 
@@ -106,6 +118,18 @@ def lib():
         L.rpcg_ir_solve.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_IrOpts),
                                     ctypes.POINTER(_IrResult), P]
         L.rpcg_ir_solve.restype = ctypes.c_int
+        L.rpcg_batch_create.argtypes = [P, ctypes.c_int, I32, P, ctypes.POINTER(_Opts), ctypes.POINTER(P), P]
+        L.rpcg_batch_create.restype = ctypes.c_int
+        L.rpcg_batch_destroy.argtypes = [P]
+        L.rpcg_batch_destroy.restype = None
+        L.rpcg_batch_get_tuning.argtypes = [P, ctypes.POINTER(_BatchTuning)]
+        L.rpcg_batch_get_tuning.restype = ctypes.c_int
+        L.rpcg_batch_set_tuning.argtypes = [P, ctypes.POINTER(_BatchTuning)]
+        L.rpcg_batch_set_tuning.restype = ctypes.c_int
+        L.rpcg_batch_tune.argtypes = [P, P, I32, ctypes.POINTER(_BatchTuning), P]
+        L.rpcg_batch_tune.restype = ctypes.c_int
+        L.rpcg_batch_solve.argtypes = [P, P, P, P, P, ctypes.POINTER(_BatchStats), P]
+        L.rpcg_batch_solve.restype = ctypes.c_int
         L.rpcg_exdot_partial.argtypes = [P, I64, P, P, P, P]
         L.rpcg_exdot_partial.restype = ctypes.c_int
         L.rpcg_acc_round.argtypes = [P, P, P, P]
@@ -117,7 +141,8 @@ def lib():
 
 EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot",
             "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
-            "rpcg_exdot_partial", "rpcg_acc_round"]
+            "rpcg_batch_create", "rpcg_batch_destroy", "rpcg_batch_get_tuning", "rpcg_batch_set_tuning",
+            "rpcg_batch_tune", "rpcg_batch_solve", "rpcg_exdot_partial", "rpcg_acc_round"]
 
 
 def status_string(s: int) -> str:
@@ -346,3 +371,106 @@ def ir_solve(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str 
     if rc < 0 and raise_on_error:
         raise RpcgError(rc, "rpcg_ir_solve")
     return x, info
+
+
+def _ptr_array(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for k, t in enumerate(tensors):
+        arr[k] = None if t is None else t.data_ptr()
+    return arr
+
+
+class Batch:
+    """Many independent systems solved together (rpcg_batch_*). The CSR
+    matrices must stay alive and unchanged while the batch exists."""
+
+    def __init__(self, mats, mode: str = "exblas", **opts):
+        if not mats:
+            raise ValueError("empty batch")
+        self.mats = list(mats)
+        dev = self.mats[0].val.device
+        self.device = dev
+        self.mode = mode
+        self._opts = _opts(**opts)
+        if self._opts.tau_history:
+            raise TypeError("tau_history is given per solve")
+        self.maxit = self._opts.maxit
+        arr = (_Csr * len(self.mats))()
+        for k, A in enumerate(self.mats):
+            arr[k] = A._c()
+        self._csr = arr
+        h = ctypes.c_void_p()
+        rc = lib().rpcg_batch_create(context(dev.index), MODES[mode], len(self.mats), ctypes.cast(arr, ctypes.c_void_p),
+                                     ctypes.byref(self._opts), ctypes.byref(h), _stream(dev))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rpcg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def tuning(self) -> dict:
+        t = _BatchTuning()
+        rc = lib().rpcg_batch_get_tuning(self._h, ctypes.byref(t))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_batch_get_tuning")
+        return {f: getattr(t, f) for f, _ in _BatchTuning._fields_ if f != "pad0"}
+
+    def set_tuning(self, **kw):
+        t = _BatchTuning()
+        lib().rpcg_batch_get_tuning(self._h, ctypes.byref(t))
+        for k, v in kw.items():
+            if not hasattr(t, k) or k == "pad0":
+                raise TypeError(f"unknown tuning field {k}")
+            setattr(t, k, v)
+        rc = lib().rpcg_batch_set_tuning(self._h, ctypes.byref(t))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_batch_set_tuning")
+
+    def tune(self, bs, trial_iterations: int = 10) -> dict:
+        for b in bs:
+            _check(b, torch.float64, "b")
+        t = _BatchTuning()
+        rc = lib().rpcg_batch_tune(self._h, ctypes.cast(_ptr_array(bs), ctypes.c_void_p), int(trial_iterations),
+                                   ctypes.byref(t), _stream(self.device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_batch_tune")
+        return {f: getattr(t, f) for f, _ in _BatchTuning._fields_ if f != "pad0"}
+
+    def solve(self, bs, x0s=None, history: bool = True, raise_on_error: bool = True):
+        """Returns (xs, infos, stats): per-system solutions and result dicts
+        (info['hist'] = tau^(0..L) when history=True) and the batch figures."""
+        if len(bs) != len(self.mats):
+            raise ValueError("one right-hand side per system")
+        xs = []
+        for k, b in enumerate(bs):
+            _check(b, torch.float64, "b")
+            x = torch.zeros_like(b) if x0s is None or x0s[k] is None else x0s[k].clone()
+            _check(x, torch.float64, "x")
+            xs.append(x)
+        hists = [torch.zeros(self.maxit + 1, dtype=torch.float64, device=self.device) for _ in bs] if history else None
+        res = (_Result * len(bs))()
+        st = _BatchStats()
+        rc = lib().rpcg_batch_solve(self._h, ctypes.cast(_ptr_array(bs), ctypes.c_void_p),
+                                    ctypes.cast(_ptr_array(xs), ctypes.c_void_p),
+                                    ctypes.cast(_ptr_array(hists), ctypes.c_void_p) if hists else None,
+                                    ctypes.cast(res, ctypes.c_void_p), ctypes.byref(st), _stream(self.device))
+        infos = []
+        for k in range(len(bs)):
+            d = _result_dict(res[k])
+            if hists is not None:
+                d["hist"] = hists[k][: res[k].iterations + 1].cpu()
+            infos.append(d)
+        stats = {f: getattr(st, f) for f, _ in _BatchStats._fields_ if f != "pad0"}
+        if rc < 0 and raise_on_error:
+            raise RpcgError(rc, "rpcg_batch_solve")
+        return xs, infos, stats

@@ -26,5 +26,7 @@ from .gen import (  # noqa: F401
     exdot_wide,
     exdot_conditioned,
     random_spd_csr,
+    batch_grid_sizes,
+    batch_systems,
     CSRHost,
 )

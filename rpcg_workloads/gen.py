@@ -230,3 +230,22 @@ def random_spd_csr(n: int, seed: int, density: float = 0.3) -> CSRHost:
     np.add.at(row_ptr, rows + 1, 1)
     row_ptr = np.cumsum(row_ptr)
     return CSRHost(n, row_ptr.astype(np.int32), cols.astype(np.int32), A[rows, cols].astype(np.float64))
+
+
+def batch_grid_sizes(seed: int, count: int = 64, lo: int = 16, hi: int = 96) -> list:
+    """Grid sizes N_s, uniform integers in [lo, hi] (the batched workload's
+    cubic grids), from the counter-based stream (modulo bias below 2^-57)."""
+    r = splitmix64(seed, count) % np.uint64(hi - lo + 1)
+    return [int(v) + lo for v in r]
+
+
+def batch_systems(seed: int, count: int = 64, lo: int = 16, hi: int = 96, sigma: float = 1.0):
+    """The batched workload: `count` 7-point variable-coefficient systems on
+    N_s^3 grids (N_s from batch_grid_sizes) with right-hand sides uniform on
+    [-1, 1). System s uses matrix seed 1000 * seed + s and vector seed
+    2000 * seed + s. Returns a list of (N_s, CSRHost, b)."""
+    out = []
+    for s, N in enumerate(batch_grid_sizes(seed, count, lo, hi)):
+        A = stencil7_varcoef_csr(N, 1000 * seed + s, sigma)
+        out.append((N, A, uniform_pm1(2000 * seed + s, A.n)))
+    return out

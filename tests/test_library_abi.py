@@ -61,7 +61,8 @@ def test_struct_layout_matches_header(tmp_path):
     import subprocess
     from paper_2005_07282_amd import rpcg
     mirrors = {"rpcg_csr": rpcg._Csr, "rpcg_csr_f32": rpcg._Csr, "rpcg_opts": rpcg._Opts,
-               "rpcg_result": rpcg._Result, "rpcg_ir_opts": rpcg._IrOpts, "rpcg_ir_result": rpcg._IrResult}
+               "rpcg_result": rpcg._Result, "rpcg_ir_opts": rpcg._IrOpts, "rpcg_ir_result": rpcg._IrResult,
+               "rpcg_batch_tuning": rpcg._BatchTuning, "rpcg_batch_stats": rpcg._BatchStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "rpcg.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -93,6 +94,11 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.rpcg_acc_round(None, None, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_pcg_solve_f32(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_ir_solve(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_batch_create(None, 2, 1, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_batch_solve(None, None, None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_batch_tune(None, None, 10, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_batch_set_tuning(None, None) == rpcg.ERR_INVALID
+    L.rpcg_batch_destroy(None)
     L.rpcg_destroy(None)
 
 
