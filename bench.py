@@ -147,6 +147,71 @@ def run_mixed_precision(N, rpcg, torch, dev):
     return out
 
 
+def run_batched(seed, rpcg, torch, dev):
+    """64 independent 7-point variable-coefficient systems on N^3 grids, N
+    uniform in 16..96, exact dots, tol 1e-8: one batched solve (autotuned
+    schedule, captured iteration graphs) against the same systems solved one
+    after another with rpcg_pcg_solve."""
+    from rpcg_workloads import batch_systems
+    log(f"[bench] batched: generating 64 systems (seed {seed})")
+    systems = batch_systems(seed)
+    mats = [rpcg.CSR.from_host(A, dev) for _, A, _ in systems]
+    bs = [torch.from_numpy(b).to(dev) for _, _, b in systems]
+    rows = [A.n for _, A, _ in systems]
+    nnz = [A.nnz for _, A, _ in systems]
+    tol, maxit = 1e-8, 2000
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    B = rpcg.Batch(mats, mode="exblas", tol=tol, maxit=maxit)
+    torch.cuda.synchronize()
+    create_ms = (time.perf_counter() - t) * 1e3
+    log("[bench] batched: autotuning")
+    tuning = B.tune(bs, trial_iterations=10)
+    log(f"[bench]   chose {tuning}")
+    B.solve(bs, history=False)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    xs, infos, st = B.solve(bs, history=False)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t) * 1e3
+    log(f"[bench]   batched solve {batch_ms:.1f} ms, {st['total_iterations']} iterations in total")
+    solo_ms = 0.0
+    same = 0
+    rpcg.pcg_solve(mats[0], bs[0], mode="exblas", tol=tol, maxit=maxit, history=False)
+    for k in range(len(mats)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x1, i1 = rpcg.pcg_solve(mats[k], bs[k], mode="exblas", tol=tol, maxit=maxit, history=False)
+        torch.cuda.synchronize()
+        solo_ms += (time.perf_counter() - t) * 1e3
+        same += int(i1["iterations"] == infos[k]["iterations"] and torch.equal(x1, xs[k]))
+    B.close()
+    row_it = sum(r * i["iterations"] for r, i in zip(rows, infos))
+    # algorithmic bytes of one iteration of a system (as for the single solve): 12 nnz + 4 (n+1) + 104 n
+    it_bytes = sum((12 * z + 4 * (r + 1) + 104 * r) * i["iterations"] for r, z, i in zip(rows, nnz, infos))
+    out = {
+        "workload": f"64 systems, 7-point diffusion with exp(N(0,1)) face coefficients on N^3 grids, N uniform "
+                    f"in 16..96 (seed {seed}; n = {sum(rows)}, nnz = {sum(nnz)} in total), b ~ U[-1,1), "
+                    f"exact dots, tol {tol}",
+        "tuning": {k: v for k, v in tuning.items()},
+        "create_ms": round(create_ms, 2),
+        "solve_ms": round(batch_ms, 2),
+        "loop_ms": round(st["loop_ms"], 2),
+        "graph_launches": st["graph_launches"],
+        "iterations_total": st["total_iterations"],
+        "iterations_max": st["max_iterations"],
+        "solo_solves_ms": round(solo_ms, 2),
+        "speedup_vs_solo": round(solo_ms / batch_ms, 3),
+        "row_iterations_per_s": round(row_it / (batch_ms * 1e-3), 1),
+        "algorithmic_GB_s": round(it_bytes / (st["loop_ms"] * 1e-3) / 1e9, 1),
+        "systems_bit_identical_to_solo": same,
+    }
+    log(f"[bench]   solo solves {solo_ms:.1f} ms; speedup {out['speedup_vs_solo']}; identical {same}/64")
+    del mats, bs, xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +224,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ir-grid", type=int, default=256,
                     help="N of the N^3 grid of the mixed-precision refinement section (0 = skip)")
+    ap.add_argument("--batch-seed", type=int, default=7,
+                    help="seed of the batched workload (64 systems, 16^3..96^3); -1 = skip")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched section and print its JSON (for a separate kernel trace)")
     ap.add_argument("--mixed-only", action="store_true",
                     help="run only the mixed-precision section and print its JSON (for a separate kernel trace)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -185,6 +254,9 @@ def main():
     rpcg.context(0)
     if args.mixed_only:
         print(json.dumps(run_mixed_precision(args.ir_grid, rpcg, torch, dev)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(run_batched(args.batch_seed, rpcg, torch, dev)), flush=True)
         return
 
     N = args.grid
@@ -300,6 +372,7 @@ def main():
         log(f"[bench]   oracle {cpu['value']} it/s")
 
     mixed = run_mixed_precision(args.ir_grid, rpcg, torch, dev) if args.ir_grid > 0 else None
+    batched = run_batched(args.batch_seed, rpcg, torch, dev) if args.batch_seed >= 0 else None
 
     traffic = k1_traffic() if N == 160 else None
     line = {
@@ -330,6 +403,7 @@ def main():
             "exdot_n": ne,
             "exdot": exd,
             "mixed_precision": mixed,
+            "batched": batched,
         },
         "roofline": {
             "bound": "hbm",

@@ -274,7 +274,7 @@ typedef struct {
                                  failed, else the highest warning, else RPCG_OK */
     int32_t graph_launches;   /* graph replays */
     int32_t max_iterations;   /* largest per-system iteration count */
-    int32_t pad0;
+    int32_t repartitions;     /* times the work was re-spread over the systems still running */
     int64_t total_iterations; /* sum of the per-system iteration counts */
     double setup_ms;          /* wall time: copies in, setup kernels */
     double loop_ms;           /* wall time of the replays */

@@ -44,6 +44,14 @@ struct rpcg_batch {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, poll_ev[2] = {nullptr, nullptr}, t_ev[2] = {nullptr, nullptr};
     int *host_active = nullptr;        // pinned, two entries
     std::vector<PcgState> host_st;
+    // re-partition between replays: pinned staging of the schedule (two sets,
+    // so the next one is written while the previous copy may still be pending)
+    PcgState *host_poll_st = nullptr;  // pinned, 2 * nsys
+    char *stage[2] = {nullptr, nullptr};
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ev[2] = {nullptr, nullptr};
+    int stage_next = 0;
+    int slot_cap = 0;                  // slots a schedule of this tuning may use
 };
 
 namespace {
@@ -96,12 +104,15 @@ void drop_graph(rpcg_batch *B)
     B->graph_valid = false;
 }
 
-// Runs of the streaming kernels for the current tuning; slots numbered
-// system by system so that each system's partials are contiguous.
-int build_schedule(rpcg_batch *B)
+// Runs of the streaming kernels for the current tuning over the systems with
+// active[q] != 0 (all when active is null); slots numbered system by system so
+// that each system's partials are contiguous.
+void compute_schedule(rpcg_batch *B, const std::vector<char> *active, std::vector<BatchRun> &runs,
+                      std::vector<int> &wg_run)
 {
     const rpcg_batch_tuning &t = B->tuning;
     const int G = t.grid_size;
+    auto on = [&](int q) { return !active || (*active)[q]; };
     std::vector<std::vector<BatchRun>> per_wg(G);
     auto add = [&](int g, int sys, int s) {
         std::vector<BatchRun> &v = per_wg[g];
@@ -110,17 +121,21 @@ int build_schedule(rpcg_batch *B)
     };
     if (t.policy == 0) {
         // contiguous chunks with equal stored entries (at least one slice of work each)
-        const long long total = B->off_host[B->total_slices];
+        long long total = 0;
+        for (int q = 0; q < B->nsys; ++q)
+            if (on(q)) total += B->off_host[B->sys[q].slice0 + B->sys[q].nslices] - B->off_host[B->sys[q].slice0];
         const long long target = std::max(1ll, (total + G - 1) / G);
         int g = 0;
         long long acc = 0;
-        for (int q = 0; q < B->nsys; ++q)
+        for (int q = 0; q < B->nsys; ++q) {
+            if (!on(q)) continue;
             for (int s = 0; s < B->sys[q].nslices; ++s) {
                 const long long gsl = B->sys[q].slice0 + s;
                 if (acc >= target && g < G - 1) { ++g; acc = 0; }
                 add(g, q, s);
                 acc += std::max(64ll, B->off_host[gsl + 1] - B->off_host[gsl]);
             }
+        }
     } else {
         // tiles of tile_slices slices, systems interleaved, dealt round-robin
         const int T = t.tile_slices;
@@ -130,13 +145,13 @@ int build_schedule(rpcg_batch *B)
         for (int j = 0; j < max_tiles; ++j)
             for (int q = 0; q < B->nsys; ++q) {
                 const int s0 = j * T, s1 = std::min(B->sys[q].nslices, s0 + T);
-                if (s0 >= s1) continue;
+                if (s0 >= s1 || !on(q)) continue;
                 const int g = (int)(i++ % G);
                 per_wg[g].push_back(BatchRun{q, s0, s1, -1});
             }
     }
-    std::vector<BatchRun> runs;
-    std::vector<int> wg_run(G + 1, 0);
+    runs.clear();
+    wg_run.assign(G + 1, 0);
     for (int g = 0; g < G; ++g) {
         wg_run[g] = (int)runs.size();
         runs.insert(runs.end(), per_wg[g].begin(), per_wg[g].end());
@@ -155,18 +170,73 @@ int build_schedule(rpcg_batch *B)
         if (k == 0 || runs[order[k - 1]].sys != r.sys) S.slot0 = (int)k;
         S.slot1 = (int)k + 1;
     }
+}
+
+size_t schedule_bytes(const rpcg_batch *B, size_t nruns)
+{
+    return sizeof(BatchSys) * B->nsys + sizeof(BatchRun) * std::max<size_t>(1, nruns) +
+           sizeof(int) * (B->tuning.grid_size + 1);
+}
+
+// Copy a schedule into the device arrays. With `async` the copies go through
+// pinned staging and are only enqueued (used between replays).
+int upload_schedule(rpcg_batch *B, const std::vector<BatchRun> &runs, const std::vector<int> &wg_run, bool async)
+{
+    const int G = B->tuning.grid_size;
+    if (!async) {
+        RPCG_TRY(hipMemcpyAsync(B->dsys.p, B->sys.data(), sizeof(BatchSys) * B->nsys, hipMemcpyHostToDevice, B->gs));
+        if (!runs.empty())
+            RPCG_TRY(hipMemcpyAsync(B->druns.p, runs.data(), sizeof(BatchRun) * runs.size(), hipMemcpyHostToDevice,
+                                    B->gs));
+        RPCG_TRY(hipMemcpyAsync(B->dwg.p, wg_run.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice, B->gs));
+        RPCG_TRY(hipStreamSynchronize(B->gs)); // the host vectors are staged before they go out of scope
+        return RPCG_OK;
+    }
+    const int k = B->stage_next;
+    B->stage_next ^= 1;
+    RPCG_TRY(hipEventSynchronize(B->stage_ev[k])); // the copy that last read this staging set is done
+    char *p = B->stage[k];
+    const size_t a = sizeof(BatchSys) * B->nsys, r = sizeof(BatchRun) * runs.size(), w = sizeof(int) * (G + 1);
+    std::memcpy(p, B->sys.data(), a);
+    if (r) std::memcpy(p + a, runs.data(), r);
+    std::memcpy(p + a + r, wg_run.data(), w);
+    RPCG_TRY(hipMemcpyAsync(B->dsys.p, p, a, hipMemcpyHostToDevice, B->gs));
+    if (r) RPCG_TRY(hipMemcpyAsync(B->druns.p, p + a, r, hipMemcpyHostToDevice, B->gs));
+    RPCG_TRY(hipMemcpyAsync(B->dwg.p, p + a + r, w, hipMemcpyHostToDevice, B->gs));
+    RPCG_TRY(hipEventRecord(B->stage_ev[k], B->gs));
+    return RPCG_OK;
+}
+
+// Schedule of every system for the current tuning; sizes the slot workspace
+// and the staging for any later re-partition over fewer systems.
+int build_schedule(rpcg_batch *B)
+{
+    std::vector<BatchRun> runs;
+    std::vector<int> wg_run;
+    compute_schedule(B, nullptr, runs, wg_run);
     B->nruns = (int)runs.size();
-    int rc = ensure_batch_ws(B, std::max(1, B->nruns));
+    // a re-partition over a subset never has more runs: policy 0 makes at most
+    // grid + nsys runs, policy 1 a subset of the tiles
+    B->slot_cap = std::max(1, B->tuning.policy == 0 ? std::max(B->nruns, B->tuning.grid_size + B->nsys) : B->nruns);
+    int rc = ensure_batch_ws(B, B->slot_cap);
     if (rc != RPCG_OK) return rc;
+    const size_t maxruns = (size_t)B->slot_cap;
     RPCG_TRY(B->dsys.ensure(sizeof(BatchSys) * B->nsys));
-    RPCG_TRY(B->druns.ensure(sizeof(BatchRun) * std::max<size_t>(1, runs.size())));
-    RPCG_TRY(B->dwg.ensure(sizeof(int) * (G + 1)));
-    RPCG_TRY(hipMemcpyAsync(B->dsys.p, B->sys.data(), sizeof(BatchSys) * B->nsys, hipMemcpyHostToDevice, B->gs));
-    if (!runs.empty())
-        RPCG_TRY(hipMemcpyAsync(B->druns.p, runs.data(), sizeof(BatchRun) * runs.size(), hipMemcpyHostToDevice,
-                                B->gs));
-    RPCG_TRY(hipMemcpyAsync(B->dwg.p, wg_run.data(), sizeof(int) * (G + 1), hipMemcpyHostToDevice, B->gs));
-    RPCG_TRY(hipStreamSynchronize(B->gs)); // the host vectors are staged before they go out of scope
+    RPCG_TRY(B->druns.ensure(sizeof(BatchRun) * maxruns));
+    RPCG_TRY(B->dwg.ensure(sizeof(int) * (B->tuning.grid_size + 1)));
+    const size_t need = schedule_bytes(B, maxruns);
+    if (need > B->stage_bytes) {
+        RPCG_TRY(hipStreamSynchronize(B->gs));
+        for (char *&p : B->stage) {
+            if (p) hipHostFree(p);
+            p = nullptr;
+        }
+        B->stage_bytes = 0;
+        for (char *&p : B->stage) RPCG_TRY(hipHostMalloc((void **)&p, need, hipHostMallocDefault));
+        B->stage_bytes = need;
+    }
+    rc = upload_schedule(B, runs, wg_run, false);
+    if (rc != RPCG_OK) return rc;
     drop_graph(B);
     return RPCG_OK;
 }
@@ -278,9 +348,13 @@ void rpcg_batch_destroy(rpcg_batch *B)
     for (Buffer *b : {&B->off, &B->val, &B->col, &B->cfirst, &B->len8, &B->vecs, &B->st, &B->hist_ptrs, &B->active,
                       &B->dsys, &B->druns, &B->dwg, &B->ws_mem})
         b->release();
-    for (hipEvent_t e : {B->ev_in, B->ev_out, B->poll_ev[0], B->poll_ev[1], B->t_ev[0], B->t_ev[1]})
+    for (hipEvent_t e : {B->ev_in, B->ev_out, B->poll_ev[0], B->poll_ev[1], B->t_ev[0], B->t_ev[1], B->stage_ev[0],
+                         B->stage_ev[1]})
         if (e) hipEventDestroy(e);
     if (B->host_active) hipHostFree(B->host_active);
+    if (B->host_poll_st) hipHostFree(B->host_poll_st);
+    for (char *p : B->stage)
+        if (p) hipHostFree(p);
     if (B->gs) hipStreamDestroy(B->gs);
     delete B;
 }
@@ -294,6 +368,9 @@ static int batch_create_body(rpcg_batch *B, const rpcg_csr *A, hipStream_t calle
     RPCG_TRY(hipEventCreate(&B->t_ev[0]));
     RPCG_TRY(hipEventCreate(&B->t_ev[1]));
     RPCG_TRY(hipHostMalloc((void **)&B->host_active, 2 * sizeof(int), hipHostMallocDefault));
+    RPCG_TRY(hipHostMalloc((void **)&B->host_poll_st, 2 * sizeof(PcgState) * B->nsys, hipHostMallocDefault));
+    RPCG_TRY(hipEventCreateWithFlags(&B->stage_ev[0], hipEventDisableTiming));
+    RPCG_TRY(hipEventCreateWithFlags(&B->stage_ev[1], hipEventDisableTiming));
     // layout: each system's rows start at a multiple of 64, its slices after the previous system's
     B->sys.resize(B->nsys);
     long long row0 = 0, slice0 = 0;
@@ -489,23 +566,52 @@ int rpcg_batch_solve(rpcg_batch *B, const double *const *b, double *const *x, do
     rc = capture_graph(B, with_hist);
     if (rc != RPCG_OK) return rc;
     auto t1 = std::chrono::steady_clock::now();
-    int launches = 0;
+    int launches = 0, repartitions = 0;
     if (ha[0] > 0) {
         const int G = B->tuning.graph_iterations;
         const int max_launch = (B->o.maxit + G - 1) / G;
+        const int nsys = B->nsys;
+        int scheduled = nsys; // systems the current schedule covers
+        std::vector<char> live(nsys);
+        std::vector<BatchRun> runs;
+        std::vector<int> wg_run;
         for (int k = 0; k < max_launch; ++k) {
             RPCG_TRY(hipGraphLaunch(B->exec, B->gs));
             ++launches;
             RPCG_TRY(hipMemcpyAsync((void *)&ha[k & 1], B->active.p, sizeof(int), hipMemcpyDeviceToHost, B->gs));
+            RPCG_TRY(hipMemcpyAsync(B->host_poll_st + (size_t)(k & 1) * nsys, B->st.p, sizeof(PcgState) * nsys,
+                                    hipMemcpyDeviceToHost, B->gs));
             RPCG_TRY(hipEventRecord(B->poll_ev[k & 1], B->gs));
             if (k > 0) {
-                RPCG_TRY(hipEventSynchronize(B->poll_ev[(k - 1) & 1]));
-                if (ha[(k - 1) & 1] == 0) break;
+                const int pk = (k - 1) & 1;
+                RPCG_TRY(hipEventSynchronize(B->poll_ev[pk]));
+                const int left = ha[pk];
+                if (left == 0) break;
+                // fewer systems left: spread the next replays' work over them
+                // (results do not depend on the schedule)
+                if (left < scheduled && k + 1 < max_launch) {
+                    const PcgState *ps = B->host_poll_st + (size_t)pk * nsys;
+                    for (int q = 0; q < nsys; ++q) live[q] = ps[q].done == 0;
+                    compute_schedule(B, &live, runs, wg_run);
+                    if ((int)runs.size() <= B->slot_cap) {
+                        rc = upload_schedule(B, runs, wg_run, true);
+                        if (rc != RPCG_OK) return rc;
+                        scheduled = left;
+                        ++repartitions;
+                    }
+                }
             }
         }
     }
     RPCG_TRY(hipStreamSynchronize(B->gs));
     const double loop_ms = ms_since(t1);
+    if (repartitions) {
+        std::vector<BatchRun> runs;
+        std::vector<int> wg_run;
+        compute_schedule(B, nullptr, runs, wg_run);
+        rc = upload_schedule(B, runs, wg_run, false);
+        if (rc != RPCG_OK) return rc;
+    }
     const double *v = (const double *)B->vecs.p;
     const size_t T = (size_t)B->total_rows;
     for (int q = 0; q < B->nsys; ++q) {
@@ -551,6 +657,7 @@ int rpcg_batch_solve(rpcg_batch *B, const double *const *b, double *const *x, do
     if (stats) {
         stats->status = worst;
         stats->graph_launches = launches;
+        stats->repartitions = repartitions;
         stats->max_iterations = max_it;
         stats->total_iterations = total_it;
         stats->setup_ms = setup_ms;

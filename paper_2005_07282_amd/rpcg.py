@@ -78,7 +78,7 @@ class _BatchTuning(ctypes.Structure):
 
 class _BatchStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("graph_launches", ctypes.c_int32), ("max_iterations", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("total_iterations", ctypes.c_int64), ("setup_ms", ctypes.c_double),
+                ("repartitions", ctypes.c_int32), ("total_iterations", ctypes.c_int64), ("setup_ms", ctypes.c_double),
                 ("loop_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
 
 
