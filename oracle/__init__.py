@@ -62,6 +62,9 @@ def lib():
         L.rpcg_oracle_pcg_f32.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, P, P]
         L.rpcg_oracle_ir_scale.restype = ctypes.c_int
         L.rpcg_oracle_ir_scale.argtypes = [ctypes.c_double]
+        L.rpcg_oracle_pcg_factored.restype = ctypes.c_int
+        L.rpcg_oracle_pcg_factored.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_double, P, P,
+                                               ctypes.c_double, ctypes.c_int32, P, P]
         L.rpcg_oracle_ir.restype = ctypes.c_int
         L.rpcg_oracle_ir.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                                      ctypes.c_double, ctypes.c_int32, P, P, P]
@@ -214,3 +217,34 @@ def ir(A, b, x0=None, tol=1e-10, maxit_out=50, tol_in=1e-4, maxit_in=2000):
                               float(tol_in), int(maxit_in), _p(hist), ctypes.byref(outer), ctypes.byref(inner))
     k = outer.value
     return dict(x=x, outer=k, inner=inner.value, hist=hist[:k + 1].copy(), status=st)
+
+
+def pcg_factored(A, G, Gt, eps, b, x0=None, tol=1e-8, maxit=2000):
+    """PCG with M^-1 = G G^T + eps I (G^T given explicitly as Gt).
+    Returns dict(x, iters, hist, status)."""
+    n = A.n
+    b = _f64(b)
+    x = np.zeros(n, dtype=np.float64) if x0 is None else _f64(x0).copy()
+    hist = np.zeros(maxit + 1, dtype=np.float64)
+    iters = ctypes.c_int32(0)
+    arrs = []
+    for M in (A, G, Gt):
+        arrs += [_i32(M.row_ptr), _i32(M.col_idx), _f64(M.val)]
+    st = lib().rpcg_oracle_pcg_factored(n, *[_p(a) for a in arrs], float(eps), _p(b), _p(x), float(tol), int(maxit),
+                                        _p(hist), ctypes.byref(iters))
+    L = iters.value
+    return dict(x=x, iters=L, hist=hist[:L + 1].copy(), status=st)
+
+
+def transpose_csr(M):
+    """Explicit transpose of a square CSR (rows of M^T in ascending column order);
+    a storage conversion with no arithmetic."""
+    n = M.n
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(M.row_ptr, dtype=np.int64)))
+    cols = np.asarray(M.col_idx, dtype=np.int64)
+    order = np.lexsort((rows, cols))
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(rp, cols + 1, 1)
+    from rpcg_workloads import CSRHost
+    return CSRHost(n, np.cumsum(rp).astype(np.int32), rows[order].astype(np.int32),
+                   np.asarray(M.val, dtype=np.float64)[order])

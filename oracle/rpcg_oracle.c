@@ -497,3 +497,69 @@ int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
     free(val32); free(r); free(rf); free(c);
     return status;
 }
+
+/* ---- PCG with a factored preconditioner M^-1 = G G^T + eps I ----------------
+ * The learned preconditioner supplies G (a sparse matrix, in the workload the
+ * lower triangle of A's pattern) and G^T explicitly as a second CSR, so that
+ * both products are row-wise fma chains in storage order, as the SpMV of
+ * Section 4.3. Only the preconditioner step S5 of Fig. 1 changes:
+ *   t = G^T r,  s = G t,  z_i = fma(eps, r_i, s_i).
+ * Every other step, and the exact dots, are those of rpcg_oracle_pcg. */
+static void factored_apply(int32_t n, const int32_t *g_rp, const int32_t *g_col, const double *g_val,
+                           const int32_t *gt_rp, const int32_t *gt_col, const double *gt_val, double eps,
+                           const double *r, double *t, double *z)
+{
+    rpcg_oracle_spmv(n, gt_rp, gt_col, gt_val, r, t);
+    rpcg_oracle_spmv(n, g_rp, g_col, g_val, t, z);
+    for (int32_t i = 0; i < n; ++i) z[i] = fma(eps, r[i], z[i]);
+}
+
+int rpcg_oracle_pcg_factored(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                             const int32_t *g_rp, const int32_t *g_col, const double *g_val,
+                             const int32_t *gt_rp, const int32_t *gt_col, const double *gt_val, double eps,
+                             const double *b, double *x, double tol, int32_t maxit, double *hist, int32_t *iters)
+{
+    *iters = 0;
+    if (n < 0 || maxit < 0) return ORC_ERR_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *r = malloc(sizeof(double) * nn), *z = malloc(sizeof(double) * nn);
+    double *d = malloc(sizeof(double) * nn), *w = malloc(sizeof(double) * nn);
+    double *t = malloc(sizeof(double) * nn);
+    int status = ORC_OK;
+    for (int32_t i = 0; i < n && status == ORC_OK; ++i)
+        if (!isfinite(b[i]) || !isfinite(x[i])) status = ORC_ERR_NONFINITE;
+    if (status != ORC_OK) goto out;
+    rpcg_oracle_spmv(n, row_ptr, col, val, x, w);
+    for (int32_t i = 0; i < n; ++i) r[i] = b[i] - w[i];
+    factored_apply(n, g_rp, g_col, g_val, gt_rp, gt_col, gt_val, eps, r, t, z);
+    for (int32_t i = 0; i < n; ++i) d[i] = z[i];
+    double beta = rpcg_oracle_exdot(n, z, r);
+    double tau = rpcg_oracle_exdot(n, r, r);
+    double bb = rpcg_oracle_exdot(n, b, b);
+    double thr = (tol * tol) * bb;
+    if (hist) hist[0] = tau;
+    if (!isfinite(tau) || !isfinite(bb) || !isfinite(beta)) { status = ORC_ERR_NONFINITE; goto out; }
+    int32_t l = 0;
+    while (tau > thr && l < maxit) {
+        double beta_old = beta;
+        rpcg_oracle_spmv(n, row_ptr, col, val, d, w);
+        double delta = rpcg_oracle_exdot(n, d, w);
+        if (!(delta > 0.0)) { status = isfinite(delta) ? ORC_ERR_BREAKDOWN : ORC_ERR_NONFINITE; break; }
+        double rho = beta / delta;
+        for (int32_t i = 0; i < n; ++i) x[i] = fma(rho, d[i], x[i]);
+        for (int32_t i = 0; i < n; ++i) r[i] = fma(-rho, w[i], r[i]);
+        factored_apply(n, g_rp, g_col, g_val, gt_rp, gt_col, gt_val, eps, r, t, z);
+        beta = rpcg_oracle_exdot(n, z, r);
+        tau = rpcg_oracle_exdot(n, r, r);
+        double gamma = beta / beta_old;
+        for (int32_t i = 0; i < n; ++i) d[i] = fma(gamma, d[i], z[i]);
+        l += 1;
+        if (hist) hist[l] = tau;
+        if (!isfinite(tau) || !isfinite(beta)) { status = ORC_ERR_NONFINITE; break; }
+    }
+    *iters = l;
+    if (status == ORC_OK && tau > thr) status = ORC_WARN_MAXIT;
+out:
+    free(r); free(z); free(d); free(w); free(t);
+    return status;
+}

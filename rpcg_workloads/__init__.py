@@ -28,5 +28,7 @@ from .gen import (  # noqa: F401
     random_spd_csr,
     batch_grid_sizes,
     batch_systems,
+    grf_field,
+    grf_diffusion_csr,
     CSRHost,
 )

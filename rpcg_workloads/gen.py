@@ -249,3 +249,53 @@ def batch_systems(seed: int, count: int = 64, lo: int = 16, hi: int = 96, sigma:
         A = stencil7_varcoef_csr(N, 1000 * seed + s, sigma)
         out.append((N, A, uniform_pm1(2000 * seed + s, A.n)))
     return out
+
+
+def grf_field(N: int, seed: int, ell: float = 8.0) -> np.ndarray:
+    """Stationary Gaussian random field on an N^3 grid with unit variance and
+    Gaussian correlation exp(-|h|^2 / (2 ell^2)) (in cells), by FFT filtering
+    of seeded white noise (periodic; the workload uses it as a texture)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = rng.standard_normal((N, N, N))
+    k = 2.0 * np.pi * np.fft.fftfreq(N)
+    kz, ky, kx = np.meshgrid(k, k, k, indexing="ij")
+    filt = np.exp(-0.25 * ell * ell * (kx * kx + ky * ky + kz * kz))  # square root of the spectral density
+    g = np.real(np.fft.ifftn(np.fft.fftn(w) * filt))
+    g -= g.mean()
+    s = g.std()
+    return g / s if s > 0 else g
+
+
+def grf_diffusion_csr(N: int, seed: int, sigma: float = 1.5, ell: float = 8.0):
+    """7-point diffusion on an N^3 grid with log-normal cell coefficients
+    c = exp(sigma * GRF) (grf_field). Face coefficient = harmonic mean of the
+    two cells it separates; a boundary face takes its cell's coefficient
+    (Dirichlet coupling to zero). A_ij = -k_face, A_ii = sum of the six faces.
+    Returns (CSRHost, c) with the cell coefficients c (N, N, N)."""
+    c = np.exp(sigma * grf_field(N, seed, ell))
+
+    def hmean(a, b):
+        return 2.0 * a * b / (a + b)
+
+    kx = np.empty((N, N, N + 1))
+    ky = np.empty((N, N + 1, N))
+    kz = np.empty((N + 1, N, N))
+    kx[:, :, 1:-1] = hmean(c[:, :, :-1], c[:, :, 1:])
+    kx[:, :, 0], kx[:, :, -1] = c[:, :, 0], c[:, :, -1]
+    ky[:, 1:-1, :] = hmean(c[:, :-1, :], c[:, 1:, :])
+    ky[:, 0, :], ky[:, -1, :] = c[:, 0, :], c[:, -1, :]
+    kz[1:-1, :, :] = hmean(c[:-1, :, :], c[1:, :, :])
+    kz[0, :, :], kz[-1, :, :] = c[0, :, :], c[-1, :, :]
+    diag = (kx[:, :, :-1] + kx[:, :, 1:]) + (ky[:, :-1, :] + ky[:, 1:, :]) + (kz[:-1, :, :] + kz[1:, :, :])
+    offv = {
+        (-1, 0, 0): -kz[:-1, :, :], (1, 0, 0): -kz[1:, :, :],
+        (0, -1, 0): -ky[:, :-1, :], (0, 1, 0): -ky[:, 1:, :],
+        (0, 0, -1): -kx[:, :, :-1], (0, 0, 1): -kx[:, :, 1:],
+        (0, 0, 0): diag,
+    }
+    row_ptr, col, oid, valid = _stencil_pattern(N, 7)
+    offs = _stencil_offsets(7)
+    vals = np.stack([offv[o].reshape(-1) for o in offs], axis=1)
+    val = vals[valid]
+    A = CSRHost(N ** 3, row_ptr.astype(np.int32), col.astype(np.int32), val.astype(np.float64))
+    return A, c
