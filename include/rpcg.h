@@ -164,6 +164,21 @@ int rpcg_pcg_solve(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr *A /* host stru
                    const double *b, double *x, const rpcg_opts *opts, rpcg_result *res,
                    void *stream);
 
+/* Jacobi-PCG with the Jacobi step replaced by a factored preconditioner
+ * M^-1 = G G^T + eps I (the form of the learned preconditioner; M^-1 is SPD
+ * whenever G is nonsingular or eps > 0). G and its transpose Gt are n x n
+ * CSR matrices given separately (Gt must equal G^T; it is not checked), so
+ * that S5 of Fig. 1 is three row-wise steps in storage order: t = Gt r,
+ * s = G t (fma chains from +0, as the SpMV of Section 4.3), and
+ * z_i = fma(eps, r_i, s_i). Everything else is rpcg_pcg_solve; the exact
+ * modes give results that are bit-identical for any launch configuration
+ * given G. eps: finite, >= 0. The structure of A, G and Gt is checked on the
+ * device (RPCG_ERR_INVALID); no diagonal condition applies. */
+int rpcg_pcg_solve_factored(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr *A /* host struct */,
+                            const rpcg_csr *G /* host struct */, const rpcg_csr *Gt /* host struct */,
+                            double eps, const double *b, double *x, const rpcg_opts *opts,
+                            rpcg_result *res, void *stream);
+
 /* ---- Binary32 solver and mixed-precision refinement ----
  * Extensions of the paper's method (whose solver is binary64 throughout):
  * the same Jacobi-PCG iteration with every value and every rounding in

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -153,6 +154,7 @@ void rpcg_destroy(rpcg_ctx *c)
     c->sell_col.release();
     c->sell_cfirst.release();
     c->sell_len.release();
+    c->scan_scratch.release();
     c->vecs.release();
     c->ir_vecs.release();
     c->beta_hist.release();
@@ -339,8 +341,11 @@ struct PcgRun {
 // iteration it launches. Waits for the stream.
 template <typename T>
 static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x, const rpcg_opts &o,
-                   const LaunchCfg &cfg_rows, const LaunchCfg &cfg_sl, hipStream_t s, PcgRun *out)
+                   const LaunchCfg &cfg_rows, const LaunchCfg &cfg_sl, hipStream_t s, PcgRun *out,
+                   const FacPre *fp = nullptr)
 {
+    constexpr bool F64 = std::is_same<T, double>::value;
+    if (fp && !F64) return RPCG_ERR_INVALID;
     auto t0 = std::chrono::steady_clock::now();
     const int n = M.n;
     RPCG_TRY(c->vecs.ensure(sizeof(T) * 5 * (size_t)std::max(1, n)));
@@ -357,7 +362,13 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
     RPCG_TRY(c->beta_hist.ensure(sizeof(double) * ((size_t)o.maxit + 1)));
     v.beta_hist = (double *)c->beta_hist.p;
     const int stride = c->ws_groups;
-    RPCG_TRY(launch_pcg_setup<T>(mode, M, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_sl));
+    T *t = v.dinv; // the factored preconditioner needs no inverse diagonal: t = G^T r lives there
+    if constexpr (F64) {
+        if (fp) RPCG_TRY(launch_fac_setup(mode, M, *fp, v, t, c->st, c->ws, stride, o.tol, o.maxit, cfg_rows));
+        else RPCG_TRY(launch_pcg_setup<T>(mode, M, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_sl));
+    } else {
+        RPCG_TRY(launch_pcg_setup<T>(mode, M, v, c->st, c->ws, stride, o.tol, o.maxit, cfg_sl));
+    }
     RPCG_TRY(hipStreamSynchronize(s));
     out->setup_ms = ms_since(t0);
     auto t1 = std::chrono::steady_clock::now();
@@ -379,9 +390,23 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
             if (ev) RPCG_TRY(hipEventRecord(ev[0], s));
             RPCG_TRY(launch_pcg_spmv_dot<T>(mode, M, v, c->st, c->ws[0], stride, cfg_sl));
             if (ev) RPCG_TRY(hipEventRecord(ev[1], s));
-            RPCG_TRY(launch_pcg_update<T>(mode, l, n, v, c->st, c->ws[0], cfg_sl.grid, c->ws + 1, stride, cfg_rows));
-            if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
-            RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws + 1, cfg_rows.grid, stride, cfg_rows));
+            bool done_fac = false;
+            if constexpr (F64) {
+                if (fp) {
+                    // beta partials in ws[0] (the SpMV's are merged first), tau in ws[1]
+                    RPCG_TRY(launch_fac_update(mode, l, n, *fp, v, t, c->st, c->ws[0], cfg_sl.grid, c->ws, stride,
+                                               cfg_rows));
+                    if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
+                    RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws, cfg_rows.grid, stride, cfg_rows));
+                    done_fac = true;
+                }
+            }
+            if (!done_fac) {
+                RPCG_TRY(launch_pcg_update<T>(mode, l, n, v, c->st, c->ws[0], cfg_sl.grid, c->ws + 1, stride,
+                                              cfg_rows));
+                if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
+                RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws + 1, cfg_rows.grid, stride, cfg_rows));
+            }
             if (ev) RPCG_TRY(hipEventRecord(ev[3], s));
         }
         launched += cnt;
@@ -450,10 +475,26 @@ static bool valid_csr_f32(const rpcg_csr_f32 *A)
     return true;
 }
 
+// Structural check of a CSR argument on the device (row pointers consistent,
+// columns in range), with the scan of the sliced-ELL construction.
+static int check_csr(rpcg_ctx *c, const rpcg_csr *E, hipStream_t s)
+{
+    const int nslices = (E->n + 63) / 64;
+    RPCG_TRY(c->scan_scratch.ensure(sizeof(long long) * (nslices + 1)));
+    RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
+    RPCG_TRY(launch_csr_scan(E->n, E->nnz, E->row_ptr, E->col_idx, 1, (long long *)c->scan_scratch.p + 1,
+                             &c->info->flags, &c->info->max_len, &c->info->max_delta, s));
+    DotInfo inf;
+    RPCG_TRY(hipMemcpyAsync(&inf, c->info, sizeof inf, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    return inf.flags ? RPCG_ERR_INVALID : RPCG_OK;
+}
+
 // Common body of the binary64 and binary32 solves.
 template <typename T>
 static int pcg_solve_any(rpcg_ctx *c, int mode, int n, int nnz, const int *rp, const int *col, const double *v64,
-                         const float *v32, const T *b, T *x, const rpcg_opts *opts, rpcg_result *res, void *stream)
+                         const float *v32, const T *b, T *x, const rpcg_opts *opts, rpcg_result *res, void *stream,
+                         const FacPre *fp = nullptr, const rpcg_csr *extra0 = nullptr, const rpcg_csr *extra1 = nullptr)
 {
     if (mode != MODE_PLAIN && mode != MODE_FPE && mode != MODE_EXBLAS) return RPCG_ERR_INVALID;
     rpcg_opts o;
@@ -473,6 +514,11 @@ static int pcg_solve_any(rpcg_ctx *c, int mode, int n, int nnz, const int *rp, c
     SellBuilt B;
     rc = build_sell(c, n, nnz, rp, col, v64, v32, !F32, F32, o.no_col16 != 0, s, &B);
     if (rc != RPCG_OK) return rc;
+    for (const rpcg_csr *E : {extra0, extra1}) {
+        if (!E) continue;
+        rc = check_csr(c, E, s);
+        if (rc != RPCG_OK) return rc;
+    }
     const double build_ms = ms_since(t0);
     const T *val;
     if constexpr (F32) val = B.val32;
@@ -480,7 +526,7 @@ static int pcg_solve_any(rpcg_ctx *c, int mode, int n, int nnz, const int *rp, c
     SellMat<T> M = sell_mat<T>(B, val, n, rp);
     M.val64 = nullptr;
     PcgRun run;
-    rc = run_pcg<T>(c, mode, M, b, x, o, cfg_rows, cfg_sl, s, &run);
+    rc = run_pcg<T>(c, mode, M, b, x, o, cfg_rows, cfg_sl, s, &run, fp);
     if (rc != RPCG_OK) return rc;
     fill_result(res, run, build_ms, cfg_rows, o.timing != 0);
     return run.status;
@@ -495,6 +541,27 @@ int rpcg_pcg_solve(rpcg_ctx *c, rpcg_mode mode, const rpcg_csr *A, const double 
     if (!c || !valid_csr(A) || (A->n > 0 && (!b || !x))) return RPCG_ERR_INVALID;
     int rc = pcg_solve_any<double>(c, (int)mode, A->n, A->nnz, A->row_ptr, A->col_idx, A->val, nullptr, b, x, opts,
                                    res, stream);
+    if (res) res->status = rc;
+    return rc;
+}
+
+int rpcg_pcg_solve_factored(rpcg_ctx *c, rpcg_mode mode, const rpcg_csr *A, const rpcg_csr *G, const rpcg_csr *Gt,
+                            double eps, const double *b, double *x, const rpcg_opts *opts, rpcg_result *res,
+                            void *stream)
+{
+    if (res) std::memset(res, 0, sizeof(*res));
+    if (!c || !valid_csr(A) || !valid_csr(G) || !valid_csr(Gt) || (A->n > 0 && (!b || !x))) return RPCG_ERR_INVALID;
+    if (G->n != A->n || Gt->n != A->n || !(eps >= 0.0) || !std::isfinite(eps)) return RPCG_ERR_INVALID;
+    FacPre fp;
+    fp.g_rp = G->row_ptr;
+    fp.g_col = G->col_idx;
+    fp.g_val = G->val;
+    fp.gt_rp = Gt->row_ptr;
+    fp.gt_col = Gt->col_idx;
+    fp.gt_val = Gt->val;
+    fp.eps = eps;
+    int rc = pcg_solve_any<double>(c, (int)mode, A->n, A->nnz, A->row_ptr, A->col_idx, A->val, nullptr, b, x, opts,
+                                   res, stream, &fp, G, Gt);
     if (res) res->status = rc;
     return rc;
 }

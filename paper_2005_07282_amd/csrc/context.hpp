@@ -49,6 +49,7 @@ struct rpcg_ctx {
     rpcg_host::Buffer vecs;    // r, z, d, w, dinv of the solver
     rpcg_host::Buffer ir_vecs; // refinement: r (binary64), rf and c (binary32)
     rpcg_host::Buffer beta_hist; // beta of every iteration
+    rpcg_host::Buffer scan_scratch; // slice widths of structural checks of extra CSR arguments
     int *host_done = nullptr;  // pinned: polled flags
     rpcg::PcgState *host_state = nullptr;
     rpcg::IrState *host_ir = nullptr;

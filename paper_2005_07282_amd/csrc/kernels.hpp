@@ -198,6 +198,29 @@ hipError_t launch_ir_prepare(int k, int maxit, double tol, int n, const double *
 hipError_t launch_ir_update(int n, double *x, const float *c, const IrState *ist, const LaunchCfg &cfg);
 
 
+// ---- PCG with a factored preconditioner M^-1 = G G^T + eps I ----
+
+// G and G^T as CSR (device arrays), both n x n.
+struct FacPre {
+    const int *g_rp, *g_col;
+    const double *g_val;
+    const int *gt_rp, *gt_col;
+    const double *gt_val;
+    double eps;
+};
+
+// Setup: r = b - A x0, partials of <r,r> (ws3[1]) and <b,b> (ws3[2]); t = G^T r;
+// z = G t + eps r, d = z, partials of <z,r> (ws3[0]); merge of the three.
+// Every step that writes partials runs on cfg.grid workgroups.
+hipError_t launch_fac_setup(int mode, const SellMat<double> &A, const FacPre &P, const PcgVecs<double> &v, double *t,
+                            PcgState *st, const DotWs *ws3, int stride, double tol, int maxit, const LaunchCfg &cfg);
+// Iteration l after the SpMV kernel (partials of <d,w> in wsd, Gd slots):
+// merge delta, rho; x, r updates with partials of <r,r> (ws[1]); t = G^T r;
+// z = G t + eps r with partials of <z,r> (ws[0]). The direction kernel then
+// merges ws[0] (beta) and ws[1] (tau).
+hipError_t launch_fac_update(int mode, int l, int n, const FacPre &P, const PcgVecs<double> &v, double *t,
+                             PcgState *st, const DotWs &wsd, int Gd, const DotWs *ws, int stride, const LaunchCfg &cfg);
+
 // ---- batched solves (many independent systems per launch) ----
 
 // Per-system constants of a batch. Rows of system s sit at [row0, row0 + n)

@@ -110,6 +110,10 @@ def lib():
         L.rpcg_pcg_solve.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_Opts),
                                      ctypes.POINTER(_Result), P]
         L.rpcg_pcg_solve.restype = ctypes.c_int
+        L.rpcg_pcg_solve_factored.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), ctypes.POINTER(_Csr),
+                                              ctypes.POINTER(_Csr), ctypes.c_double, P, P, ctypes.POINTER(_Opts),
+                                              ctypes.POINTER(_Result), P]
+        L.rpcg_pcg_solve_factored.restype = ctypes.c_int
         L.rpcg_pcg_solve_f32.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_Opts),
                                          ctypes.POINTER(_Result), P]
         L.rpcg_pcg_solve_f32.restype = ctypes.c_int
@@ -140,7 +144,7 @@ def lib():
 
 
 EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot",
-            "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
+            "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_factored", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
             "rpcg_batch_create", "rpcg_batch_destroy", "rpcg_batch_get_tuning", "rpcg_batch_set_tuning",
             "rpcg_batch_tune", "rpcg_batch_solve", "rpcg_exdot_partial", "rpcg_acc_round"]
 
@@ -474,3 +478,28 @@ class Batch:
         if rc < 0 and raise_on_error:
             raise RpcgError(rc, "rpcg_batch_solve")
         return xs, infos, stats
+
+
+def pcg_solve_factored(A: CSR, G: CSR, Gt: CSR, eps: float, b: torch.Tensor, x0: torch.Tensor | None = None,
+                       mode: str = "exblas", history: bool = True, raise_on_error: bool = True, **opts):
+    """PCG with M^-1 = G G^T + eps I (Gt = G^T given explicitly). Returns (x, info)."""
+    _check(b, torch.float64, "b")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    _check(x, torch.float64, "x")
+    o = _opts(**opts)
+    hist = None
+    if history and o.tau_history is None:
+        hist = torch.zeros(o.maxit + 1, dtype=torch.float64, device=b.device)
+        o.tau_history = hist.data_ptr()
+    ca, cg, cgt = A._c(), G._c(), Gt._c()
+    r = _Result()
+    rc = lib().rpcg_pcg_solve_factored(context(b.device.index), MODES[mode], ctypes.byref(ca), ctypes.byref(cg),
+                                       ctypes.byref(cgt), float(eps), b.data_ptr(), x.data_ptr(), ctypes.byref(o),
+                                       ctypes.byref(r), _stream(b.device))
+    info = _result_dict(r)
+    info["status"] = rc
+    if hist is not None:
+        info["hist"] = hist[: r.iterations + 1].cpu()
+    if rc < 0 and raise_on_error:
+        raise RpcgError(rc, "rpcg_pcg_solve_factored")
+    return x, info
