@@ -330,6 +330,71 @@ int rpcg_batch_solve(rpcg_batch *batch, const double *const *b, double *const *x
                      double *const *tau_history, rpcg_result *res, rpcg_batch_stats *stats,
                      void *stream);
 
+/* ---- Learned preconditioner ----
+ * An extension of the paper's method: a small convolutional network maps a
+ * 7-point operator A on an N^3 grid (rows in z-y-x order) to a sparse factor
+ * G on the lower-triangle pattern of A, and PCG runs with M^-1 = G G^T + eps I
+ * (rpcg_pcg_solve_factored), which is SPD by construction.
+ *
+ * Network (per grid cell, zero padding, 3x3x3 kernels, tap t = 9(dz+1) +
+ * 3(dy+1) + (dx+1) reading the cell at offset (dz, dy, dx)):
+ *   features f: ln(|a_ij| / a_ii) of the -x, -y, -z neighbours (-4 if absent),
+ *               (number of absent neighbours) / 6
+ *   h1 = relu(conv1(f) + b1), h2 = relu(conv2(h1) + b2)   (16 channels each)
+ *   o  = conv3(h2) + b3                                    (4 channels)
+ *   G_ii = RN32(s_i exp(clamp(o_0, -4, 4))), G_i,j(k) = RN32(s_i o_k) for the
+ *   -x, -y, -z neighbour j(k), s_i = RN32(1 / sqrt(a_ii)); G^T stored too.
+ * Weights, features and hidden activations are bfloat16, products accumulate
+ * in float32 on the matrix cores. Parameters (float32, RPCG_LP_NPARAMS):
+ * W1 [27][16][4], b1 [16], W2 [27][16][16], b2 [16], W3 [27][4][16], b3 [4]
+ * (weights [tap][out][in]).
+ * Training loss for vectors u of a system: mean |G G^T A u + eps A u - u|^2 /
+ * |u|^2; its gradient reaches the parameters through the network's own
+ * backward kernels, with weight gradients summed in a fixed order. */
+#define RPCG_LP_NPARAMS 10404
+
+typedef struct rpcg_lpnet rpcg_lpnet;
+
+/* Structure of G and G^T for an N^3 grid: rows of G hold the -z, -y, -x
+ * neighbours and the diagonal, rows of G^T the diagonal and the +x, +y, +z
+ * neighbours (ascending columns); both have rpcg_lp_pattern_nnz(N) =
+ * 4 N^3 - 3 N^2 entries. Host arrays of N^3 + 1 and nnz entries. */
+int64_t rpcg_lp_pattern_nnz(int32_t N);
+int rpcg_lp_pattern(int32_t N, int32_t *g_row_ptr, int32_t *g_col, int32_t *gt_row_ptr, int32_t *gt_col);
+
+/* A network for systems on N^3 grids, batches of up to max_batch systems
+ * (device workspace of roughly 200 bytes per cell and system). Parameters
+ * start at zero; set them with rpcg_lp_set_params. */
+int rpcg_lp_create(rpcg_ctx *ctx, int32_t N, int32_t max_batch, rpcg_lpnet **out /* host */);
+void rpcg_lp_destroy(rpcg_lpnet *net);
+/* params: host array of RPCG_LP_NPARAMS floats (layout above). Setting them
+ * also resets the optimiser state. */
+int rpcg_lp_set_params(rpcg_lpnet *net, const float *params);
+int rpcg_lp_get_params(rpcg_lpnet *net, float *params);
+
+/* Network outputs o (device, float32 [nb][N^3][4]) for nb systems A (host
+ * array of device CSR 7-point operators on the N^3 grid). RPCG_ERR_NOT_SPD if
+ * a diagonal entry is not positive. */
+int rpcg_lp_forward(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, float *o, void *stream);
+/* G and G^T of nb systems into caller-allocated device CSR (structure from
+ * rpcg_lp_pattern, values written as binary64). Waits for completion. */
+int rpcg_lp_factor(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, rpcg_csr *G, rpcg_csr *Gt, void *stream);
+/* Training loss (host, may be NULL) and its gradient with respect to the
+ * outputs (device, binary64 [nb][N^3][4], may be NULL), averaged over the nb
+ * systems and their nu vectors u (host array of nb * nu device pointers,
+ * system-major). Waits for completion. */
+int rpcg_lp_loss_grad(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, const double *const *u, int32_t nu,
+                      double eps, double *loss, double *dout, void *stream);
+/* Parameter gradient (device, float32 RPCG_LP_NPARAMS) for an output gradient
+ * dout (device, binary64 [nb][N^3][4], rounded to bfloat16 first). */
+int rpcg_lp_backward(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, const double *dout, float *grad,
+                     void *stream);
+/* One optimisation step (Adam, beta1 0.9, beta2 0.999, epsilon 1e-8, step
+ * size lr) on the loss of nb systems; *loss (host, may be NULL) receives the
+ * loss before the step. Waits for completion. */
+int rpcg_lp_train_step(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, const double *const *u, int32_t nu,
+                       double eps, float lr, double *loss, void *stream);
+
 /* Long-accumulator interface (Section 4.3, Listing 3: the per-process
  * accumulator that is summed as integers across processes, then rounded).
  * The accumulator is RPCG_ACC_DIGITS signed 64-bit digits; digit k has weight

@@ -1,0 +1,380 @@
+// C-ABI of the learned preconditioner (declared in include/rpcg.h): the
+// network object, its forward and backward passes, the factor G, the
+// training step. Host side only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rpcg.h"
+#include "context.hpp"
+#include "kernels.hpp"
+#include "lp_factor.hpp"
+
+using namespace rpcg;
+using namespace rpcg_host;
+
+static_assert(RPCG_LP_NPARAMS == LP_NPARAMS, "parameter count");
+
+struct rpcg_lpnet {
+    rpcg_ctx *ctx = nullptr;
+    int N = 0, max_batch = 0;
+    long long n = 0;        // N^3
+    int gnnz = 0;           // entries of G (and G^T)
+    int fwd_nb = 0;         // batch of the cached forward pass
+    int step = 0;           // Adam steps taken
+    static constexpr int DW_GRID = 256; // slots of the weight-gradient sums (fixed: fixed order)
+    Buffer params, grad, am, av, w1, w2, w3, w2t, w3t;
+    Buffer feat, s, pre1, h1, pre2, h2, o, do64, dob, d2, d1, pw, pb;
+    Buffer g_rp, g_col, gt_rp, gt_col, g_val, gt_val, vecs, scal;
+};
+
+namespace {
+
+// Structure of G (rows: -z, -y, -x, diagonal) and G^T (rows: diagonal, +x, +y, +z).
+void lp_pattern_host(int N, int32_t *grp, int32_t *gcol, int32_t *gtrp, int32_t *gtcol)
+{
+    const long long n = (long long)N * N * N, NN = (long long)N * N;
+    int p = 0, q = 0;
+    for (long long i = 0; i < n; ++i) {
+        const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / NN);
+        grp[i] = p;
+        if (z > 0) gcol[p++] = (int32_t)(i - NN);
+        if (y > 0) gcol[p++] = (int32_t)(i - N);
+        if (x > 0) gcol[p++] = (int32_t)(i - 1);
+        gcol[p++] = (int32_t)i;
+        gtrp[i] = q;
+        gtcol[q++] = (int32_t)i;
+        if (x < N - 1) gtcol[q++] = (int32_t)(i + 1);
+        if (y < N - 1) gtcol[q++] = (int32_t)(i + N);
+        if (z < N - 1) gtcol[q++] = (int32_t)(i + NN);
+    }
+    grp[n] = p;
+    gtrp[n] = q;
+}
+
+long long lp_nnz(long long N) { return 4 * N * N * N - 3 * N * N; }
+
+int check_batch(const rpcg_lpnet *L, int nb, const rpcg_csr *A)
+{
+    if (nb < 1 || nb > L->max_batch || !A) return RPCG_ERR_INVALID;
+    for (int k = 0; k < nb; ++k)
+        if (!valid_csr(&A[k]) || A[k].n != L->n) return RPCG_ERR_INVALID;
+    return RPCG_OK;
+}
+
+int lp_prep(rpcg_lpnet *L, hipStream_t s)
+{
+    RPCG_TRY(launch_lp_prep((const float *)L->params.p, (bf16_t *)L->w1.p, (bf16_t *)L->w2.p, (bf16_t *)L->w3.p,
+                            (bf16_t *)L->w2t.p, (bf16_t *)L->w3t.p, s));
+    return RPCG_OK;
+}
+
+int lp_forward(rpcg_lpnet *L, int nb, const rpcg_csr *A, hipStream_t s)
+{
+    int *bad = &L->ctx->info->flags;
+    RPCG_TRY(hipMemsetAsync(L->ctx->info, 0, sizeof(DotInfo), s));
+    for (int k = 0; k < nb; ++k)
+        RPCG_TRY(launch_lp_features(L->N, A[k].row_ptr, A[k].col_idx, A[k].val, (bf16_t *)L->feat.p + k * L->n * 4,
+                                    (float *)L->s.p + k * L->n, bad, s));
+    const float *p = (const float *)L->params.p;
+    RPCG_TRY(launch_lp_conv(4, 16, EPI_RELU, nb, L->N, (const bf16_t *)L->feat.p, (const bf16_t *)L->w1.p,
+                            p + LP_OFF_B1, nullptr, (float *)L->pre1.p, (bf16_t *)L->h1.p, s));
+    RPCG_TRY(launch_lp_conv(16, 16, EPI_RELU, nb, L->N, (const bf16_t *)L->h1.p, (const bf16_t *)L->w2.p,
+                            p + LP_OFF_B2, nullptr, (float *)L->pre2.p, (bf16_t *)L->h2.p, s));
+    RPCG_TRY(launch_lp_conv(16, 4, EPI_LINEAR, nb, L->N, (const bf16_t *)L->h2.p, (const bf16_t *)L->w3.p,
+                            p + LP_OFF_B3, nullptr, (float *)L->o.p, nullptr, s));
+    DotInfo inf;
+    RPCG_TRY(hipMemcpyAsync(&inf, L->ctx->info, sizeof inf, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    if (inf.flags) return RPCG_ERR_NOT_SPD;
+    L->fwd_nb = nb;
+    return RPCG_OK;
+}
+
+// G, G^T values of instance k into g_val / gt_val.
+int lp_factor_one(rpcg_lpnet *L, int k, double *g_val, double *gt_val, hipStream_t s)
+{
+    RPCG_TRY(launch_lp_factor(L->N, (const float *)L->o.p + k * L->n * 4, (const float *)L->s.p + k * L->n,
+                              (const int *)L->g_rp.p, (const int *)L->gt_rp.p, g_val, gt_val, s));
+    return RPCG_OK;
+}
+
+// Loss and dL/do (binary64, into do64) over the cached forward pass.
+int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *u, int nu, double eps, double *loss,
+                 hipStream_t s)
+{
+    const long long n = L->n;
+    double *V = (double *)L->vecs.p;
+    double *v = V, *y = V + n, *w = V + 2 * n, *r = V + 3 * n, *q = V + 4 * n;
+    double *G = (double *)L->g_val.p, *Gt = (double *)L->gt_val.p;
+    double *sc = (double *)L->scal.p; // uu, rr, loss
+    RPCG_TRY(hipMemsetAsync(L->do64.p, 0, sizeof(double) * 4 * n * nb, s));
+    RPCG_TRY(hipMemsetAsync(sc + 2, 0, sizeof(double), s));
+    rpcg_opts o;
+    rpcg_opts_default(&o);
+    o.fpe_size = 3;
+    LaunchCfg cd{};
+    cd.grid = (int)std::min<long long>(std::max<long long>((n + 2047) / 2048, 1), 8ll * L->ctx->num_cus);
+    cd.block = 256;
+    cd.early_exit = true;
+    cd.fpe_size = 3;
+    cd.fallback = true;
+    cd.xcd_parts = 1;
+    cd.stream = s;
+    const int *grp = (const int *)L->g_rp.p, *gcol = (const int *)L->g_col.p;
+    const int *gtrp = (const int *)L->gt_rp.p, *gtcol = (const int *)L->gt_col.p;
+    const double scale = 1.0 / ((double)nu * nb);
+    for (int k = 0; k < nb; ++k) {
+        int rc = lp_factor_one(L, k, G, Gt, s);
+        if (rc != RPCG_OK) return rc;
+        for (int m = 0; m < nu; ++m) {
+            const double *uk = u[(size_t)k * nu + m];
+            RPCG_TRY(launch_spmv_csr((int)n, A[k].row_ptr, A[k].col_idx, A[k].val, uk, v, s));   // v = A u
+            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, v, y, s));                          // y = G^T v
+            RPCG_TRY(launch_spmv_csr((int)n, grp, gcol, G, y, w, s));                             // G y
+            RPCG_TRY(launch_lp_resid(n, eps, w, v, uk, r, s));                                    // r
+            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, r, q, s));                          // q = G^T r
+            RPCG_TRY(launch_exdot(MODE_EXBLAS, n, uk, uk, sc, L->ctx->ws[0], L->ctx->ws_groups, L->ctx->info, cd));
+            RPCG_TRY(launch_exdot(MODE_EXBLAS, n, r, r, sc + 1, L->ctx->ws[0], L->ctx->ws_groups, L->ctx->info, cd));
+            RPCG_TRY(launch_lp_dodg(L->N, scale, sc, sc + 1, (const float *)L->o.p + k * n * 4,
+                                    (const float *)L->s.p + k * n, grp, G, r, y, v, q, (double *)L->do64.p + k * n * 4,
+                                    sc + 2, s));
+        }
+    }
+    if (loss) {
+        RPCG_TRY(hipMemcpyAsync(loss, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        RPCG_TRY(hipStreamSynchronize(s));
+    }
+    return RPCG_OK;
+}
+
+// Parameter gradient from the output gradient (bfloat16, in dob) over the cached forward pass.
+int lp_backward(rpcg_lpnet *L, int nb, hipStream_t s)
+{
+    const int N = L->N, G = rpcg_lpnet::DW_GRID;
+    float *gr = (float *)L->grad.p, *pw = (float *)L->pw.p, *pb = (float *)L->pb.p;
+    const float *pre1 = (const float *)L->pre1.p, *pre2 = (const float *)L->pre2.p;
+    // layer 3
+    RPCG_TRY(launch_lp_conv_dw(16, 4, nb, N, (const bf16_t *)L->h2.p, (const bf16_t *)L->dob.p, pw, pb, G, s));
+    RPCG_TRY(launch_lp_reduce(G, 4, 16, pw, pb, gr + LP_OFF_W3, gr + LP_OFF_B3, s));
+    RPCG_TRY(launch_lp_conv(4, 16, EPI_MASK, nb, N, (const bf16_t *)L->dob.p, (const bf16_t *)L->w3t.p, nullptr, pre2,
+                            nullptr, (bf16_t *)L->d2.p, s));
+    // layer 2
+    RPCG_TRY(launch_lp_conv_dw(16, 16, nb, N, (const bf16_t *)L->h1.p, (const bf16_t *)L->d2.p, pw, pb, G, s));
+    RPCG_TRY(launch_lp_reduce(G, 16, 16, pw, pb, gr + LP_OFF_W2, gr + LP_OFF_B2, s));
+    RPCG_TRY(launch_lp_conv(16, 16, EPI_MASK, nb, N, (const bf16_t *)L->d2.p, (const bf16_t *)L->w2t.p, nullptr, pre1,
+                            nullptr, (bf16_t *)L->d1.p, s));
+    // layer 1
+    RPCG_TRY(launch_lp_conv_dw(4, 16, nb, N, (const bf16_t *)L->feat.p, (const bf16_t *)L->d1.p, pw, pb, G, s));
+    RPCG_TRY(launch_lp_reduce(G, 16, 4, pw, pb, gr + LP_OFF_W1, gr + LP_OFF_B1, s));
+    return RPCG_OK;
+}
+
+int lp_create_body(rpcg_lpnet *L)
+{
+    const long long cells = L->n * L->max_batch;
+    const long long nz = lp_nnz(L->N);
+    L->gnnz = (int)nz;
+    for (Buffer *b : {&L->params, &L->grad, &L->am, &L->av}) RPCG_TRY(b->ensure(sizeof(float) * LP_NPARAMS));
+    RPCG_TRY(L->w1.ensure(sizeof(bf16_t) * LP_TAPS * 16 * 4));
+    RPCG_TRY(L->w2.ensure(sizeof(bf16_t) * LP_TAPS * 256));
+    RPCG_TRY(L->w3.ensure(sizeof(bf16_t) * LP_TAPS * 256));
+    RPCG_TRY(L->w2t.ensure(sizeof(bf16_t) * LP_TAPS * 256));
+    RPCG_TRY(L->w3t.ensure(sizeof(bf16_t) * LP_TAPS * 16 * 4));
+    RPCG_TRY(L->feat.ensure(sizeof(bf16_t) * 4 * cells));
+    RPCG_TRY(L->s.ensure(sizeof(float) * cells));
+    RPCG_TRY(L->pre1.ensure(sizeof(float) * 16 * cells));
+    RPCG_TRY(L->h1.ensure(sizeof(bf16_t) * 16 * cells));
+    RPCG_TRY(L->pre2.ensure(sizeof(float) * 16 * cells));
+    RPCG_TRY(L->h2.ensure(sizeof(bf16_t) * 16 * cells));
+    RPCG_TRY(L->o.ensure(sizeof(float) * 4 * cells));
+    RPCG_TRY(L->do64.ensure(sizeof(double) * 4 * cells));
+    RPCG_TRY(L->dob.ensure(sizeof(bf16_t) * 4 * cells));
+    RPCG_TRY(L->d2.ensure(sizeof(bf16_t) * 16 * cells));
+    RPCG_TRY(L->d1.ensure(sizeof(bf16_t) * 16 * cells));
+    RPCG_TRY(L->pw.ensure(sizeof(float) * rpcg_lpnet::DW_GRID * LP_TAPS * 256));
+    RPCG_TRY(L->pb.ensure(sizeof(float) * rpcg_lpnet::DW_GRID * 16));
+    RPCG_TRY(L->g_rp.ensure(sizeof(int) * (L->n + 1)));
+    RPCG_TRY(L->gt_rp.ensure(sizeof(int) * (L->n + 1)));
+    RPCG_TRY(L->g_col.ensure(sizeof(int) * nz));
+    RPCG_TRY(L->gt_col.ensure(sizeof(int) * nz));
+    RPCG_TRY(L->g_val.ensure(sizeof(double) * nz));
+    RPCG_TRY(L->gt_val.ensure(sizeof(double) * nz));
+    RPCG_TRY(L->vecs.ensure(sizeof(double) * 5 * L->n));
+    RPCG_TRY(L->scal.ensure(sizeof(double) * 8));
+    std::vector<int32_t> grp(L->n + 1), gcol(nz), gtrp(L->n + 1), gtcol(nz);
+    lp_pattern_host(L->N, grp.data(), gcol.data(), gtrp.data(), gtcol.data());
+    RPCG_TRY(hipMemcpy(L->g_rp.p, grp.data(), sizeof(int) * (L->n + 1), hipMemcpyHostToDevice));
+    RPCG_TRY(hipMemcpy(L->gt_rp.p, gtrp.data(), sizeof(int) * (L->n + 1), hipMemcpyHostToDevice));
+    RPCG_TRY(hipMemcpy(L->g_col.p, gcol.data(), sizeof(int) * nz, hipMemcpyHostToDevice));
+    RPCG_TRY(hipMemcpy(L->gt_col.p, gtcol.data(), sizeof(int) * nz, hipMemcpyHostToDevice));
+    RPCG_TRY(hipMemset(L->params.p, 0, sizeof(float) * LP_NPARAMS));
+    RPCG_TRY(hipMemset(L->am.p, 0, sizeof(float) * LP_NPARAMS));
+    RPCG_TRY(hipMemset(L->av.p, 0, sizeof(float) * LP_NPARAMS));
+    RPCG_TRY(hipDeviceSynchronize());
+    return lp_prep(L, nullptr);
+}
+
+} // namespace
+
+extern "C" {
+
+int64_t rpcg_lp_pattern_nnz(int32_t N) { return N < 1 ? -1 : lp_nnz(N); }
+
+int rpcg_lp_pattern(int32_t N, int32_t *g_row_ptr, int32_t *g_col, int32_t *gt_row_ptr, int32_t *gt_col)
+{
+    if (N < 1 || (long long)N * N * N > (1ll << 30) || !g_row_ptr || !g_col || !gt_row_ptr || !gt_col)
+        return RPCG_ERR_INVALID;
+    lp_pattern_host(N, g_row_ptr, g_col, gt_row_ptr, gt_col);
+    return RPCG_OK;
+}
+
+void rpcg_lp_destroy(rpcg_lpnet *L)
+{
+    if (!L) return;
+    hipSetDevice(L->ctx->device);
+    hipDeviceSynchronize();
+    for (Buffer *b : {&L->params, &L->grad, &L->am, &L->av, &L->w1, &L->w2, &L->w3, &L->w2t, &L->w3t, &L->feat, &L->s,
+                      &L->pre1, &L->h1, &L->pre2, &L->h2, &L->o, &L->do64, &L->dob, &L->d2, &L->d1, &L->pw, &L->pb,
+                      &L->g_rp, &L->g_col, &L->gt_rp, &L->gt_col, &L->g_val, &L->gt_val, &L->vecs, &L->scal})
+        b->release();
+    delete L;
+}
+
+int rpcg_lp_create(rpcg_ctx *c, int32_t N, int32_t max_batch, rpcg_lpnet **out)
+{
+    if (!out) return RPCG_ERR_INVALID;
+    *out = nullptr;
+    if (!c || N < 2 || max_batch < 1 || (long long)N * N * N * max_batch > (1ll << 30)) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    rpcg_lpnet *L = new (std::nothrow) rpcg_lpnet();
+    if (!L) return RPCG_ERR_OOM;
+    L->ctx = c;
+    L->N = N;
+    L->max_batch = max_batch;
+    L->n = (long long)N * N * N;
+    int rc = lp_create_body(L);
+    if (rc != RPCG_OK) { rpcg_lp_destroy(L); return rc; }
+    *out = L;
+    return RPCG_OK;
+}
+
+int rpcg_lp_set_params(rpcg_lpnet *L, const float *params)
+{
+    if (!L || !params) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(L->ctx->device));
+    RPCG_TRY(hipMemcpy(L->params.p, params, sizeof(float) * LP_NPARAMS, hipMemcpyHostToDevice));
+    RPCG_TRY(hipMemset(L->am.p, 0, sizeof(float) * LP_NPARAMS));
+    RPCG_TRY(hipMemset(L->av.p, 0, sizeof(float) * LP_NPARAMS));
+    L->step = 0;
+    int rc = lp_prep(L, nullptr);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(hipDeviceSynchronize());
+    return RPCG_OK;
+}
+
+int rpcg_lp_get_params(rpcg_lpnet *L, float *params)
+{
+    if (!L || !params) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(L->ctx->device));
+    RPCG_TRY(hipMemcpy(params, L->params.p, sizeof(float) * LP_NPARAMS, hipMemcpyDeviceToHost));
+    return RPCG_OK;
+}
+
+int rpcg_lp_forward(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, float *o, void *stream)
+{
+    if (!L) return RPCG_ERR_INVALID;
+    int rc = check_batch(L, nb, A);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(hipSetDevice(L->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    rc = lp_forward(L, nb, A, s);
+    if (rc != RPCG_OK) return rc;
+    if (o) RPCG_TRY(hipMemcpyAsync(o, L->o.p, sizeof(float) * 4 * L->n * nb, hipMemcpyDeviceToDevice, s));
+    return RPCG_OK;
+}
+
+int rpcg_lp_factor(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, rpcg_csr *G, rpcg_csr *Gt, void *stream)
+{
+    if (!L || !G || !Gt) return RPCG_ERR_INVALID;
+    int rc = check_batch(L, nb, A);
+    if (rc != RPCG_OK) return rc;
+    for (int k = 0; k < nb; ++k)
+        if (G[k].n != L->n || Gt[k].n != L->n || G[k].nnz != L->gnnz || Gt[k].nnz != L->gnnz || !G[k].val || !Gt[k].val)
+            return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(L->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    rc = lp_forward(L, nb, A, s);
+    if (rc != RPCG_OK) return rc;
+    for (int k = 0; k < nb; ++k) {
+        rc = lp_factor_one(L, k, (double *)G[k].val, (double *)Gt[k].val, s);
+        if (rc != RPCG_OK) return rc;
+    }
+    RPCG_TRY(hipStreamSynchronize(s));
+    return RPCG_OK;
+}
+
+int rpcg_lp_loss_grad(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const double *const *u, int32_t nu, double eps,
+                      double *loss, double *dout, void *stream)
+{
+    if (!L || !u || nu < 1 || !(eps >= 0.0)) return RPCG_ERR_INVALID;
+    int rc = check_batch(L, nb, A);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(hipSetDevice(L->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    rc = lp_forward(L, nb, A, s);
+    if (rc != RPCG_OK) return rc;
+    rc = lp_loss_grad(L, nb, A, u, nu, eps, loss, s);
+    if (rc != RPCG_OK) return rc;
+    if (dout) RPCG_TRY(hipMemcpyAsync(dout, L->do64.p, sizeof(double) * 4 * L->n * nb, hipMemcpyDeviceToDevice, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    return RPCG_OK;
+}
+
+int rpcg_lp_backward(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const double *dout, float *grad, void *stream)
+{
+    if (!L || !dout || !grad) return RPCG_ERR_INVALID;
+    int rc = check_batch(L, nb, A);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(hipSetDevice(L->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    rc = lp_forward(L, nb, A, s);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(launch_lp_to_bf16(4 * L->n * nb, dout, (bf16_t *)L->dob.p, s));
+    rc = lp_backward(L, nb, s);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(hipMemcpyAsync(grad, L->grad.p, sizeof(float) * LP_NPARAMS, hipMemcpyDeviceToDevice, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    return RPCG_OK;
+}
+
+int rpcg_lp_train_step(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const double *const *u, int32_t nu, double eps,
+                       float lr, double *loss, void *stream)
+{
+    if (!L || !u || nu < 1 || !(eps >= 0.0) || !(lr >= 0.f)) return RPCG_ERR_INVALID;
+    int rc = check_batch(L, nb, A);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(hipSetDevice(L->ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    rc = lp_forward(L, nb, A, s);
+    if (rc != RPCG_OK) return rc;
+    rc = lp_loss_grad(L, nb, A, u, nu, eps, nullptr, s);
+    if (rc != RPCG_OK) return rc;
+    RPCG_TRY(launch_lp_to_bf16(4 * L->n * nb, (const double *)L->do64.p, (bf16_t *)L->dob.p, s));
+    rc = lp_backward(L, nb, s);
+    if (rc != RPCG_OK) return rc;
+    L->step += 1;
+    RPCG_TRY(launch_lp_adam(LP_NPARAMS, (float *)L->params.p, (const float *)L->grad.p, (float *)L->am.p,
+                            (float *)L->av.p, lr, 0.9f, 0.999f, 1e-8f, L->step, s));
+    rc = lp_prep(L, s);
+    if (rc != RPCG_OK) return rc;
+    if (loss) RPCG_TRY(hipMemcpyAsync(loss, (double *)L->scal.p + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    return RPCG_OK;
+}
+
+} // extern "C"

@@ -134,6 +134,28 @@ def lib():
         L.rpcg_batch_tune.restype = ctypes.c_int
         L.rpcg_batch_solve.argtypes = [P, P, P, P, P, ctypes.POINTER(_BatchStats), P]
         L.rpcg_batch_solve.restype = ctypes.c_int
+        L.rpcg_lp_pattern_nnz.argtypes = [I32]
+        L.rpcg_lp_pattern_nnz.restype = I64
+        L.rpcg_lp_pattern.argtypes = [I32, P, P, P, P]
+        L.rpcg_lp_pattern.restype = ctypes.c_int
+        L.rpcg_lp_create.argtypes = [P, I32, I32, ctypes.POINTER(P)]
+        L.rpcg_lp_create.restype = ctypes.c_int
+        L.rpcg_lp_destroy.argtypes = [P]
+        L.rpcg_lp_destroy.restype = None
+        L.rpcg_lp_set_params.argtypes = [P, P]
+        L.rpcg_lp_set_params.restype = ctypes.c_int
+        L.rpcg_lp_get_params.argtypes = [P, P]
+        L.rpcg_lp_get_params.restype = ctypes.c_int
+        L.rpcg_lp_forward.argtypes = [P, I32, P, P, P]
+        L.rpcg_lp_forward.restype = ctypes.c_int
+        L.rpcg_lp_factor.argtypes = [P, I32, P, P, P, P]
+        L.rpcg_lp_factor.restype = ctypes.c_int
+        L.rpcg_lp_loss_grad.argtypes = [P, I32, P, P, I32, ctypes.c_double, P, P, P]
+        L.rpcg_lp_loss_grad.restype = ctypes.c_int
+        L.rpcg_lp_backward.argtypes = [P, I32, P, P, P, P]
+        L.rpcg_lp_backward.restype = ctypes.c_int
+        L.rpcg_lp_train_step.argtypes = [P, I32, P, P, I32, ctypes.c_double, ctypes.c_float, P, P]
+        L.rpcg_lp_train_step.restype = ctypes.c_int
         L.rpcg_exdot_partial.argtypes = [P, I64, P, P, P, P]
         L.rpcg_exdot_partial.restype = ctypes.c_int
         L.rpcg_acc_round.argtypes = [P, P, P, P]
@@ -146,7 +168,9 @@ def lib():
 EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot",
             "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_factored", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
             "rpcg_batch_create", "rpcg_batch_destroy", "rpcg_batch_get_tuning", "rpcg_batch_set_tuning",
-            "rpcg_batch_tune", "rpcg_batch_solve", "rpcg_exdot_partial", "rpcg_acc_round"]
+            "rpcg_batch_tune", "rpcg_batch_solve", "rpcg_lp_pattern_nnz", "rpcg_lp_pattern", "rpcg_lp_create",
+            "rpcg_lp_destroy", "rpcg_lp_set_params", "rpcg_lp_get_params", "rpcg_lp_forward", "rpcg_lp_factor",
+            "rpcg_lp_loss_grad", "rpcg_lp_backward", "rpcg_lp_train_step", "rpcg_exdot_partial", "rpcg_acc_round"]
 
 
 def status_string(s: int) -> str:
@@ -503,3 +527,130 @@ def pcg_solve_factored(A: CSR, G: CSR, Gt: CSR, eps: float, b: torch.Tensor, x0:
     if rc < 0 and raise_on_error:
         raise RpcgError(rc, "rpcg_pcg_solve_factored")
     return x, info
+
+
+LP_NPARAMS = 10404
+
+
+def _csr_array(mats):
+    arr = (_Csr * len(mats))()
+    for k, A in enumerate(mats):
+        arr[k] = A._c()
+    return arr
+
+
+class LearnedPreconditioner:
+    """The network of rpcg_lp_* for systems on N^3 grids (7-point operators)."""
+
+    def __init__(self, N: int, max_batch: int = 1, device=None, params=None):
+        import numpy as np
+        self.N = int(N)
+        self.max_batch = int(max_batch)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        h = ctypes.c_void_p()
+        rc = lib().rpcg_lp_create(context(self.device.index), self.N, self.max_batch, ctypes.byref(h))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_create")
+        self._h = h
+        n = self.N ** 3
+        nnz = int(lib().rpcg_lp_pattern_nnz(self.N))
+        grp = np.zeros(n + 1, np.int32)
+        gcol = np.zeros(nnz, np.int32)
+        gtrp = np.zeros(n + 1, np.int32)
+        gtcol = np.zeros(nnz, np.int32)
+        rc = lib().rpcg_lp_pattern(self.N, grp.ctypes.data, gcol.ctypes.data, gtrp.ctypes.data, gtcol.ctypes.data)
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_pattern")
+        self.pattern = (grp, gcol, gtrp, gtcol)
+        self._grp = torch.from_numpy(grp).to(self.device)
+        self._gcol = torch.from_numpy(gcol).to(self.device)
+        self._gtrp = torch.from_numpy(gtrp).to(self.device)
+        self._gtcol = torch.from_numpy(gtcol).to(self.device)
+        if params is not None:
+            self.set_params(params)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rpcg_lp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == LP_NPARAMS
+        rc = lib().rpcg_lp_set_params(self._h, p.ctypes.data)
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_set_params")
+
+    def get_params(self):
+        import numpy as np
+        p = np.zeros(LP_NPARAMS, np.float32)
+        rc = lib().rpcg_lp_get_params(self._h, p.ctypes.data)
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_get_params")
+        return p
+
+    def forward(self, mats):
+        o = torch.empty(len(mats), self.N ** 3, 4, dtype=torch.float32, device=self.device)
+        arr = _csr_array(mats)
+        rc = lib().rpcg_lp_forward(self._h, len(mats), ctypes.cast(arr, ctypes.c_void_p), o.data_ptr(),
+                                   _stream(self.device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_forward")
+        return o
+
+    def factor(self, mats):
+        """[(G, Gt)] as CSR on the device for each system."""
+        nnz = self._gcol.numel()
+        Gs = [CSR(self.N ** 3, self._grp, self._gcol, torch.empty(nnz, dtype=torch.float64, device=self.device))
+              for _ in mats]
+        Gts = [CSR(self.N ** 3, self._gtrp, self._gtcol, torch.empty(nnz, dtype=torch.float64, device=self.device))
+               for _ in mats]
+        arr, ga, gta = _csr_array(mats), _csr_array(Gs), _csr_array(Gts)
+        rc = lib().rpcg_lp_factor(self._h, len(mats), ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(ga, ctypes.c_void_p),
+                                  ctypes.cast(gta, ctypes.c_void_p), _stream(self.device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_factor")
+        return list(zip(Gs, Gts))
+
+    def loss_grad(self, mats, us, eps=1e-6):
+        """us: per system a list of vectors. Returns (loss, dL/do [nb][N^3][4] float64)."""
+        nu = len(us[0])
+        flat = [u for row in us for u in row]
+        dout = torch.empty(len(mats), self.N ** 3, 4, dtype=torch.float64, device=self.device)
+        loss = ctypes.c_double(0.0)
+        arr = _csr_array(mats)
+        rc = lib().rpcg_lp_loss_grad(self._h, len(mats), ctypes.cast(arr, ctypes.c_void_p),
+                                     ctypes.cast(_ptr_array(flat), ctypes.c_void_p), nu, float(eps), ctypes.byref(loss),
+                                     dout.data_ptr(), _stream(self.device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_loss_grad")
+        return loss.value, dout
+
+    def backward(self, mats, dout):
+        _check(dout, torch.float64, "dout")
+        grad = torch.empty(LP_NPARAMS, dtype=torch.float32, device=self.device)
+        arr = _csr_array(mats)
+        rc = lib().rpcg_lp_backward(self._h, len(mats), ctypes.cast(arr, ctypes.c_void_p), dout.data_ptr(),
+                                    grad.data_ptr(), _stream(self.device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_backward")
+        return grad
+
+    def train_step(self, mats, us, lr, eps=1e-6):
+        nu = len(us[0])
+        flat = [u for row in us for u in row]
+        loss = ctypes.c_double(0.0)
+        arr = _csr_array(mats)
+        rc = lib().rpcg_lp_train_step(self._h, len(mats), ctypes.cast(arr, ctypes.c_void_p),
+                                      ctypes.cast(_ptr_array(flat), ctypes.c_void_p), nu, float(eps), float(lr),
+                                      ctypes.byref(loss), _stream(self.device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_lp_train_step")
+        return loss.value

@@ -1,0 +1,159 @@
+"""GPU checks of the learned preconditioner against the CPU oracle
+(oracle/lpnet.py): network outputs, loss and output gradient, parameter
+gradient (tolerances: the two sides round to bfloat16 at the same points and
+differ in accumulation order); G invariant to the batch it is computed in;
+training steps reproducible; the preconditioned solve with the network's G
+bit-identical to the oracle given G."""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import lpnet
+from rpcg_workloads import CSRHost, grf_diffusion_csr, uniform_pm1
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2005_07282_amd import rpcg
+    rpcg.context(0)
+    return rpcg
+
+
+def params(seed, w3=0.05):
+    rng = np.random.default_rng(seed)
+    q = lpnet.split(lpnet.init_params(seed).astype(np.float64))
+    q["W3"] = rng.standard_normal(q["W3"].shape) * w3
+    q["b1"] = rng.standard_normal(16) * 0.1
+    q["b2"] = rng.standard_normal(16) * 0.1
+    q["b3"] = rng.standard_normal(4) * 0.1
+    return lpnet.join(q).astype(np.float32)
+
+
+def systems(N, seeds):
+    return [grf_diffusion_csr(N, s)[0] for s in seeds]
+
+
+@pytest.fixture(scope="module")
+def net10(R):
+    net = R.LearnedPreconditioner(10, max_batch=3)
+    net.set_params(params(1))
+    return net
+
+
+def test_forward_matches_oracle(R, net10):
+    N = 10
+    As = systems(N, [11, 12])
+    o = net10.forward([R.CSR.from_host(A) for A in As]).cpu().numpy()
+    p = params(1).astype(np.float64)
+    for k, A in enumerate(As):
+        ref = lpnet.forward(p, lpnet.features(A, N), bf16=True)["o"].reshape(-1, 4)
+        scale = np.abs(ref).max()
+        err = np.abs(o[k] - ref)
+        print(f"forward system {k}: max |diff| / max |o| = {err.max() / scale:.2e}, "
+              f"elements off by > 1e-3 relative: {np.mean(err > 1e-3 * scale):.4f}", flush=True)
+        assert err.max() <= 3e-2 * scale
+        assert np.mean(err > 1e-3 * scale) < 0.01
+
+
+def test_loss_grad_matches_oracle(R, net10):
+    N = 10
+    As = systems(N, [13])
+    mats = [R.CSR.from_host(A) for A in As]
+    us = [[uniform_pm1(30 + m, As[0].n) for m in range(2)]]
+    ud = [[torch.from_numpy(u).cuda() for u in row] for row in us]
+    loss, dout = net10.loss_grad(mats, ud, eps=1e-6)
+    o = net10.forward(mats).cpu().numpy()[0]
+    G, dgdo = lpnet.factor(As[0], N, o)
+    L, dG = lpnet.loss_grad(As[0], G, us[0], 1e-6)
+    do = lpnet.do_from_dg(G, dG, dgdo, N).reshape(-1, 4)
+    print(f"loss gpu {loss:.12g} oracle {L:.12g}", flush=True)
+    # the exponential of the diagonal output is the only step not correctly
+    # rounded on both sides (last-bit differences of G_ii)
+    assert abs(loss - L) <= 1e-6 * abs(L)
+    d = dout.cpu().numpy()[0]
+    print(f"dL/do: max |diff| / max = {np.max(np.abs(d - do)) / np.max(np.abs(do)):.2e}", flush=True)
+    assert np.max(np.abs(d - do)) <= 1e-5 * np.max(np.abs(do))
+
+
+def test_backward_matches_oracle(R, net10):
+    N = 10
+    As = systems(N, [14, 15])
+    mats = [R.CSR.from_host(A) for A in As]
+    rng = np.random.default_rng(5)
+    dout = rng.standard_normal((2, N ** 3, 4))
+    g = net10.backward(mats, torch.from_numpy(dout).cuda()).cpu().numpy().astype(np.float64)
+    p = params(1).astype(np.float64)
+    ref = np.zeros(lpnet.NPARAMS)
+    for k, A in enumerate(As):
+        c = lpnet.forward(p, lpnet.features(A, N), bf16=True)
+        ref += lpnet.backward(c, dout[k].reshape(N, N, N, 4))
+    off = 0
+    for name, shape in lpnet.SHAPES:
+        m = int(np.prod(shape))
+        a, b = g[off:off + m], ref[off:off + m]
+        rel = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print(f"gradient {name}: relative difference {rel:.2e}", flush=True)
+        assert rel < 2e-2, name
+        off += m
+
+
+def test_factor_independent_of_batch(R, net10):
+    N = 10
+    As = systems(N, [16, 17, 18])
+    mats = [R.CSR.from_host(A) for A in As]
+    together = net10.factor(mats)
+    alone = net10.factor([mats[1]])[0]
+    G1, Gt1 = together[1]
+    assert torch.equal(G1.val, alone[0].val) and torch.equal(Gt1.val, alone[1].val)
+    # G^T is the transpose of G, entry for entry
+    grp, gcol, gtrp, gtcol = net10.pattern
+    Gs = sp.csr_matrix((G1.val.cpu().numpy(), gcol, grp), shape=(N ** 3, N ** 3))
+    Gts = sp.csr_matrix((Gt1.val.cpu().numpy(), gtcol, gtrp), shape=(N ** 3, N ** 3))
+    assert (Gs.T != Gts).nnz == 0
+
+
+def test_training_reproducible_and_learning(R):
+    N = 12
+    As = systems(N, [21, 22, 23, 24])
+    mats = [R.CSR.from_host(A) for A in As]
+    us = []
+    for k, A in enumerate(As):
+        # Krylov vectors: early Jacobi-PCG iterates of a random right-hand side
+        b = torch.from_numpy(uniform_pm1(40 + k, A.n)).cuda()
+        row = []
+        for it in (3, 10):
+            x, _ = R.pcg_solve(mats[k], b, mode="exblas", maxit=it, tol=1e-14, history=False, raise_on_error=False)
+            row.append(x)
+        us.append(row)
+    runs = []
+    for rep in range(2):
+        net = R.LearnedPreconditioner(N, max_batch=4, params=lpnet.init_params(3))
+        losses = [net.train_step(mats, us, lr=1e-3) for _ in range(30)]
+        runs.append((losses, net.get_params()))
+        net.close()
+    (l1, p1), (l2, p2) = runs
+    print("loss", l1[0], "->", l1[-1], flush=True)
+    assert l1 == l2 and np.array_equal(p1, p2)  # fixed-order reductions: bit-reproducible training
+    assert l1[-1] < 0.5 * l1[0]
+
+
+def test_solve_with_network_factor_bitexact(R, orc, net10):
+    N = 10
+    A = systems(N, [19])[0]
+    (G, Gt), = net10.factor([R.CSR.from_host(A)])
+    grp, gcol, gtrp, gtcol = net10.pattern
+    Gh = CSRHost(N ** 3, grp, gcol, G.val.cpu().numpy())
+    Gth = CSRHost(N ** 3, gtrp, gtcol, Gt.val.cpu().numpy())
+    b = uniform_pm1(50, A.n)
+    ref = orc.pcg_factored(A, Gh, Gth, 1e-6, b, tol=1e-10, maxit=3000)
+    x, info = R.pcg_solve_factored(R.CSR.from_host(A), G, Gt, 1e-6, torch.from_numpy(b).cuda(), tol=1e-10,
+                                   maxit=3000, raise_on_error=False)
+    assert info["status"] == ref["status"] and info["iterations"] == ref["iters"]
+    assert np.array_equal(info["hist"].numpy(), ref["hist"])
+    assert np.array_equal(x.cpu().numpy(), ref["x"])

@@ -99,6 +99,25 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.rpcg_batch_tune(None, None, 10, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_batch_set_tuning(None, None) == rpcg.ERR_INVALID
     L.rpcg_batch_destroy(None)
+    assert L.rpcg_lp_create(None, 8, 1, None) == rpcg.ERR_INVALID
+    assert L.rpcg_lp_train_step(None, 1, None, None, 1, 0.0, 0.0, None, None) == rpcg.ERR_INVALID
+    L.rpcg_lp_destroy(None)
+
+
+def test_lp_pattern_host(L):
+    import numpy as np
+    from paper_2005_07282_amd import rpcg
+    N = 3
+    nnz = L.rpcg_lp_pattern_nnz(N)
+    assert nnz == 4 * 27 - 3 * 9
+    a, b, c, d = (np.zeros(28, np.int32), np.zeros(nnz, np.int32), np.zeros(28, np.int32), np.zeros(nnz, np.int32))
+    assert L.rpcg_lp_pattern(N, a.ctypes.data, b.ctypes.data, c.ctypes.data, d.ctypes.data) == 0
+    import scipy.sparse as sp
+    G = sp.csr_matrix((np.ones(nnz), b, a), shape=(27, 27))
+    Gt = sp.csr_matrix((np.ones(nnz), d, c), shape=(27, 27))
+    assert (G.T != Gt).nnz == 0
+    assert sp.triu(G, 1).nnz == 0 and G.diagonal().all()
+    assert rpcg.LP_NPARAMS == 10404
     L.rpcg_destroy(None)
 
 
