@@ -212,6 +212,65 @@ def run_batched(seed, rpcg, torch, dev):
     return out
 
 
+LP_FWD_FLOP_PER_CELL = 2 * 27 * (4 * 16 + 16 * 16 + 16 * 4)  # three convolutions, algorithmic
+
+
+def run_learned(n_eval, rpcg, torch, dev):
+    """Learned preconditioner (committed trained parameters) against Jacobi:
+    exact-dot PCG to 1e-10 on held-out 64^3 log-normal diffusion instances;
+    throughput of the bfloat16 MFMA network (forward, training step)."""
+    from paper_2005_07282_amd import learned
+    if not os.path.exists(learned.PARAMS_FILE):
+        log("[bench] learned preconditioner: no trained parameters, skipped")
+        return None
+    N = 64
+    params = learned.load_params()
+    log(f"[bench] learned preconditioner: {n_eval} held-out instances of {N}^3")
+    ev = learned.Dataset(rpcg, torch, N, [learned.EVAL_SEED0 + k for k in range(n_eval)], dev)
+    net = rpcg.LearnedPreconditioner(N, max_batch=8, params=params)
+    learned.evaluate(rpcg, torch, net, ev, limit=1)  # warm-up
+    rows = learned.evaluate(rpcg, torch, net, ev)
+    out = learned.summarize(rows)
+    # network throughput: forward of 8 systems; one training step on 8 systems (separate copy)
+    nb = min(8, n_eval)
+    mats = ev.mats[:nb]
+    net.forward(mats)
+    reps = 5
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        net.forward(mats)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t) * 1e3 / reps
+    from rpcg_workloads import uniform_pm1
+    us = [[torch.from_numpy(uniform_pm1(900 + 7 * k + j, ev.n)).to(dev) for j in range(4)] for k in range(nb)]
+    tnet = rpcg.LearnedPreconditioner(N, max_batch=nb, params=params)
+    tnet.train_step(mats, us, lr=0.0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        tnet.train_step(mats, us, lr=0.0)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t) * 1e3 / reps
+    tnet.close()
+    net.close()
+    flop = LP_FWD_FLOP_PER_CELL * ev.n * nb
+    out.update({
+        "workload": f"7-point diffusion, exp(1.5 GRF) coefficients (correlation 8 cells), {N}^3, held-out grid seeds "
+                    f"{learned.EVAL_SEED0}..{learned.EVAL_SEED0 + n_eval - 1}, b ~ U[-1,1), exact dots, tol 1e-10, "
+                    f"M^-1 = G G^T + 1e-6 I",
+        "forward_ms_8_systems": round(fwd_ms, 3),
+        "forward_TFLOP_s_bf16": round(flop / (fwd_ms * 1e-3) / 1e12, 2),
+        "forward_frac_of_bf16_peak": round(flop / (fwd_ms * 1e-3) / 2.5e15, 4),
+        "train_step_ms_8_systems_4_vectors": round(step_ms, 3),
+    })
+    log(f"[bench]   iterations Jacobi {out['jacobi_iterations_mean']:.1f}, learned {out['learned_iterations_mean']:.1f}; "
+        f"time ratio {out['time_ratio_incl_factor']:.3f}")
+    del ev
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -228,6 +287,10 @@ def main():
                     help="seed of the batched workload (64 systems, 16^3..96^3); -1 = skip")
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched section and print its JSON (for a separate kernel trace)")
+    ap.add_argument("--lp-eval", type=int, default=20,
+                    help="held-out 64^3 instances for the learned-preconditioner section (0 = skip)")
+    ap.add_argument("--lp-only", action="store_true",
+                    help="run only the learned-preconditioner section and print its JSON")
     ap.add_argument("--mixed-only", action="store_true",
                     help="run only the mixed-precision section and print its JSON (for a separate kernel trace)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -257,6 +320,9 @@ def main():
         return
     if args.batch_only:
         print(json.dumps(run_batched(args.batch_seed, rpcg, torch, dev)), flush=True)
+        return
+    if args.lp_only:
+        print(json.dumps(run_learned(args.lp_eval, rpcg, torch, dev)), flush=True)
         return
 
     N = args.grid
@@ -373,6 +439,7 @@ def main():
 
     mixed = run_mixed_precision(args.ir_grid, rpcg, torch, dev) if args.ir_grid > 0 else None
     batched = run_batched(args.batch_seed, rpcg, torch, dev) if args.batch_seed >= 0 else None
+    learned_pc = run_learned(args.lp_eval, rpcg, torch, dev) if args.lp_eval > 0 else None
 
     traffic = k1_traffic() if N == 160 else None
     line = {
@@ -404,6 +471,7 @@ def main():
             "exdot": exd,
             "mixed_precision": mixed,
             "batched": batched,
+            "learned_preconditioner": learned_pc,
         },
         "roofline": {
             "bound": "hbm",

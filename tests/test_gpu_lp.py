@@ -157,3 +157,20 @@ def test_solve_with_network_factor_bitexact(R, orc, net10):
     assert info["status"] == ref["status"] and info["iterations"] == ref["iters"]
     assert np.array_equal(info["hist"].numpy(), ref["hist"])
     assert np.array_equal(x.cpu().numpy(), ref["x"])
+
+
+@pytest.mark.slow
+def test_trained_network_beats_jacobi(R):
+    """The committed parameters (trained on 2,000 instances of 64^3) against
+    Jacobi on held-out instances: fewer exact-dot PCG iterations to 1e-10, the
+    same solution to 1e-8."""
+    from paper_2005_07282_amd import learned
+    ev = learned.Dataset(R, torch, 64, [learned.EVAL_SEED0 + 150 + k for k in range(4)], torch.device("cuda:0"))
+    net = R.LearnedPreconditioner(64, max_batch=1, params=learned.load_params())
+    rows = learned.evaluate(R, torch, net, ev)
+    net.close()
+    for r in rows:
+        print("held-out: Jacobi", r["jacobi_it"], "learned", r["learned_it"], flush=True)
+        assert r["status"] == (0, 0)
+        assert r["learned_it"] < 0.8 * r["jacobi_it"]
+        assert r["max_rel_diff"] < 1e-8
