@@ -212,6 +212,102 @@ def run_batched(seed, rpcg, torch, dev):
     return out
 
 
+def run_stress(n, w, n_ill, w_ill, rpcg, torch, dev):
+    """The paper's stress workloads. Band transform (Section 5.1, bandL =
+    bandU = w, b = A 1, x0 = 0, tol 1e-8): plain, exact-dot and FPE PCG, per
+    iteration cost and overheads. Ill-conditioned band (Section 5.3: first
+    row and column scaled by 2^16, condition number about 1e12, at the size
+    of Table 3): tau history of the exact modes against plain's, as Table 3
+    prints it."""
+    import numpy as np
+    from rpcg_workloads import band_csr, scale_first
+
+    def band_system(nn, ww, sigma):
+        A = band_csr(nn, ww)
+        if sigma != 1.0:
+            A = scale_first(A, sigma)
+        Ad = rpcg.CSR.from_host(A, dev)
+        nnz = int(A.row_ptr[-1])
+        del A
+        bd = rpcg.spmv(Ad, torch.ones(nn, dtype=torch.float64, device=dev))  # integers: exact in any order
+        return Ad, bd, nnz
+
+    def solve(Ad, bd, mode, p=0):
+        rpcg.pcg_solve(Ad, bd, mode=mode, maxit=2, tol=1e-8, fpe_size=p, history=False, raise_on_error=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, info = rpcg.pcg_solve(Ad, bd, mode=mode, tol=1e-8, maxit=20000, fpe_size=p, history=True, timing=1)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) * 1e3
+        it = max(1, info["iterations"])
+        return x, info, {"iterations": info["iterations"], "solve_ms": round(wall, 2),
+                         "setup_ms": round(info["setup_ms"], 2),
+                         "ms_per_iteration": round(info["loop_ms"] / it, 5),
+                         "k_spmv_dot_ms": round(info["k_spmv_dot_ms"] / max(1, info["k_launches"]), 5),
+                         "fpe_escapes": info["fpe_escapes"], "fallbacks": info["fallbacks"]}
+
+    out = {}
+    log(f"[bench] stress: band n={n} w={w}")
+    t = time.time()
+    Ad, bd, nnz = band_system(n, w, 1.0)
+    log(f"[bench]   nnz={nnz} ({time.time() - t:.1f}s)")
+    p_auto, rng = rpcg.fpe_size_auto(Ad, bd)
+    runs, xs, hs = {}, {}, {}
+    for mode, p in (("plain", 0), ("exblas", 0), ("fpe", p_auto)):
+        xs[mode], info, runs[mode] = solve(Ad, bd, mode, p)
+        hs[mode] = info["hist"]
+        log(f"[bench]   {mode}: {runs[mode]['iterations']} it, {runs[mode]['ms_per_iteration']} ms/it")
+    k1_bytes_band = 10 * nnz + 4 * (n + 1) + 16 * n  # 16-bit codes + values, row pointers, d, w (SELL-64)
+    out["band"] = {
+        "workload": f"band matrix n={n}, bandL = bandU = {w} (nnz={nnz}), 2w+1 on the diagonal, -1 in the band, "
+                    f"b = A 1, x0 = 0, tol 1e-8",
+        "fpe_size_auto": p_auto, "exponent_range": rng,
+        "runs": runs,
+        "exblas_over_plain": round(runs["exblas"]["ms_per_iteration"] / runs["plain"]["ms_per_iteration"], 4),
+        "fpe_over_plain": round(runs["fpe"]["ms_per_iteration"] / runs["plain"]["ms_per_iteration"], 4),
+        "k_spmv_dot_GB_s_exblas": round(k1_bytes_band / (runs["exblas"]["k_spmv_dot_ms"] * 1e-3) / 1e9, 1),
+        "exblas_fpe_identical": bool(torch.equal(xs["exblas"], xs["fpe"]) and torch.equal(hs["exblas"], hs["fpe"])),
+    }
+    del Ad, bd, xs
+    torch.cuda.empty_cache()
+    if n_ill > 0:
+        sigma = 2.0 ** 16
+        log(f"[bench] stress: ill-conditioned band n={n_ill} w={w_ill} sigma=2^16")
+        t = time.time()
+        Ad, bd, nnz = band_system(n_ill, w_ill, sigma)
+        log(f"[bench]   nnz={nnz} ({time.time() - t:.1f}s)")
+        p_auto, rng = rpcg.fpe_size_auto(Ad, bd)
+        runs, xs, hs = {}, {}, {}
+        for mode, p in (("plain", 0), ("exblas", 0), ("fpe", p_auto)):
+            xs[mode], info, runs[mode] = solve(Ad, bd, mode, p)
+            hs[mode] = info["hist"].numpy()
+            log(f"[bench]   {mode}: {runs[mode]['iterations']} it")
+        escapes = {}
+        for p in range(1, 9):
+            xp, info = rpcg.pcg_solve(Ad, bd, mode="fpe", tol=1e-8, maxit=20000, fpe_size=p, history=False)
+            escapes[str(p)] = {"escapes": info["fpe_escapes"], "fallbacks": info["fallbacks"],
+                               "identical_to_exblas": bool(torch.equal(xp, xs["exblas"]))}
+        he, hp = hs["exblas"], hs["plain"]
+        k = min(len(he), len(hp))
+        show = sorted({0, 2, 9, 10, k // 2, len(he) - 1} & set(range(len(he))))
+        out["ill_conditioned"] = {
+            "workload": f"band matrix n={n_ill}, bandL = bandU = {w_ill} (nnz={nnz}), first row and column "
+                        f"scaled by 2^16 (condition number about {sigma ** 2 * (2 * w_ill + 1):.1e}), "
+                        f"b = A 1, x0 = 0, tol 1e-8",
+            "fpe_size_auto": p_auto, "exponent_range": rng,
+            "runs": runs,
+            "exblas_fpe_identical": bool(torch.equal(xs["exblas"], xs["fpe"]) and np.array_equal(he, hs["fpe"])),
+            "fpe_escapes_by_p": escapes,
+            "plain_tau_entries_differing": int(np.sum(he[:k].view(np.uint64) != hp[:k].view(np.uint64))),
+            "plain_tau_max_rel_diff": float(np.max(np.abs(hp[:k] - he[:k]) / he[:k])),
+            "tau_hex": {str(j): {"exact": float(he[j]).hex(),
+                                 "plain": float(hp[j]).hex() if j < len(hp) else None} for j in show},
+        }
+        del Ad, bd, xs
+        torch.cuda.empty_cache()
+    return out
+
+
 LP_FWD_FLOP_PER_CELL = 2 * 27 * (4 * 16 + 16 * 16 + 16 * 4)  # three convolutions, algorithmic
 
 
@@ -291,6 +387,11 @@ def main():
                     help="held-out 64^3 instances for the learned-preconditioner section (0 = skip)")
     ap.add_argument("--lp-only", action="store_true",
                     help="run only the learned-preconditioner section and print its JSON")
+    ap.add_argument("--stress-n", type=int, default=4_000_000,
+                    help="rows of the band stress matrix (bandL = bandU = 100); 0 skips the stress section")
+    ap.add_argument("--stress-ill-n", type=int, default=159 ** 3,
+                    help="rows of the ill-conditioned band matrix (bandL = bandU = 200); 0 skips it")
+    ap.add_argument("--stress-only", action="store_true", help="only the stress section; prints its JSON")
     ap.add_argument("--mixed-only", action="store_true",
                     help="run only the mixed-precision section and print its JSON (for a separate kernel trace)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -323,6 +424,9 @@ def main():
         return
     if args.lp_only:
         print(json.dumps(run_learned(args.lp_eval, rpcg, torch, dev)), flush=True)
+        return
+    if args.stress_only:
+        print(json.dumps(run_stress(args.stress_n, 100, args.stress_ill_n, 200, rpcg, torch, dev)), flush=True)
         return
 
     N = args.grid
@@ -440,6 +544,7 @@ def main():
     mixed = run_mixed_precision(args.ir_grid, rpcg, torch, dev) if args.ir_grid > 0 else None
     batched = run_batched(args.batch_seed, rpcg, torch, dev) if args.batch_seed >= 0 else None
     learned_pc = run_learned(args.lp_eval, rpcg, torch, dev) if args.lp_eval > 0 else None
+    stress = run_stress(args.stress_n, 100, args.stress_ill_n, 200, rpcg, torch, dev) if args.stress_n > 0 else None
 
     traffic = k1_traffic() if N == 160 else None
     line = {
@@ -472,6 +577,7 @@ def main():
             "mixed_precision": mixed,
             "batched": batched,
             "learned_preconditioner": learned_pc,
+            "stress": stress,
         },
         "roofline": {
             "bound": "hbm",

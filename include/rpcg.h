@@ -152,6 +152,18 @@ int rpcg_exdot(rpcg_ctx *ctx, rpcg_mode mode, int64_t n, const double *x, const 
 int rpcg_spmv(rpcg_ctx *ctx, const rpcg_csr *A /* host struct */, const double *x, double *y,
               void *stream);
 
+/* Expansion length for FPE mode bound to the data's dynamic range (the
+ * binding of the FPE length to the dynamic range that Section 7 proposes as
+ * future work). With R = largest minus smallest binary exponent over the
+ * nonzero finite entries of A and b, *p = min(8, 4 + floor(2R / 53)): 4, the
+ * default, on well-scaled data, one more term per 53 bits of the range of
+ * the products. The choice affects speed only: with fpe_fallback set,
+ * whatever an expansion cannot hold goes to a long accumulator and results
+ * stay exact. *range (may be NULL) receives R. Waits for completion.
+ * Errors: RPCG_ERR_INVALID for NULL ctx, A, p or (n > 0) b. */
+int rpcg_fpe_size_auto(rpcg_ctx *ctx, const rpcg_csr *A /* host struct */, const double *b,
+                       int32_t *p /* host */, int32_t *range /* host */, void *stream);
+
 /* Solve A x = b with Jacobi-PCG (Fig. 1 / Fig. 2). b: n doubles; x: n
  * doubles, in: starting guess x^(0), out: final iterate. A must be SPD with a
  * positive stored diagonal entry in every row. The CSR structure is checked

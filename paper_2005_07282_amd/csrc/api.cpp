@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -226,6 +227,28 @@ int rpcg_acc_round(rpcg_ctx *c, const int64_t *digits, double *out, void *stream
     if (!c || !digits || !out) return RPCG_ERR_INVALID;
     RPCG_TRY(hipSetDevice(c->device));
     RPCG_TRY(launch_acc_round((const long long *)digits, out, (hipStream_t)stream));
+    return RPCG_OK;
+}
+
+int rpcg_fpe_size_auto(rpcg_ctx *c, const rpcg_csr *A, const double *b, int32_t *p, int32_t *range_out,
+                       void *stream)
+{
+    if (!c || !valid_csr(A) || (A->n > 0 && !b) || !p) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    int init[2] = {1 << 20, -(1 << 20)};
+    int *dev = &c->info->max_len; // two adjacent ints of the scratch record
+    static_assert(offsetof(DotInfo, pad1) == offsetof(DotInfo, max_len) + sizeof(int), "adjacent scratch ints");
+    RPCG_TRY(hipMemcpyAsync(dev, init, sizeof init, hipMemcpyHostToDevice, s));
+    RPCG_TRY(launch_exp_range(A->nnz, A->val, dev, dev + 1, s));
+    RPCG_TRY(launch_exp_range(A->n, b, dev, dev + 1, s));
+    int got[2];
+    RPCG_TRY(hipMemcpyAsync(got, dev, sizeof got, hipMemcpyDeviceToHost, s));
+    RPCG_TRY(hipStreamSynchronize(s));
+    const int range = got[1] >= got[0] ? got[1] - got[0] : 0;
+    // products of two entries span about twice the range; a term holds 53 bits
+    *p = std::min(MAX_FPE, 4 + 2 * range / 53);
+    if (range_out) *range_out = range;
     return RPCG_OK;
 }
 

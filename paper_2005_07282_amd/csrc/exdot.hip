@@ -2,6 +2,8 @@
 // rounding of a long accumulator, and the CSR SpMV.
 #include "reduce.hpp"
 
+#include <algorithm>
+
 namespace rpcg {
 
 // ---------------------------------------------------------------------------
@@ -143,6 +145,38 @@ hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const doub
     long long grid = ((long long)n + block - 1) / block;
     if (grid > 65536) grid = 65536;
     hipLaunchKernelGGL(k_spmv_csr, dim3((unsigned)grid), dim3(block), 0, s, n, row_ptr, col, val, x, y);
+    return hipGetLastError();
+}
+
+// Smallest and largest binary exponent (floor(log2 |v|)) over the nonzero
+// finite entries of v; *emin / *emax are lowered / raised atomically.
+__global__ void k_exp_range(long long n, const double *__restrict__ v, int *emin, int *emax)
+{
+    int lo = 1 << 20, hi = -(1 << 20);
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v[i]) & 0x7FFFFFFFFFFFFFFFull;
+        if (b == 0 || (b >> 52) == 0x7FF) continue;
+        const int be = (int)(b >> 52);
+        const int e = be ? be - 1023 : (63 - __builtin_clzll(b)) - 1074;
+        lo = min(lo, e);
+        hi = max(hi, e);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off, 64));
+        hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(emin, lo);
+        atomicMax(emax, hi);
+    }
+}
+
+hipError_t launch_exp_range(long long n, const double *v, int *emin, int *emax, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int grid = (int)std::min<long long>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_exp_range, dim3(grid), dim3(256), 0, s, n, v, emin, emax);
     return hipGetLastError();
 }
 

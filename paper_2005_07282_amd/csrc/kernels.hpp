@@ -122,6 +122,8 @@ hipError_t launch_exdot(int mode, long long n, const double *x, const double *y,
 hipError_t launch_exdot_partial(long long n, const double *x, const double *y, long long *digits,
                                 const DotWs &ws, int stride, DotInfo *info, const LaunchCfg &cfg);
 hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s);
+// Exponent range (floor(log2 |v|)) of the nonzero finite entries of v, merged into *emin, *emax.
+hipError_t launch_exp_range(long long n, const double *v, int *emin, int *emax, hipStream_t s);
 hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
                            const double *x, double *y, hipStream_t s);
 

@@ -105,6 +105,8 @@ def lib():
         L.rpcg_destroy.restype = None
         L.rpcg_exdot.argtypes = [P, ctypes.c_int, I64, P, P, P, ctypes.POINTER(_Opts), ctypes.POINTER(_Result), P]
         L.rpcg_exdot.restype = ctypes.c_int
+        L.rpcg_fpe_size_auto.argtypes = [P, ctypes.POINTER(_Csr), P, P, P, P]
+        L.rpcg_fpe_size_auto.restype = ctypes.c_int
         L.rpcg_spmv.argtypes = [P, ctypes.POINTER(_Csr), P, P, P]
         L.rpcg_spmv.restype = ctypes.c_int
         L.rpcg_pcg_solve.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_Opts),
@@ -165,7 +167,7 @@ def lib():
     return _lib
 
 
-EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot",
+EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot", "rpcg_fpe_size_auto",
             "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_factored", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
             "rpcg_batch_create", "rpcg_batch_destroy", "rpcg_batch_get_tuning", "rpcg_batch_set_tuning",
             "rpcg_batch_tune", "rpcg_batch_solve", "rpcg_lp_pattern_nnz", "rpcg_lp_pattern", "rpcg_lp_create",
@@ -654,3 +656,15 @@ class LearnedPreconditioner:
         if rc != 0:
             raise RpcgError(rc, "rpcg_lp_train_step")
         return loss.value
+
+
+def fpe_size_auto(A: CSR, b: torch.Tensor):
+    """(p, R): expansion length chosen from the exponent range R of A and b."""
+    _check(b, torch.float64, "b")
+    c = A._c()
+    p, r = ctypes.c_int32(0), ctypes.c_int32(0)
+    rc = lib().rpcg_fpe_size_auto(context(b.device.index), ctypes.byref(c), b.data_ptr(), ctypes.byref(p),
+                                  ctypes.byref(r), _stream(b.device))
+    if rc != 0:
+        raise RpcgError(rc, "rpcg_fpe_size_auto")
+    return p.value, r.value

@@ -30,5 +30,11 @@ from .gen import (  # noqa: F401
     batch_systems,
     grf_field,
     grf_diffusion_csr,
+    band_csr,
+    scale_first,
+    suitesparse_like,
+    suitesparse_like_parts,
+    scale_sym,
+    SUITESPARSE_LIKE,
     CSRHost,
 )

@@ -299,3 +299,111 @@ def grf_diffusion_csr(N: int, seed: int, sigma: float = 1.5, ell: float = 8.0):
     val = vals[valid]
     A = CSRHost(N ** 3, row_ptr.astype(np.int32), col.astype(np.int32), val.astype(np.float64))
     return A, c
+
+
+def band_csr(n: int, w: int) -> CSRHost:
+    """Symmetric band matrix with half-bandwidth w (the paper's weak-scaling
+    transform, bandL = bandU = w, nnz = (2w+1) n - w (w+1)): -1 on every
+    off-diagonal position of the band, 2w + 1 on the diagonal (strictly
+    diagonally dominant, hence SPD; the eigenvalues lie between 1 and the
+    maximum of the Toeplitz symbol 2w + 2 - sin((w + 1/2) t) / sin(t / 2),
+    about 1.43 (2w + 1) for large w). Columns ascending."""
+    i = np.arange(n, dtype=np.int64)
+    lo = np.maximum(i - w, 0)
+    hi = np.minimum(i + w, n - 1)
+    counts = hi - lo + 1
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    if nnz >= 2 ** 31:
+        raise ValueError("nnz does not fit int32 row pointers")
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.full(nnz, -1.0)
+    step = 1 << 16
+    for s0 in range(0, n, step):  # row blocks, to bound the temporaries
+        s1 = min(n, s0 + step)
+        c = counts[s0:s1]
+        seg = slice(int(row_ptr[s0]), int(row_ptr[s1]))
+        if np.all(c == 2 * w + 1):
+            col[seg] = (lo[s0:s1, None] + np.arange(2 * w + 1)[None, :]).ravel()
+        else:
+            pos = np.arange(row_ptr[s0], row_ptr[s1]) - np.repeat(row_ptr[s0:s1], c)
+            col[seg] = np.repeat(lo[s0:s1], c) + pos
+    val[row_ptr[:-1] + (i - lo)] = float(2 * w + 1)
+    return CSRHost(n, row_ptr.astype(np.int32), col, val)
+
+
+def scale_first(A: CSRHost, sigma: float) -> CSRHost:
+    """The paper's ill-conditioned generator: the first row and the first
+    column multiplied by sigma (A' = S A S, S = diag(sigma, 1, ..., 1)); with
+    sigma a power of two the scaling is exact."""
+    val = A.val.copy()
+    val[int(A.row_ptr[0]):int(A.row_ptr[1])] *= sigma
+    val[np.flatnonzero(A.col_idx == 0)] *= sigma
+    return CSRHost(A.n, A.row_ptr, A.col_idx, val)
+
+
+def suitesparse_like_parts(seed: int, nnz: int, cond: float, kappa_b: float = 1e6):
+    """The two factors of a SuiteSparse-shaped stand-in (only the paper's
+    printed nonzero counts and condition numbers are used, Section 5.4).
+
+    B: n = max(100, nnz // 32) rows and nnz nonzeros (up to parity): the
+    graph Laplacian of a random subset of the edges of a band of the
+    narrowest half-width h that holds them (so the spectrum spreads like
+    that of a mesh, not of an expander), edge weights in (0, 1], plus
+    delta = 2 * mean(diagonal) / kappa_b on the diagonal, then rows and
+    columns permuted at random. cond(B) is about min(kappa_b, that of the
+    Laplacian), and Jacobi does not remove it.
+
+    e: integer exponents of D = diag(2^e_i), uniform in [0, E] with
+    4^(E-1) = cond / min(cond, kappa_b): the part of the condition number
+    that Jacobi undoes."""
+    n = max(100, nnz // 32)
+    m = min(max(0, (nnz - n) // 2), n * (n - 1) // 2)  # distinct off-diagonal pairs
+    rng = np.random.Generator(np.random.PCG64(seed))
+    h = 0
+    while n * h - h * (h + 1) // 2 < m:
+        h += 1
+    # the band's pairs (i, i + j), j = 1..h, numbered row by row
+    j = np.arange(1, h + 1)
+    counts = np.clip(n - j, 0, None)
+    off = np.concatenate([[0], np.cumsum(counts)])
+    pick = np.sort(rng.choice(int(off[-1]), size=m, replace=False))
+    jj = np.searchsorted(off, pick, side="right")  # 1-based distance
+    ii = pick - off[jj - 1]
+    perm = rng.permutation(n)
+    r, c = perm[ii], perm[ii + jj]
+    r, c = np.minimum(r, c), np.maximum(r, c)
+    v = -rng.random(m) - 2.0 ** -20
+    import scipy.sparse as sp
+    U = sp.coo_matrix((v, (r, c)), shape=(n, n)).tocsr()
+    Bo = (U + U.T).tocsr()
+    d = np.asarray(abs(Bo).sum(axis=1)).reshape(-1)
+    kb = min(float(cond), float(kappa_b))
+    d = d + 2.0 * d.mean() / kb
+    B = (Bo + sp.diags(d)).tocsr()
+    B.sort_indices()
+    E = max(0, int(round(np.log2(float(cond) / kb) / 2)) + 1)
+    e = rng.integers(0, E + 1, n)
+    Bh = CSRHost(n, B.indptr.astype(np.int32), B.indices.astype(np.int32), B.data.astype(np.float64))
+    return Bh, e
+
+
+def scale_sym(A: CSRHost, e: np.ndarray) -> CSRHost:
+    """D A D with D = diag(2^e_i) (exact while nothing overflows or goes subnormal)."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    return CSRHost(A.n, A.row_ptr, A.col_idx, np.ldexp(A.val, e[rows] + e[A.col_idx]))
+
+
+def suitesparse_like(seed: int, nnz: int, cond: float, kappa_b: float = 1e6) -> CSRHost:
+    """D B D from suitesparse_like_parts: about nnz nonzeros, condition number
+    about cond."""
+    B, e = suitesparse_like_parts(seed, nnz, cond, kappa_b)
+    return scale_sym(B, e)
+
+
+# (nonzeros, condition number) pairs printed in the paper's SuiteSparse tables
+# (Section 5.4), in the order printed
+SUITESPARSE_LIKE = [(32399, 2.22e18), (26198, 9.00e15), (27520, 1.03e14), (1015156, 7.61e11), (1021159, 1.10e9),
+                    (219024, 6.28e9), (83883, 5.64e8), (72356, 3.56e7), (1666, 3.89e6), (97707, 4.78e5),
+                    (56126, 1.49e4)]
