@@ -397,6 +397,7 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
     auto t1 = std::chrono::steady_clock::now();
 
     const bool timing = o.timing != 0;
+    const bool k1_only = o.timing == 2;
     const int batch = 8;
     if (timing) {
         int rc = ensure_events(c->events, (size_t)EV_PER_IT * std::max(1, o.maxit));
@@ -413,6 +414,7 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
             if (ev) RPCG_TRY(hipEventRecord(ev[0], s));
             RPCG_TRY(launch_pcg_spmv_dot<T>(mode, M, v, c->st, c->ws[0], stride, cfg_sl));
             if (ev) RPCG_TRY(hipEventRecord(ev[1], s));
+            if (k1_only) ev = nullptr;
             bool done_fac = false;
             if constexpr (F64) {
                 if (fp) {
@@ -458,7 +460,7 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
         // the first L iterations did the work; later launches were no-ops
         const int L = std::min(S.iter, launched);
         for (int i = 0; i < L; ++i)
-            for (int k = 0; k < 3; ++k) {
+            for (int k = 0; k < (k1_only ? 1 : 3); ++k) {
                 float ms = 0.f;
                 hipEvent_t *ev = &c->events[(size_t)i * EV_PER_IT];
                 if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) out->k_ms[k] += ms;

@@ -89,6 +89,7 @@ inline bool valid_opts(const rpcg_opts &o)
     if (o.spmv_block_size != 0 && (o.spmv_block_size < 64 || o.spmv_block_size > MAX_BLOCK || o.spmv_block_size % 64))
         return false;
     if (o.spmv_grid_size < 0 || o.spmv_grid_size > 65536) return false;
+    if (o.timing < 0 || o.timing > 2) return false;
     return true;
 }
 
@@ -107,11 +108,14 @@ inline int resolve_fpe_size(int p, int mode)
     return mode == rpcg::MODE_EXBLAS ? 3 : 4;
 }
 
+// Timing events between solver kernels. They carry no system-scope fence:
+// the kernels' results stay on the device, and a fence per event would write
+// back the caches between kernels and slow the timed loop.
 inline int ensure_events(std::vector<hipEvent_t> &evs, size_t need)
 {
     while (evs.size() < need) {
         hipEvent_t e;
-        RPCG_TRY(hipEventCreate(&e));
+        RPCG_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
         evs.push_back(e);
     }
     return RPCG_OK;

@@ -222,6 +222,13 @@ def test_timing_fields(R, w1):
     assert info["k_launches"] == ref["iters"]
     assert info["k_spmv_dot_ms"] > 0 and info["k_update_ms"] > 0 and info["k_direction_ms"] > 0
     assert _eq(x, ref["x"])
+    # timing = 2 brackets only the SpMV+dot kernel; other values are rejected
+    x, info = _solve(R, A, b, "exblas", timing=2)
+    assert info["k_launches"] == ref["iters"]
+    assert info["k_spmv_dot_ms"] > 0 and info["k_update_ms"] == 0 and info["k_direction_ms"] == 0
+    assert _eq(x, ref["x"])
+    with pytest.raises(R.RpcgError):
+        _solve(R, A, b, "exblas", timing=3)
 
 
 @pytest.mark.slow
