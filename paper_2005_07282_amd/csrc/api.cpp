@@ -188,7 +188,13 @@ static int run_exdot(rpcg_ctx *c, int mode, int64_t n, const double *x, const do
     o.fpe_size = resolve_fpe_size(o.fpe_size, mode);
     RPCG_TRY(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    LaunchCfg cfg = make_cfg(c, o, std::max<int64_t>(1, (n + 7) / 8), 256, s);
+    // 1024-thread workgroups; four per CU for the expansion modes, eight for
+    // plain (measured at 2^28 elements: 5.2 / 3.8 TB/s exact on narrow / wide
+    // data against 4.5 / 3.0 with 256-thread workgroups, eight per CU)
+    LaunchCfg cfg = make_cfg(c, o, std::max<int64_t>(1, (n + 7) / 8), 1024, s);
+    if (!o.grid_size)
+        cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 8ll * cfg.block - 1) / (8ll * cfg.block),
+                                                               (mode == MODE_PLAIN ? 8ll : 4ll) * c->num_cus));
     int rc = ensure_ws(c, cfg.grid);
     if (rc != RPCG_OK) return rc;
     RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
