@@ -4,8 +4,10 @@
 //
 // Reduction structure (Section 3.2 / 4.3 mapped onto one GPU): each lane
 // keeps its own accumulator (an expansion, or a plain sum); the lanes of a
-// workgroup combine into one workgroup partial (a long accumulator in LDS,
-// or an expansion merged in a fixed tree) written to a slot. The kernel that
+// workgroup combine into one workgroup partial written to a slot: a plain
+// sum in a fixed tree, or, in both exact modes, a long accumulator in LDS
+// that receives each wavefront's expansion after a fixed lane tree (in FPE
+// mode the escapes of that tree are counted, as in Section 4.3). The kernel that
 // needs the scalar next merges all slots in a fixed order at its start, in
 // every workgroup alike, and rounds once; the kernel boundary makes the slots
 // visible, so no device-scope fence or atomic ticket is needed inside the
@@ -41,9 +43,8 @@ __device__ __forceinline__ T wave_sum_down(T v)
 struct RedShared {
     long long acc[3][ACC_DIGITS]; // long accumulators
     long long red_ll[MAX_WAVES];
-    double part[MAX_WAVES * MAX_FPE];
+    double part[MAX_WAVES];
     int rng[2];
-    int esc;
     int flag;
     double val[3];
 };
@@ -199,44 +200,6 @@ __device__ inline long long block_sum_ll(long long v, RedShared &sh)
     return t;
 }
 
-// Merge the expansions of all wavefronts of the workgroup into thread 0's
-// `a` (pairwise tree over the wavefronts). Every thread must call. Returns
-// the escapes of all merges (valid in thread 0).
-template <int P>
-__device__ __forceinline__ int block_fpe_merge(double (&a)[P], bool ee, bool capture, long long *acc, int &flags,
-                               RedShared &sh)
-{
-    long long esc = wave_fpe_merge<P>(a, ee, capture, acc, flags);
-    esc = block_sum_ll(esc, sh);
-    if (lane_id() == 0) {
-#pragma unroll
-        for (int i = 0; i < P; ++i) sh.part[wave_id() * MAX_FPE + i] = a[i];
-    }
-    if (threadIdx.x == 0) sh.esc = 0;
-    __syncthreads();
-    const int W = num_waves();
-    for (int step = 1; step < W; step <<= 1) {
-        const int w = wave_id();
-        if (lane_id() == 0 && (w % (2 * step)) == 0 && w + step < W) {
-            double x[P], y[P];
-#pragma unroll
-            for (int i = 0; i < P; ++i) { x[i] = sh.part[w * MAX_FPE + i]; y[i] = sh.part[(w + step) * MAX_FPE + i]; }
-            int e2 = fpe_sum_capture<P>(x, y, ee, capture, acc, flags);
-            if (e2) atomicAdd(&sh.esc, e2);
-#pragma unroll
-            for (int i = 0; i < P; ++i) sh.part[w * MAX_FPE + i] = x[i];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < P; ++i) a[i] = sh.part[i];
-        esc += sh.esc;
-    }
-    __syncthreads();
-    return (int)esc;
-}
-
 // ---------------------------------------------------------------------------
 // Slots: one workgroup partial per producing workgroup. Long-accumulator
 // words are stored word-major (word k of slot g at digits[k * stride + g]) so
@@ -268,14 +231,20 @@ __device__ __forceinline__ void block_finish(LaneDot<MODE, P> &L, long long *acc
                     if (L.a[i] != 0.0) acc_add_lds(acc, L.a[i], L.flags);
             }
         } else {
+            // each lane merges its result and error expansions, the
+            // wavefront merges its lanes' expansions (fixed tree, escapes
+            // counted), and the wavefront's expansion is added exactly to the
+            // long accumulator, which already holds whatever escaped on the
+            // way: the slot is the exact workgroup partial, merged across
+            // workgroups like exblas
             L.esc += fpe_sum_capture<P>(L.a, L.e, ee, capture, acc, L.flags);
-            int esc = block_fpe_merge<P>(L.a, ee, capture, acc, L.flags, sh);
-            long long esc_lanes = block_sum_ll(L.esc, sh);
-            if (threadIdx.x == 0) {
+            L.esc += wave_fpe_merge<P>(L.a, ee, capture, acc, L.flags);
+            if (lane_id() == 0) {
 #pragma unroll
-                for (int i = 0; i < P; ++i) sv.ws.part[(long long)g * MAX_FPE + i] = L.a[i];
-                sv.ws.esc[g] = (int)(esc + esc_lanes);
+                for (int i = 0; i < P; ++i) acc_add_lds(acc, L.a[i], L.flags);
             }
+            const long long esc = block_sum_ll(L.esc, sh);
+            if (threadIdx.x == 0) sv.ws.esc[g] = (int)esc;
         }
         if (threadIdx.x == 0) { sh.rng[0] = ACC_DIGITS; sh.rng[1] = -1; }
         __syncthreads();
@@ -442,22 +411,13 @@ __device__ __forceinline__ T merge_slots(const SlotView &sv, int G, bool ee, boo
         zero_acc(acc);
         if (threadIdx.x == 0) { sh.rng[0] = ACC_DIGITS; sh.rng[1] = -1; }
         __syncthreads();
-        // FPE: merge the workgroup expansions (pairwise tree from the slots up)
-        double a[P > 0 ? P : 1];
+        // FPE: the slots are exact workgroup partials (expansion included);
+        // only the escape counts are summed here
         if constexpr (MODE == MODE_FPE) {
-#pragma unroll
-            for (int i = 0; i < P; ++i) a[i] = 0.0;
             long long esc_slots = 0;
-            for (int g = threadIdx.x; g < G; g += blockDim.x) {
-                double b[P];
-#pragma unroll
-                for (int i = 0; i < P; ++i) b[i] = sv.ws.part[(long long)g * MAX_FPE + i];
-                int e = fpe_sum_capture<P>(a, b, ee, capture, acc, flags);
-                esc_slots += e + sv.ws.esc[g];
-            }
+            for (int g = threadIdx.x; g < G; g += blockDim.x) esc_slots += sv.ws.esc[g];
             long long esc_tot = block_sum_ll(esc_slots, sh);
-            int e2 = block_fpe_merge<P>(a, ee, capture, acc, flags, sh);
-            if (threadIdx.x == 0) *esc_out = esc_tot + e2;
+            if (threadIdx.x == 0) *esc_out = esc_tot;
         }
         // long-accumulator words: global nonzero range, then one word per wavefront
         int kmin = ACC_DIGITS, kmax = -1;
@@ -478,15 +438,6 @@ __device__ __forceinline__ T merge_slots(const SlotView &sv, int G, bool ee, boo
             if (lane_id() == 0) atomicAdd((unsigned long long *)&acc[k], (unsigned long long)s);
         }
         __syncthreads();
-        if constexpr (MODE == MODE_FPE) {
-            // NearSum (Section 4.3): the rounded exact value of the final
-            // expansion plus whatever was captured
-            if (threadIdx.x == 0) {
-#pragma unroll
-                for (int i = 0; i < P; ++i) acc_add_lds(acc, a[i], flags);
-            }
-            __syncthreads();
-        }
         if (flags) atomicOr(flags_out, flags);
         if (wave_id() == 0) {
             T v = wave_acc_round<T>(acc);
