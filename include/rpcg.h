@@ -42,9 +42,11 @@ extern "C" {
  *           one launch configuration but not across configurations.
  *  FPE    - per-lane floating-point expansions (two of size fpe_size: result
  *           and error, Section 4.2) updated with TwoSum (Alg. 1, 4) over
- *           TwoProd (Alg. 2), merged by fpesum (Alg. 3) in a fixed order and
- *           rounded once (NearSum, Section 4.3); see fpe_fallback for what
- *           happens when an expansion is too short.
+ *           TwoProd (Alg. 2), merged by fpesum (Alg. 3) in a fixed order
+ *           within each wavefront; each wavefront's expansion is then summed
+ *           exactly with the others and rounded once (the value NearSum gives,
+ *           Section 4.3); see fpe_fallback for what happens when an expansion
+ *           is too short.
  *  EXBLAS - per-lane expansion flushed into a workgroup long accumulator
  *           (Section 2.1 and 4.1), accumulators summed as integers, rounded
  *           once (exblas Round, Section 4.3). */
@@ -85,7 +87,9 @@ typedef struct {
     int32_t fpe_fallback;  /* FPE mode: what an expansion cannot hold (an escape, the
                               capacity warning of Section 4.3) is kept exactly in a long
                               accumulator, so the result stays exact (default 1); 0 drops
-                              it as the expansion-only variant does (RPCG_WARN_FPE_INEXACT) */
+                              it as the expansion-only variant does (RPCG_WARN_FPE_INEXACT).
+                              Escapes arise in the lanes and in the wavefront merges; the
+                              sum across wavefronts and workgroups is exact. */
     int32_t block_size;    /* threads per workgroup of the dot and vector kernels:
                               0 = auto, else 64..1024, multiple of 64 */
     int32_t grid_size;     /* workgroups of the dot and vector kernels: 0 = auto, else 1..65536 */
