@@ -13,7 +13,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "../../include/rpcg.h"
+#include "rpcg.h"
 #include "context.hpp"
 #include "kernels.hpp"
 

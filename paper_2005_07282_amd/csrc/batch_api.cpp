@@ -10,7 +10,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/rpcg.h"
+#include "rpcg.h"
 #include "context.hpp"
 #include "kernels.hpp"
 

@@ -9,7 +9,7 @@
 #include <map>
 #include <vector>
 
-#include "../../include/rpcg.h"
+#include "rpcg.h"
 #include "kernels.hpp"
 
 namespace rpcg_host {
