@@ -19,31 +19,66 @@ __device__ __forceinline__ void tap_offset(int t, int &dz, int &dy, int &dx)
 // over (tap, input channel) in chunks of 16: one tap per chunk with 16 input
 // channels, four taps per chunk with 4. Lane l supplies A[m = l%16][k = 4(l/16)
 // + j] and B[k][n = l%16] for j < 4 and receives D[4(l/16) + j][l%16].
+//
+// A workgroup of four wavefronts takes a block of 16 x 4 x 1 cells (one
+// y-line per wavefront) and first stages the block's inputs with their halo
+// (18 x 6 x 3 cells, zeros outside the grid) in LDS with coalesced loads;
+// the A operands are then read from LDS, so each input is fetched from
+// memory once per block instead of once per tap.
+constexpr int CONV_BX = 16, CONV_BY = 4;                       // block of output cells (x, y)
+constexpr int CONV_HX = CONV_BX + 2, CONV_HY = CONV_BY + 2, CONV_HZ = 3; // with halo
+constexpr int CONV_HCELLS = CONV_HX * CONV_HY * CONV_HZ;
+
+// Stage the inputs of the block of BY y-lines of 16 cells at (x0, y0, z) of
+// system b, with a one-cell halo, into tile[(zc * (BY + 2) + yc) * 18 + xc][CIN]
+// (zeros outside the grid). 8-byte units, consecutive threads on consecutive
+// units, so each halo row is one contiguous run.
+template <int CIN, int BY>
+__device__ __forceinline__ void stage_halo(bf16_t *tile, const bf16_t *__restrict__ inb, int N, int x0, int y0, int z)
+{
+    constexpr int UPC = CIN / 4, HY = BY + 2, HC = CONV_HX * HY * CONV_HZ;
+    for (int u = threadIdx.x; u < HC * UPC; u += blockDim.x) {
+        const int cell = u / UPC, q = u % UPC;
+        const int xc = cell % CONV_HX, yc = (cell / CONV_HX) % HY, zc = cell / (CONV_HX * HY);
+        const int X = x0 - 1 + xc, Y = y0 - 1 + yc, Z = z - 1 + zc;
+        v4s v = {0, 0, 0, 0};
+        if (X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N)
+            v = *(const v4s *)(inb + (((long long)Z * N + Y) * N + X) * CIN + 4 * q);
+        *(v4s *)&tile[cell * CIN + 4 * q] = v;
+    }
+}
+
 template <int CIN, int COUT, int EPI>
-__global__ void __launch_bounds__(256) k_lp_conv(int nb, int N, const bf16_t *__restrict__ in,
-                                                 const bf16_t *__restrict__ wt, const float *__restrict__ bias,
-                                                 const float *__restrict__ mask, float *__restrict__ pre,
-                                                 bf16_t *__restrict__ act)
+__global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const bf16_t *__restrict__ in,
+                                                          const bf16_t *__restrict__ wt, const float *__restrict__ bias,
+                                                          const float *__restrict__ mask, float *__restrict__ pre,
+                                                          bf16_t *__restrict__ act)
 {
     constexpr int TPC = 16 / CIN;                       // taps per chunk
     constexpr int NCH = (LP_TAPS + TPC - 1) / TPC;      // chunks
     __shared__ bf16_t w[NCH * TPC][16][CIN];
+    __shared__ __attribute__((aligned(16))) bf16_t tile[CONV_HCELLS * CIN];
     for (int e = threadIdx.x; e < NCH * TPC * 16 * CIN; e += blockDim.x)
         (&w[0][0][0])[e] = e < LP_TAPS * 16 * CIN ? wt[e] : (bf16_t)0;
-    __syncthreads();
     const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
-    const int tiles_x = (N + 15) >> 4;
-    const long long ntiles = (long long)nb * N * N * tiles_x;
+    const int wave = threadIdx.x >> 6;
+    const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + CONV_BY - 1) / CONV_BY;
+    const long long nblocks = (long long)nb * N * tiles_y * tiles_x;
     const long long N3 = (long long)N * N * N;
-    const int waves = blockDim.x >> 6;
-    for (long long tile = (long long)blockIdx.x * waves + (threadIdx.x >> 6); tile < ntiles;
-         tile += (long long)gridDim.x * waves) {
-        const int tx = (int)(tile % tiles_x);
-        const long long line = tile / tiles_x; // (b, z, y)
-        const int y = (int)(line % N), z = (int)((line / N) % N);
-        const long long b = line / ((long long)N * N);
-        const int x0 = tx * 16;
+    for (long long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) { // workgroup-uniform
+        const int tx = (int)(blk % tiles_x);
+        long long r = blk / tiles_x;
+        const int ty = (int)(r % tiles_y);
+        r /= tiles_y;
+        const int z = (int)(r % N);
+        const long long b = r / N;
+        const int x0 = tx * CONV_BX, y0 = ty * CONV_BY;
         const bf16_t *inb = in + b * N3 * CIN;
+        __syncthreads(); // the previous block's readers are done (and the weights are in place)
+        stage_halo<CIN, CONV_BY>(tile, inb, N, x0, y0, z);
+        __syncthreads();
+        const int y = y0 + wave;
+        if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
         v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll 3
         for (int c = 0; c < NCH; ++c) {
@@ -53,9 +88,9 @@ __global__ void __launch_bounds__(256) k_lp_conv(int nb, int N, const bf16_t *__
             if (t < LP_TAPS) {
                 int dz, dy, dx;
                 tap_offset(t, dz, dy, dx);
-                const int X = x0 + m + dx, Y = y + dy, Z = z + dz;
-                if (x0 + m < N && X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N)
-                    a = *(const v4s *)(inb + (((long long)Z * N + Y) * N + X) * CIN + cbase);
+                // rows m past the grid's edge read valid LDS cells; their outputs are not stored
+                const int hc = ((dz + 1) * CONV_HY + (wave + dy + 1)) * CONV_HX + (m + dx + 1);
+                a = *(const v4s *)&tile[hc * CIN + cbase];
             }
             const v4s bw = *(const v4s *)&w[t][m][cbase];
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
@@ -84,30 +119,45 @@ __global__ void __launch_bounds__(256) k_lp_conv(int nb, int N, const bf16_t *__
 
 // Weight gradient dW[t][co][ci] = sum over cells of dout[cell][co] in[cell + off(t)][ci]
 // and bias gradient db[co] = sum of dout[cell][co], on 16x16x16 MFMA with
-// M = co, N = ci, K = the 16 cells of a tile. Each workgroup sums its waves in
-// wave order and writes one slot; the slots are summed in slot order later.
+// M = co, N = ci, K = the 16 cells of a tile. A workgroup of DW_BY wavefronts
+// takes blocks of 16 x DW_BY x 1 cells (one y-line per wavefront), stages
+// their inputs with the halo in LDS, and each wavefront accumulates its
+// line's 27 tap products; the B operands come from LDS, six cells per
+// (dz, dy) serving the three dx taps. Each workgroup sums its waves in wave
+// order and writes one slot; the slots are summed in slot order later.
+constexpr int DW_BY = 8;
+
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(256) k_lp_conv_dw(int nb, int N, const bf16_t *__restrict__ in,
-                                                    const bf16_t *__restrict__ dout, float *__restrict__ pw,
-                                                    float *__restrict__ pb)
+__global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const bf16_t *__restrict__ in,
+                                                          const bf16_t *__restrict__ dout, float *__restrict__ pw,
+                                                          float *__restrict__ pb)
 {
+    constexpr int HY = DW_BY + 2;
     __shared__ float sw[LP_TAPS][16][16];
-    __shared__ float sbl[4][4][16]; // [wave][lane group][co]
+    __shared__ float sbl[DW_BY][4][16]; // [wave][lane group][co]
+    __shared__ __attribute__((aligned(16))) bf16_t tile[CONV_HX * HY * CONV_HZ * CIN];
     const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
     const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
-    const int tiles_x = (N + 15) >> 4;
-    const long long ntiles = (long long)nb * N * N * tiles_x;
+    const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + DW_BY - 1) / DW_BY;
+    const long long nblocks = (long long)nb * N * tiles_y * tiles_x;
     const long long N3 = (long long)N * N * N;
     v4f acc[LP_TAPS];
 #pragma unroll
     for (int t = 0; t < LP_TAPS; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    for (long long tile = (long long)blockIdx.x * waves + wave; tile < ntiles; tile += (long long)gridDim.x * waves) {
-        const int tx = (int)(tile % tiles_x);
-        const long long line = tile / tiles_x;
-        const int y = (int)(line % N), z = (int)((line / N) % N);
-        const long long b = line / ((long long)N * N);
-        const int x0 = tx * 16;
+    for (long long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) { // workgroup-uniform
+        const int tx = (int)(blk % tiles_x);
+        long long r = blk / tiles_x;
+        const int ty = (int)(r % tiles_y);
+        r /= tiles_y;
+        const int z = (int)(r % N);
+        const long long b = r / N;
+        const int x0 = tx * CONV_BX, y0 = ty * DW_BY;
+        __syncthreads(); // the previous block's readers are done
+        stage_halo<CIN, DW_BY>(tile, in + b * N3 * CIN, N, x0, y0, z);
+        __syncthreads();
+        const int y = y0 + wave;
+        if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
         // A[m = co][k = cell 4g + j]
         v4s a = {0, 0, 0, 0};
 #pragma unroll
@@ -119,21 +169,22 @@ __global__ void __launch_bounds__(256) k_lp_conv_dw(int nb, int N, const bf16_t 
                 bsum += bf16_to_f32(h);
             }
         }
+        // B[k = cell 4g + j][n = ci] = in[cell + off(t)][ci]; columns past the
+        // row end meet zero A entries, so their (finite) values do not matter
 #pragma unroll
-        for (int t = 0; t < LP_TAPS; ++t) {
-            int dz, dy, dx;
-            tap_offset(t, dz, dy, dx);
-            const int Y = y + dy, Z = z + dz;
-            v4s bv = {0, 0, 0, 0};
-            if (m < CIN && Y >= 0 && Y < N && Z >= 0 && Z < N) {
+        for (int zy = 0; zy < 9; ++zy) {
+            const int dz = zy / 3 - 1, dy = zy % 3 - 1;
+            short v[6] = {0, 0, 0, 0, 0, 0};
+            if (m < CIN) {
+                const int row = ((dz + 1) * HY + (wave + dy + 1)) * CONV_HX + 4 * g;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int xc = x0 + 4 * g + j, X = xc + dx;
-                    if (xc < N && X >= 0 && X < N)
-                        bv[j] = (short)in[(b * N3 + ((long long)Z * N + Y) * N + X) * CIN + m];
-                }
+                for (int i = 0; i < 6; ++i) v[i] = (short)tile[(row + i) * CIN + m];
             }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[t], 0, 0, 0);
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const v4s bv = {v[dx], v[dx + 1], v[dx + 2], v[dx + 3]};
+                acc[zy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[zy * 3 + dx], 0, 0, 0);
+            }
         }
     }
     // workgroup sum in wave order; lane l holds dW[t][4g + j][l % 16]
@@ -222,19 +273,20 @@ __global__ void k_lp_adam(int n, float *__restrict__ p, const float *__restrict_
 hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_t *in, const bf16_t *wt,
                           const float *bias, const float *mask, float *pre, bf16_t *act, hipStream_t s)
 {
-    const long long tiles = (long long)nb * N * N * ((N + 15) / 16);
-    const int grid = (int)std::min<long long>((tiles + 3) / 4, 8192);
+    const long long blocks = (long long)nb * N * ((N + CONV_BY - 1) / CONV_BY) * ((N + CONV_BX - 1) / CONV_BX);
+    const int grid = (int)std::min<long long>(blocks, 8192);
+    const int block = 64 * CONV_BY;
     if (grid <= 0) return hipSuccess;
     if (cin == 4 && cout == 16 && epi == EPI_RELU)
-        k_lp_conv<4, 16, EPI_RELU><<<grid, 256, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
+        k_lp_conv<4, 16, EPI_RELU><<<grid, block, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
     else if (cin == 16 && cout == 16 && epi == EPI_RELU)
-        k_lp_conv<16, 16, EPI_RELU><<<grid, 256, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
+        k_lp_conv<16, 16, EPI_RELU><<<grid, block, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
     else if (cin == 16 && cout == 4 && epi == EPI_LINEAR)
-        k_lp_conv<16, 4, EPI_LINEAR><<<grid, 256, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
+        k_lp_conv<16, 4, EPI_LINEAR><<<grid, block, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
     else if (cin == 4 && cout == 16 && epi == EPI_MASK)
-        k_lp_conv<4, 16, EPI_MASK><<<grid, 256, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
+        k_lp_conv<4, 16, EPI_MASK><<<grid, block, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
     else if (cin == 16 && cout == 16 && epi == EPI_MASK)
-        k_lp_conv<16, 16, EPI_MASK><<<grid, 256, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
+        k_lp_conv<16, 16, EPI_MASK><<<grid, block, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -243,12 +295,13 @@ hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_
 hipError_t launch_lp_conv_dw(int cin, int cout, int nb, int N, const bf16_t *in, const bf16_t *dout, float *pw,
                              float *pb, int grid, hipStream_t s)
 {
+    const int block = 64 * DW_BY;
     if (cin == 16 && cout == 4)
-        k_lp_conv_dw<16, 4><<<grid, 256, 0, s>>>(nb, N, in, dout, pw, pb);
+        k_lp_conv_dw<16, 4><<<grid, block, 0, s>>>(nb, N, in, dout, pw, pb);
     else if (cin == 16 && cout == 16)
-        k_lp_conv_dw<16, 16><<<grid, 256, 0, s>>>(nb, N, in, dout, pw, pb);
+        k_lp_conv_dw<16, 16><<<grid, block, 0, s>>>(nb, N, in, dout, pw, pb);
     else if (cin == 4 && cout == 16)
-        k_lp_conv_dw<4, 16><<<grid, 256, 0, s>>>(nb, N, in, dout, pw, pb);
+        k_lp_conv_dw<4, 16><<<grid, block, 0, s>>>(nb, N, in, dout, pw, pb);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
