@@ -103,6 +103,40 @@ def test_backward_matches_oracle(R, net10):
         off += m
 
 
+def test_forward_backward_ragged_blocks(R):
+    """N = 21 cuts the convolutions' blocks raggedly: one full and one
+    5-cell tile along x, y-blocks of 4 (forward) and 8 (weight gradient)
+    with remainders, and halos on every side."""
+    N = 21
+    net = R.LearnedPreconditioner(N, max_batch=2)
+    net.set_params(params(3))
+    As = systems(N, [31, 32])
+    mats = [R.CSR.from_host(A) for A in As]
+    o = net.forward(mats).cpu().numpy()
+    p = params(3).astype(np.float64)
+    rng = np.random.default_rng(9)
+    dout = rng.standard_normal((2, N ** 3, 4))
+    g = net.backward(mats, torch.from_numpy(dout).cuda()).cpu().numpy().astype(np.float64)
+    net.close()
+    ref_g = np.zeros(lpnet.NPARAMS)
+    for k, A in enumerate(As):
+        c = lpnet.forward(p, lpnet.features(A, N), bf16=True)
+        ref = c["o"].reshape(-1, 4)
+        scale = np.abs(ref).max()
+        err = np.abs(o[k] - ref)
+        print(f"N=21 forward system {k}: max |diff| / max |o| = {err.max() / scale:.2e}", flush=True)
+        assert err.max() <= 3e-2 * scale
+        assert np.mean(err > 1e-3 * scale) < 0.01
+        ref_g += lpnet.backward(c, dout[k].reshape(N, N, N, 4))
+    off = 0
+    for name, shape in lpnet.SHAPES:
+        m = int(np.prod(shape))
+        rel = np.linalg.norm(g[off:off + m] - ref_g[off:off + m]) / np.linalg.norm(ref_g[off:off + m])
+        print(f"N=21 gradient {name}: relative difference {rel:.2e}", flush=True)
+        assert rel < 2e-2, name
+        off += m
+
+
 def test_factor_independent_of_batch(R, net10):
     N = 10
     As = systems(N, [16, 17, 18])
