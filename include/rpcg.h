@@ -230,7 +230,12 @@ typedef struct {
     double tol;            /* outer: stop when <r,r> <= RN(RN(tol*tol) <b,b>) with r = b - A x
                               formed in binary64 (default 1e-10) */
     int32_t maxit;         /* outer corrections at most (default 50) */
-    int32_t pad0;
+    int32_t adaptive_inner; /* 1 (default): the inner tolerance of outer step k is
+                              max(inner.tol, RN(0.25 * RN(sqrt(RN(thr / rr_k))))), with
+                              thr the outer threshold and rr_k = <r,r> of the step, so the
+                              last correction aims just below the outer target instead of
+                              a full inner.tol reduction past it; 0: inner.tol for every
+                              step. Other values: RPCG_ERR_INVALID */
     double *rr_history;    /* optional DEVICE array of maxit+1 doubles: <r,r> of every outer step */
     rpcg_opts inner;       /* the binary32 inner solves: tol (default 1e-4), maxit (default 2000),
                               expansion and launch options; its tau_history must be NULL */

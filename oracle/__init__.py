@@ -67,7 +67,7 @@ def lib():
                                                ctypes.c_double, ctypes.c_int32, P, P]
         L.rpcg_oracle_ir.restype = ctypes.c_int
         L.rpcg_oracle_ir.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
-                                     ctypes.c_double, ctypes.c_int32, P, P, P]
+                                     ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P]
         _lib = L
     return _lib
 
@@ -203,9 +203,10 @@ def ir_scale(rr: float) -> int:
     return lib().rpcg_oracle_ir_scale(float(rr))
 
 
-def ir(A, b, x0=None, tol=1e-10, maxit_out=50, tol_in=1e-4, maxit_in=2000):
+def ir(A, b, x0=None, tol=1e-10, maxit_out=50, tol_in=1e-4, maxit_in=2000, adaptive=True):
     """Mixed-precision refinement (binary32 inner PCG on the values rounded to
-    binary32, binary64 outer loop on the values as given).
+    binary32, binary64 outer loop on the values as given); adaptive: the inner
+    tolerance of a step is max(tol_in, 0.25 sqrt(thr / rr)).
     Returns dict(x, outer, inner, hist (rr per outer step), status)."""
     n = A.n
     b = _f64(b)
@@ -214,7 +215,8 @@ def ir(A, b, x0=None, tol=1e-10, maxit_out=50, tol_in=1e-4, maxit_in=2000):
     outer, inner = ctypes.c_int32(0), ctypes.c_int32(0)
     rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val)
     st = lib().rpcg_oracle_ir(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit_out),
-                              float(tol_in), int(maxit_in), _p(hist), ctypes.byref(outer), ctypes.byref(inner))
+                              float(tol_in), int(maxit_in), int(bool(adaptive)), _p(hist), ctypes.byref(outer),
+                              ctypes.byref(inner))
     k = outer.value
     return dict(x=x, outer=k, inner=inner.value, hist=hist[:k + 1].copy(), status=st)
 

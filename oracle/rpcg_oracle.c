@@ -459,13 +459,15 @@ int rpcg_oracle_ir_scale(double rr)
  *   outer loop k = 0, 1, ...: r = b - A x (rows exact, rounded once);
  *     rr = <r,r> (exact); hist[k] = rr; stop if rr <= RN(RN(tol*tol) <b,b>)
  *     or k = maxit; s = rpcg_oracle_ir_scale(rr);
- *     c = PCG32(RN32(A), RN32(r 2^-s), x0 = 0, tol_in, maxit_in);
+ *     t = tol_in, or with adaptive = 1 max(tol_in, RN(0.25 RN(sqrt(RN(thr / rr)))))
+ *     (the reduction the outer residual still needs, with a margin of 4);
+ *     c = PCG32(RN32(A), RN32(r 2^-s), x0 = 0, t, maxit_in);
  *     x = RN(x + (double)c 2^s)
  *   *outer: corrections applied; *inner: total inner iterations.
  * Returns the outer status (OK, WARN_MAXIT) or the first inner error. */
 int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val64,
                    const double *b, double *x, double tol, int32_t maxit_out, double tol_in,
-                   int32_t maxit_in, double *hist, int32_t *outer, int32_t *inner)
+                   int32_t maxit_in, int32_t adaptive, double *hist, int32_t *outer, int32_t *inner)
 {
     *outer = 0; *inner = 0;
     size_t nn = (size_t)(n > 0 ? n : 1);
@@ -487,8 +489,13 @@ int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
         int sc = rpcg_oracle_ir_scale(rr);
         for (int32_t i = 0; i < n; ++i) rf[i] = (float)ldexp(r[i], -sc);
         for (int32_t i = 0; i < n; ++i) c[i] = 0.0f;
+        double t = tol_in;
+        if (adaptive) {
+            double need = 0.25 * sqrt(thr / rr);
+            if (need > t) t = need;
+        }
         int32_t it = 0;
-        int st = rpcg_oracle_pcg_f32(n, row_ptr, col, val32, rf, c, tol_in, maxit_in, NULL, &it);
+        int st = rpcg_oracle_pcg_f32(n, row_ptr, col, val32, rf, c, t, maxit_in, NULL, &it);
         *inner += it;
         if (st < 0) { status = st; break; }
         for (int32_t i = 0; i < n; ++i) x[i] = x[i] + ldexp((double)c[i], sc);

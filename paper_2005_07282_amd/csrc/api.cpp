@@ -614,6 +614,7 @@ void rpcg_ir_opts_default(rpcg_ir_opts *o)
     std::memset(o, 0, sizeof(*o));
     o->tol = 1e-10;
     o->maxit = 50;
+    o->adaptive_inner = 1;
     rpcg_opts_default(&o->inner);
     o->inner.tol = 1e-4;
 }
@@ -697,8 +698,13 @@ static int ir_body(rpcg_ctx *c, int mode, const rpcg_csr *A, const double *b, do
         if (H->flags & FLAG_INEXACT) inexact = true;
         if (H->stop) { status = H->status; break; }
         auto ti = std::chrono::steady_clock::now();
+        // inner tolerance of this step (rr > thr >= 0 here): the reduction the
+        // outer residual still needs, with a factor 4 of margin, unless
+        // inner.tol asks for more
+        rpcg_opts ok = o;
+        if (io.adaptive_inner) ok.tol = std::max(o.tol, 0.25 * std::sqrt(H->thr / H->rr));
         PcgRun run;
-        rc = run_pcg<float>(c, mode, M, rf, cv, o, cfg_rows, cfg_sl, s, &run);
+        rc = run_pcg<float>(c, mode, M, rf, cv, ok, cfg_rows, cfg_sl, s, &run);
         if (rc != RPCG_OK) return rc;
         inner_ms += ms_since(ti);
         inner_its += run.S.iter;
@@ -748,7 +754,9 @@ int rpcg_ir_solve(rpcg_ctx *c, rpcg_mode mode, const rpcg_csr *A, const double *
     rpcg_ir_opts io;
     rpcg_ir_opts_default(&io);
     if (opts) io = *opts;
-    if (!(io.tol >= 0.0) || io.maxit < 0 || io.inner.tau_history || !valid_opts(io.inner)) return RPCG_ERR_INVALID;
+    if (!(io.tol >= 0.0) || io.maxit < 0 || io.inner.tau_history || !valid_opts(io.inner) ||
+        (io.adaptive_inner != 0 && io.adaptive_inner != 1))
+        return RPCG_ERR_INVALID;
     RPCG_TRY(hipSetDevice(c->device));
     int rc = ir_body(c, (int)mode, A, b, x, io, res, (hipStream_t)stream);
     if (res) res->status = rc;

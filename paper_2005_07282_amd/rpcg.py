@@ -56,7 +56,7 @@ class _Result(ctypes.Structure):
 
 
 class _IrOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("pad0", ctypes.c_int32),
+    _fields_ = [("tol", ctypes.c_double), ("maxit", ctypes.c_int32), ("adaptive_inner", ctypes.c_int32),
                 ("rr_history", ctypes.c_void_p), ("inner", _Opts)]
 
 
@@ -365,12 +365,14 @@ def pcg_solve_f32(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode:
 
 def ir_solve(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str = "exblas",
              tol: float = 1e-10, maxit: int = 50, tol_inner: float = 1e-4, maxit_inner: int = 2000,
-             history: bool = True, raise_on_error: bool = True, **inner):
+             adaptive_inner: bool = True, history: bool = True, raise_on_error: bool = True, **inner):
     """Mixed-precision refinement (binary32 inner Jacobi-PCG, binary64 outer
     residual and update). tol/maxit are the outer ones, tol_inner/maxit_inner
-    those of every inner solve; `inner` takes the other rpcg_opts fields of the
-    inner solves (expansion length, launch shapes, timing). Returns (x, info);
-    info['rr_hist'] holds <r,r> of every outer step when history=True."""
+    those of every inner solve (with adaptive_inner, tol_inner is the least
+    reduction a step asks for; see rpcg_ir_opts); `inner` takes the other
+    rpcg_opts fields of the inner solves (expansion length, launch shapes,
+    timing). Returns (x, info); info['rr_hist'] holds <r,r> of every outer
+    step when history=True."""
     _check(b, torch.float64, "b")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     _check(x, torch.float64, "x")
@@ -378,6 +380,7 @@ def ir_solve(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str 
     lib().rpcg_ir_opts_default(ctypes.byref(o))
     o.tol = tol
     o.maxit = maxit
+    o.adaptive_inner = int(bool(adaptive_inner))
     o.inner.tol = tol_inner
     o.inner.maxit = maxit_inner
     for k, v in inner.items():

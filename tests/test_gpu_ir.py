@@ -162,6 +162,18 @@ def test_ir_bitexact(R, orc, mode):
     assert orc.relres_true(A, b, x) <= 1e-10
 
 
+def test_ir_fixed_inner_tolerance(R, orc):
+    """adaptive_inner = 0: every inner solve to tol_inner, as the oracle's
+    fixed-tolerance refinement; it overshoots the target on the last step."""
+    A, b, xs = stencil_problem(20, 7)
+    res = orc.ir(A, b, tol=1e-10, tol_in=1e-4, adaptive=False)
+    ad = orc.ir(A, b, tol=1e-10, tol_in=1e-4, adaptive=True)
+    assert res["inner"] > ad["inner"]
+    print("ir 20^3 fixed inner tolerance", flush=True)
+    x, info = _ir(R, A, b, tol=1e-10, maxit=50, adaptive_inner=False)
+    _check_ir(res, x, info)
+
+
 def test_ir_error_vs_fp64_oracle(R, orc):
     """The refinement's solution against the binary64 exact-dot PCG solution of
     the oracle (same tolerance): the stated error is at the 1e-9 level."""

@@ -125,5 +125,5 @@ def test_ir_opts_default(L):
     from paper_2005_07282_amd import rpcg
     o = rpcg._IrOpts()
     L.rpcg_ir_opts_default(ctypes.byref(o))
-    assert o.tol == 1e-10 and o.maxit == 50 and o.rr_history is None
+    assert o.tol == 1e-10 and o.maxit == 50 and o.rr_history is None and o.adaptive_inner == 1
     assert o.inner.tol == 1e-4 and o.inner.maxit == 2000 and o.inner.fpe_fallback == 1

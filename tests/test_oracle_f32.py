@@ -136,6 +136,27 @@ def test_ir_reaches_fp64_accuracy(orc):
     assert np.max(np.abs(res["x"] - xs)) < 1e-8
 
 
+def test_ir_adaptive_inner_tolerance(orc):
+    """The adaptive rule only loosens a step's inner tolerance when the outer
+    residual needs less than tol_in of reduction: the earlier steps are the
+    fixed-tolerance ones bit for bit, the last one stops nearer the target
+    (still below it) with fewer inner iterations."""
+    N = 16
+    A = stencil27_csr(N)
+    K = uniform_pm1_int52(8, A.n)
+    b = stencil27_rhs_from_int52(N, K)
+    fixed = orc.ir(A, b, tol=1e-10, tol_in=1e-4, adaptive=False)
+    ad = orc.ir(A, b, tol=1e-10, tol_in=1e-4, adaptive=True)
+    assert fixed["status"] == 0 and ad["status"] == 0
+    k = ad["outer"]
+    assert fixed["outer"] == k >= 2
+    assert np.array_equal(ad["hist"][:k], fixed["hist"][:k])
+    thr = 1e-20 * orc.exdot(b, b)
+    assert fixed["hist"][k] < ad["hist"][k] <= thr
+    assert ad["inner"] < fixed["inner"]
+    assert orc.relres_true(A, b, ad["x"]) <= 1e-10
+
+
 def test_ir_first_step_is_the_f32_solve(orc):
     """With one outer step the refinement's x is exactly (double)c 2^s of the
     binary32 solve of the scaled right-hand side (x0 = 0, r0 = b)."""
