@@ -78,13 +78,24 @@ __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags
 // it is counted and, with `capture`, added to the long accumulator so the
 // result stays exact; without `capture` it is dropped as in the paper.
 // PLAIN: an fma running sum.
-template <int MODE, int P>
+//
+// ADAPT (EXBLAS only): when the expansion keeps overflowing (wide exponent
+// ranges, where nearly every product leaves a remainder), the lane adds
+// the TwoProd halves straight into the long accumulator for a while and
+// skips the expansion arithmetic that would not have absorbed them; one
+// window in eight measures the overflow rate again. Either path adds the
+// exact products, so the result does not depend on the switching.
+constexpr int ADAPT_WINDOW = 32;   // adds per measurement window
+constexpr int ADAPT_DIRECT = 7;    // windows in direct mode before measuring again
+
+template <int MODE, int P, bool ADAPT = false>
 struct LaneDot {
     double a[P];
     double e[P];
     double s;
     int esc;
     int flags;
+    int win, wfl, direct; // ADAPT: adds and flushes in this window, direct windows left
 
     __device__ __forceinline__ void init()
     {
@@ -93,6 +104,7 @@ struct LaneDot {
         s = 0.0;
         esc = 0;
         flags = 0;
+        win = wfl = direct = 0;
     }
 
     __device__ __forceinline__ void add(double x, double y, long long *acc, bool ee, bool capture)
@@ -103,7 +115,22 @@ struct LaneDot {
             double r, t;
             two_prod(x, y, r, t);
             if (__builtin_fabs(r) < 0x1p-969 && x != 0.0 && y != 0.0) flags |= FLAG_INEXACT;
-            if constexpr (MODE == MODE_EXBLAS) {
+            if constexpr (MODE == MODE_EXBLAS && ADAPT) {
+                if (direct) {
+                    acc_add_lds(acc, r, flags);
+                    acc_add_lds(acc, t, flags);
+                } else {
+                    double left = fpe_accumulate<P>(a, r, ee);
+                    if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
+                    left = fpe_accumulate<P>(a, t, ee);
+                    if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
+                }
+                if (++win == ADAPT_WINDOW) {
+                    // more than one flush per add on average: go direct
+                    direct = direct ? direct - 1 : (wfl > ADAPT_WINDOW ? ADAPT_DIRECT : 0);
+                    win = wfl = 0;
+                }
+            } else if constexpr (MODE == MODE_EXBLAS) {
                 double left = fpe_accumulate<P>(a, r, ee);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
                 left = fpe_accumulate<P>(a, t, ee);
@@ -211,9 +238,9 @@ struct SlotView {
 };
 
 // Write the workgroup partial of one dot into slot g. All threads call.
-template <int MODE, int P>
-__device__ __forceinline__ void block_finish(LaneDot<MODE, P> &L, long long *acc, const SlotView &sv, int g, bool ee,
-                             bool capture, int *gflags, RedShared &sh)
+template <int MODE, int P, bool ADAPT>
+__device__ __forceinline__ void block_finish(LaneDot<MODE, P, ADAPT> &L, long long *acc, const SlotView &sv, int g,
+                                             bool ee, bool capture, int *gflags, RedShared &sh)
 {
     if constexpr (MODE == MODE_PLAIN) {
         double t = block_sum_d(L.s, sh);

@@ -82,6 +82,22 @@ def test_launch_config_invariance(R, orc, mode):
             assert _same(out.item(), want), (block, grid, p)
 
 
+def test_mixed_ranges_switch_paths(R, orc):
+    """Narrow, wide, narrow segments: in exblas mode each lane moves from its
+    expansion to adding the products straight into the accumulator and back
+    as the overflow rate changes; the result stays the exact dot for any
+    launch shape (the switching points move with the shape)."""
+    parts = [exdot_narrow(21, 300000), exdot_wide(22, 300000), exdot_narrow(23, 300001)]
+    x = np.concatenate([p[0] for p in parts])
+    y = np.concatenate([p[1] for p in parts])
+    want = orc.exdot(x, y)
+    X, Y = _dev(x), _dev(y)
+    for block, grid in ((0, 0), (64, 1), (256, 37), (1024, 1024), (512, 4096)):
+        print(f"exdot mixed ranges block={block} grid={grid}", flush=True)
+        out, info = R.exdot(X, Y, mode="exblas", block_size=block, grid_size=grid)
+        assert _same(out.item(), want), (block, grid)
+
+
 def test_fpe_escapes_and_fallback(R, orc):
     """Wide data overflows short expansions (Section 4.3 warning); with the
     fallback the result is still the exact dot, without it a warning is raised."""
