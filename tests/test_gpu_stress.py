@@ -12,7 +12,7 @@ exact one in trailing digits, as Table 3 shows for the original code."""
 import numpy as np
 import pytest
 
-from rpcg_workloads import (SUITESPARSE_LIKE, band_csr, scale_first, scale_sym, suitesparse_like,
+from rpcg_workloads import (SUITESPARSE_LIKE, band_csr, random_spd_csr, scale_first, scale_sym, suitesparse_like,
                             suitesparse_like_parts, uniform_pm1)
 
 pytestmark = pytest.mark.gpu
@@ -35,12 +35,17 @@ def _eq(a, b):
 
 
 SS_SMALL = [p for p in SUITESPARSE_LIKE if p[0] <= 60000]
-CASES = ["band", "band_sigma16"] + [f"ss_{nnz}" for nnz, _ in SS_SMALL]
+# band_w150 and dense_spd have rows of 301 and about 360 entries: longer than
+# the one-byte row lengths of the sliced-ELL copy can hold
+CASES = ["band", "band_sigma16", "band_w150", "dense_spd"] + [f"ss_{nnz}" for nnz, _ in SS_SMALL]
 
 
 def make_case(orc, name):
-    if name.startswith("band"):
-        A = band_csr(3000, 100)
+    if name == "dense_spd":
+        A = random_spd_csr(400, 5, density=0.9)
+        b = orc.spmv(A, uniform_pm1(8, A.n))
+    elif name.startswith("band"):
+        A = band_csr(1200, 150) if name == "band_w150" else band_csr(3000, 100)
         if name == "band_sigma16":
             A = scale_first(A, 2.0 ** 16)
         b = orc.spmv(A, np.ones(A.n))  # b = A 1 (Section 5.1)
