@@ -506,7 +506,8 @@ def main():
         out = torch.empty(1, dtype=torch.float64, device=dev)
         for mode in ("exblas", "fpe", "plain"):
             stream = torch.cuda.current_stream()
-            for _ in range(3):
+            # about 30 ms of warm-up: the GPU idled while the host generated the data
+            for _ in range(30):
                 rpcg.exdot(X, Y, mode=mode, out=out, sync=False)
             times = []
             for _ in range(args.exdot_reps):
