@@ -377,8 +377,10 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
     if (fp && !F64) return RPCG_ERR_INVALID;
     auto t0 = std::chrono::steady_clock::now();
     const int n = M.n;
-    RPCG_TRY(c->vecs.ensure(sizeof(T) * 5 * (size_t)std::max(1, n)));
+    // five work vectors; the factored preconditioner keeps a second r buffer
+    RPCG_TRY(c->vecs.ensure(sizeof(T) * (fp ? 6 : 5) * (size_t)std::max(1, n)));
     T *vb = (T *)c->vecs.p;
+    T *r2 = vb + 5 * (size_t)n;
     PcgVecs<T> v;
     v.b = b;
     v.x = x;
@@ -424,9 +426,12 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
             bool done_fac = false;
             if constexpr (F64) {
                 if (fp) {
-                    // beta partials in ws[0] (the SpMV's are merged first), tau in ws[1]
-                    RPCG_TRY(launch_fac_update(mode, l, n, *fp, v, t, c->st, c->ws[0], cfg_sl.grid, c->ws, stride,
-                                               cfg_rows));
+                    // beta partials in ws[0] (the SpMV's are merged first), tau in ws[1];
+                    // r alternates between its buffer and r2
+                    PcgVecs<T> vl = v;
+                    vl.r = (l & 1) ? r2 : v.r;
+                    RPCG_TRY(launch_fac_update(mode, l, n, *fp, vl, (l & 1) ? v.r : r2, t, c->st, c->ws[0],
+                                               cfg_sl.grid, c->ws, stride, cfg_rows));
                     if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
                     RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws, cfg_rows.grid, stride, cfg_rows));
                     done_fac = true;

@@ -216,12 +216,14 @@ struct FacPre {
 // Every step that writes partials runs on cfg.grid workgroups.
 hipError_t launch_fac_setup(int mode, const SellMat<double> &A, const FacPre &P, const PcgVecs<double> &v, double *t,
                             PcgState *st, const DotWs *ws3, int stride, double tol, int maxit, const LaunchCfg &cfg);
-// Iteration l after the SpMV kernel (partials of <d,w> in wsd, Gd slots):
-// merge delta, rho; x, r updates with partials of <r,r> (ws[1]); t = G^T r;
-// z = G t + eps r with partials of <z,r> (ws[0]). The direction kernel then
-// merges ws[0] (beta) and ws[1] (tau).
-hipError_t launch_fac_update(int mode, int l, int n, const FacPre &P, const PcgVecs<double> &v, double *t,
-                             PcgState *st, const DotWs &wsd, int Gd, const DotWs *ws, int stride, const LaunchCfg &cfg);
+// Iteration l after the SpMV kernel (partials of <d,w> in wsd, Gd slots), two
+// launches: merge delta, rho; x update; r update read from v.r and written to
+// r_new (the caller alternates the two buffers), partials of <r,r> (ws[1]),
+// t = G^T r; then z = G t + eps r with partials of <z,r> (ws[0]). The
+// direction kernel then merges ws[0] (beta) and ws[1] (tau).
+hipError_t launch_fac_update(int mode, int l, int n, const FacPre &P, const PcgVecs<double> &v, double *r_new,
+                             double *t, PcgState *st, const DotWs &wsd, int Gd, const DotWs *ws, int stride,
+                             const LaunchCfg &cfg);
 
 // ---- batched solves (many independent systems per launch) ----
 
