@@ -226,6 +226,30 @@ def test_large_closed_form(R):
             assert out.item() == exact, (cond, mode, info)
 
 
+@pytest.mark.slow
+def test_full_size_wide_exponents(R, orc):
+    """The benchmark's workload at full size: 2^28 pairs with exponents
+    uniform over 2^+-200 (the bench's seeds and chunks), in the launch
+    configuration the bench times; both exact modes return the oracle's
+    exact dot, summed over the chunks as exact integers and rounded once."""
+    ne, chunk = 1 << 28, 1 << 24
+    X = torch.empty(ne, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    E = 0
+    for c0 in range(0, ne, chunk):
+        xs, ys = exdot_wide(1000 + c0 // chunk, chunk)
+        X[c0:c0 + chunk].copy_(torch.from_numpy(xs))
+        Y[c0:c0 + chunk].copy_(torch.from_numpy(ys))
+        E += orc.exdot_exact(xs, ys)
+    want = orc.round_exact(E)
+    for mode in ("exblas", "fpe"):
+        print(f"exdot 2^28 wide {mode}", flush=True)
+        out, info = R.exdot(X, Y, mode=mode)
+        assert _same(out.item(), want), mode
+    del X, Y
+    torch.cuda.empty_cache()
+
+
 def test_async_call_without_result(R, orc):
     x, y = exdot_narrow(2, 10000)
     out, info = R.exdot(_dev(x), _dev(y), mode="exblas", sync=False)
