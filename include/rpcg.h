@@ -274,7 +274,7 @@ void rpcg_ir_opts_default(rpcg_ir_opts *opts /* host */);
  * RPCG_WARN_MAXIT when k = maxit. Otherwise s = floor(e / 2) where
  * rr = m 2^e, 1 <= m < 2; the inner binary32 solve (rpcg_pcg_solve_f32
  * semantics, `mode` selects its dot products) runs on rf = RN32(r 2^-s) from
- * c = 0; x = RN(x + c 2^s). An inner solve that stops at its maxit is
+ * c = 0 to the step's inner tolerance (see adaptive_inner); x = RN(x + c 2^s). An inner solve that stops at its maxit is
  * accepted; an inner error ends the call with that error. The outer dots are
  * always exact (EXBLAS) whatever `mode` is. Waits for completion. */
 int rpcg_ir_solve(rpcg_ctx *ctx, rpcg_mode mode, const rpcg_csr *A /* host struct */,
