@@ -116,6 +116,25 @@ def test_fpe_escapes_and_fallback(R, orc):
     assert _same(out.item(), orc.exdot(xn, yn))
 
 
+def test_fpe8_holds_424_bits(R, orc):
+    """Section 4.2: an expansion of eight doubles represents at least
+    8 x 53 = 424 bits. Eight terms with random 53-bit significands, every
+    term just below the previous one, form one 424-bit string: the merge of
+    the eight products into one expansion keeps all of them at p = 8 (no
+    escape, exact without the fallback) and loses one term at p = 7. (A run
+    of equal bits would not do: 2^a - 2^b needs only two terms.)"""
+    rng = np.random.default_rng(42)
+    x = np.array([float(rng.integers(2 ** 52, 2 ** 53)) * 2.0 ** (-53 * k) for k in range(8)])
+    y = np.ones(8)
+    want = orc.exdot(x, y)
+    X, Y = _dev(x), _dev(y)
+    out, info = R.exdot(X, Y, mode="fpe", fpe_size=8, fpe_fallback=0, block_size=64, grid_size=1)
+    assert info["fpe_escapes"] == 0 and info["status"] == 0
+    assert _same(out.item(), want)
+    out, info = R.exdot(X, Y, mode="fpe", fpe_size=7, fpe_fallback=0, block_size=64, grid_size=1)
+    assert info["fpe_escapes"] >= 1 and info["status"] == R.WARN_FPE_INEXACT
+
+
 def test_early_exit_changes_nothing(R, orc):
     x, y = exdot_narrow(9, 30001)
     want = orc.exdot(x, y)
