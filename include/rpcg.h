@@ -113,7 +113,10 @@ typedef struct {
     double tau0;           /* <r0, r0> */
     double tau_final;      /* <r_L, r_L> */
     double threshold;      /* RN(RN(tol*tol) * <b,b>) */
-    int64_t fpe_escapes;   /* expansion overflows seen (FPE mode) */
+    int64_t fpe_escapes;   /* FPE mode: values that did not stay in an expansion (overflow
+                              remainders; in the standalone dot also the products that a lane
+                              whose expansions keep overflowing adds straight into the long
+                              accumulator, which only happens with fpe_fallback set) */
     int64_t fallbacks;     /* FPE mode: dots in which an escape was kept by the long accumulator */
     double setup_ms;       /* wall time of setup (solver) */
     double loop_ms;        /* wall time of the iteration loop (solver) */

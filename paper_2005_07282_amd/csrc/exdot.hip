@@ -20,7 +20,7 @@ k_exdot_part(long long n, const double *__restrict__ x, const double *__restrict
     zero_acc(acc);
     __syncthreads();
 
-    LaneDot<MODE, P, MODE == MODE_EXBLAS> L;
+    LaneDot<MODE, P, MODE != MODE_PLAIN> L;
     L.init();
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;

@@ -79,7 +79,7 @@ __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags
 // result stays exact; without `capture` it is dropped as in the paper.
 // PLAIN: an fma running sum.
 //
-// ADAPT (EXBLAS only): when the expansion keeps overflowing (wide exponent
+// ADAPT (standalone dot): when the expansion keeps overflowing (wide exponent
 // ranges, where nearly every product leaves a remainder), the lane adds
 // the TwoProd halves straight into the long accumulator for a while and
 // skips the expansion arithmetic that would not have absorbed them; one
@@ -135,6 +135,25 @@ struct LaneDot {
                 if (left != 0.0) acc_add_lds(acc, left, flags);
                 left = fpe_accumulate<P>(a, t, ee);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
+            } else if constexpr (ADAPT) {
+                // FPE with the fallback: the same switching; what goes to the
+                // long accumulator directly counts as escaped (it did not stay
+                // in an expansion). Without the fallback the lane never
+                // switches, as remainders are then dropped, not kept.
+                if (direct) {
+                    acc_add_lds(acc, r, flags);
+                    acc_add_lds(acc, t, flags);
+                    esc += (r != 0.0) + (t != 0.0);
+                } else {
+                    double left = fpe_accumulate<P>(a, r, ee);
+                    if (left != 0.0) { ++esc; ++wfl; if (capture) acc_add_lds(acc, left, flags); }
+                    left = fpe_accumulate<P>(e, t, ee);
+                    if (left != 0.0) { ++esc; ++wfl; if (capture) acc_add_lds(acc, left, flags); }
+                }
+                if (++win == ADAPT_WINDOW) {
+                    direct = direct ? direct - 1 : (capture && wfl > ADAPT_WINDOW ? ADAPT_DIRECT : 0);
+                    win = wfl = 0;
+                }
             } else {
                 double left = fpe_accumulate<P>(a, r, ee);
                 if (left != 0.0) { ++esc; if (capture) acc_add_lds(acc, left, flags); }
