@@ -102,6 +102,25 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.rpcg_lp_create(None, 8, 1, None) == rpcg.ERR_INVALID
     assert L.rpcg_lp_train_step(None, 1, None, None, 1, 0.0, 0.0, None, None) == rpcg.ERR_INVALID
     L.rpcg_lp_destroy(None)
+    assert L.rpcg_pcg_solve_factored(None, 2, None, None, None, 1e-6, None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_fpe_size_auto(None, None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_exdot_partial(None, 10, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_batch_get_tuning(None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_lp_set_params(None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_lp_get_params(None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_lp_forward(None, 1, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_lp_factor(None, 1, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_lp_loss_grad(None, 1, None, None, 1, 1e-6, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_lp_backward(None, 1, None, None, None, None) == rpcg.ERR_INVALID
+
+
+def test_status_strings(L):
+    """Every status code has its own description; unknown codes get one too."""
+    from paper_2005_07282_amd import rpcg
+    codes = [0, 1, 2, -1, -2, -3, -4, -5, -6]
+    texts = [L.rpcg_status_string(c) for c in codes]
+    assert all(t for t in texts) and len(set(texts)) == len(codes)
+    assert L.rpcg_status_string(12345)
 
 
 def test_lp_pattern_host(L):
