@@ -29,22 +29,30 @@ constexpr int CONV_BX = 16, CONV_BY = 4;                       // block of outpu
 constexpr int CONV_HX = CONV_BX + 2, CONV_HY = CONV_BY + 2, CONV_HZ = 3; // with halo
 constexpr int CONV_HCELLS = CONV_HX * CONV_HY * CONV_HZ;
 
+// The staged inputs are kept in groups of four channels: group q of cell c
+// is the 8 bytes at tile[(q * P + c) * 4], with a pitch P = 1 (mod 16) cells
+// so that the four groups of one cell fall in different LDS banks.
+__host__ __device__ constexpr int halo_pitch(int cells) { return cells + (17 - cells % 16) % 16; }
+
 // Stage the inputs of the block of BY y-lines of 16 cells at (x0, y0, z) of
-// system b, with a one-cell halo, into tile[(zc * (BY + 2) + yc) * 18 + xc][CIN]
-// (zeros outside the grid). 8-byte units, consecutive threads on consecutive
-// units, so each halo row is one contiguous run.
+// system b, with a one-cell halo, into cells (zc * (BY + 2) + yc) * 18 + xc
+// of tile (zeros outside the grid). 8-byte units; sixteen consecutive
+// threads take one channel group of sixteen consecutive cells, so a
+// wavefront reads whole runs of the input and writes whole LDS rows.
 template <int CIN, int BY>
 __device__ __forceinline__ void stage_halo(bf16_t *tile, const bf16_t *__restrict__ inb, int N, int x0, int y0, int z)
 {
-    constexpr int UPC = CIN / 4, HY = BY + 2, HC = CONV_HX * HY * CONV_HZ;
-    for (int u = threadIdx.x; u < HC * UPC; u += blockDim.x) {
-        const int cell = u / UPC, q = u % UPC;
+    constexpr int UPC = CIN / 4, HY = BY + 2, HC = CONV_HX * HY * CONV_HZ, P = halo_pitch(HC);
+    constexpr int RUNS = (HC + 15) / 16;
+    for (int u = threadIdx.x; u < RUNS * 16 * UPC; u += blockDim.x) {
+        const int q = (u >> 4) % UPC, cell = (u / (16 * UPC)) * 16 + (u & 15);
+        if (cell >= HC) continue;
         const int xc = cell % CONV_HX, yc = (cell / CONV_HX) % HY, zc = cell / (CONV_HX * HY);
         const int X = x0 - 1 + xc, Y = y0 - 1 + yc, Z = z - 1 + zc;
         v4s v = {0, 0, 0, 0};
         if (X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N)
             v = *(const v4s *)(inb + (((long long)Z * N + Y) * N + X) * CIN + 4 * q);
-        *(v4s *)&tile[cell * CIN + 4 * q] = v;
+        *(v4s *)&tile[(q * P + cell) * 4] = v;
     }
 }
 
@@ -56,10 +64,16 @@ __global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const b
 {
     constexpr int TPC = 16 / CIN;                       // taps per chunk
     constexpr int NCH = (LP_TAPS + TPC - 1) / TPC;      // chunks
-    __shared__ bf16_t w[NCH * TPC][16][CIN];
-    __shared__ __attribute__((aligned(16))) bf16_t tile[CONV_HCELLS * CIN];
-    for (int e = threadIdx.x; e < NCH * TPC * 16 * CIN; e += blockDim.x)
-        (&w[0][0][0])[e] = e < LP_TAPS * 16 * CIN ? wt[e] : (bf16_t)0;
+    constexpr int UPC = CIN / 4, P = halo_pitch(CONV_HCELLS);
+    // weights by channel group: w[((t * UPC + q) * 16 + co) * 4 + j] = W[t][co][4q + j]
+    __shared__ __attribute__((aligned(16))) bf16_t w[NCH * TPC * UPC * 16 * 4];
+    __shared__ __attribute__((aligned(16))) bf16_t tile[UPC * P * 4];
+    for (int u = threadIdx.x; u < NCH * TPC * UPC * 16; u += blockDim.x) {
+        const int co = u & 15, q = (u >> 4) % UPC, t = u / (16 * UPC);
+        v4s v = {0, 0, 0, 0};
+        if (t < LP_TAPS) v = *(const v4s *)(wt + (t * 16 + co) * CIN + 4 * q);
+        *(v4s *)&w[u * 4] = v;
+    }
     const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
     const int wave = threadIdx.x >> 6;
     const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + CONV_BY - 1) / CONV_BY;
@@ -83,16 +97,16 @@ __global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const b
 #pragma unroll 3
         for (int c = 0; c < NCH; ++c) {
             const int t = c * TPC + (CIN == 16 ? 0 : g);
-            const int cbase = CIN == 16 ? 4 * g : 0;
+            const int q = CIN == 16 ? g : 0; // channel group
             v4s a = {0, 0, 0, 0};
             if (t < LP_TAPS) {
                 int dz, dy, dx;
                 tap_offset(t, dz, dy, dx);
                 // rows m past the grid's edge read valid LDS cells; their outputs are not stored
                 const int hc = ((dz + 1) * CONV_HY + (wave + dy + 1)) * CONV_HX + (m + dx + 1);
-                a = *(const v4s *)&tile[hc * CIN + cbase];
+                a = *(const v4s *)&tile[(q * P + hc) * 4];
             }
-            const v4s bw = *(const v4s *)&w[t][m][cbase];
+            const v4s bw = *(const v4s *)&w[((t * UPC + q) * 16 + m) * 4];
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
         }
         const int co = m;
@@ -135,7 +149,8 @@ __global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const 
     constexpr int HY = DW_BY + 2;
     __shared__ float sw[LP_TAPS][16][16];
     __shared__ float sbl[DW_BY][4][16]; // [wave][lane group][co]
-    __shared__ __attribute__((aligned(16))) bf16_t tile[CONV_HX * HY * CONV_HZ * CIN];
+    constexpr int P = halo_pitch(CONV_HX * HY * CONV_HZ);
+    __shared__ __attribute__((aligned(16))) bf16_t tile[CIN / 4 * P * 4];
     const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
     const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
     const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + DW_BY - 1) / DW_BY;
@@ -178,7 +193,7 @@ __global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const 
             if (m < CIN) {
                 const int row = ((dz + 1) * HY + (wave + dy + 1)) * CONV_HX + 4 * g;
 #pragma unroll
-                for (int i = 0; i < 6; ++i) v[i] = (short)tile[(row + i) * CIN + m];
+                for (int i = 0; i < 6; ++i) v[i] = (short)tile[((m >> 2) * P + row + i) * 4 + (m & 3)];
             }
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
