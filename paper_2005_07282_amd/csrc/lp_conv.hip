@@ -238,10 +238,13 @@ __global__ void k_lp_reduce(int nslots, int cout, int cin, const float *__restri
         if (i < nw) {
             const int t = i / (cout * cin), o = (i / cin) % cout, c = i % cin;
             const int src = (t * 16 + o) * 16 + c;
+            // the loads run ahead of the adds, which keep the slot order
+#pragma unroll 16
             for (int k = 0; k < nslots; ++k) s += pw[(long long)k * LP_TAPS * 256 + src];
             gw[i] = s;
         } else {
             const int o = i - nw;
+#pragma unroll 16
             for (int k = 0; k < nslots; ++k) s += pb[k * 16 + o];
             gb[o] = s;
         }
