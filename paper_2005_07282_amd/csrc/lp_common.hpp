@@ -45,7 +45,7 @@ enum { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2 };
 // acc where mask [cell][COUT] > 0, else 0 (the adjoint pass of a relu layer).
 hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_t *in, const bf16_t *wt,
                           const float *bias, const float *mask, float *pre, bf16_t *act, hipStream_t s);
-// Partial weight and bias gradients, one slot per workgroup:
+// Partial weight and bias gradients in grid slots (three workgroups per slot, one per dz):
 // pw[g][27][16][16] (out, in), pb[g][16]; then a fixed-order sum over slots.
 hipError_t launch_lp_conv_dw(int cin, int cout, int nb, int N, const bf16_t *in, const bf16_t *dout, float *pw,
                              float *pb, int grid, hipStream_t s);

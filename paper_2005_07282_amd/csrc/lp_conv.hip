@@ -34,21 +34,22 @@ constexpr int CONV_HCELLS = CONV_HX * CONV_HY * CONV_HZ;
 // so that the four groups of one cell fall in different LDS banks.
 __host__ __device__ constexpr int halo_pitch(int cells) { return cells + (17 - cells % 16) % 16; }
 
-// Stage the inputs of the block of BY y-lines of 16 cells at (x0, y0, z) of
-// system b, with a one-cell halo, into cells (zc * (BY + 2) + yc) * 18 + xc
-// of tile (zeros outside the grid). 8-byte units; sixteen consecutive
-// threads take one channel group of sixteen consecutive cells, so a
-// wavefront reads whole runs of the input and writes whole LDS rows.
-template <int CIN, int BY>
-__device__ __forceinline__ void stage_halo(bf16_t *tile, const bf16_t *__restrict__ inb, int N, int x0, int y0, int z)
+// Stage the inputs of the block of BY y-lines of 16 cells at (x0, y0) of
+// system b, with a one-cell halo in x and y, over the HZ planes from z0,
+// into cells (zc * (BY + 2) + yc) * 18 + xc of tile (zeros outside the
+// grid). 8-byte units; sixteen consecutive threads take one channel group of
+// sixteen consecutive cells, so a wavefront reads whole runs of the input
+// and writes whole LDS rows.
+template <int CIN, int BY, int HZ>
+__device__ __forceinline__ void stage_halo(bf16_t *tile, const bf16_t *__restrict__ inb, int N, int x0, int y0, int z0)
 {
-    constexpr int UPC = CIN / 4, HY = BY + 2, HC = CONV_HX * HY * CONV_HZ, P = halo_pitch(HC);
+    constexpr int UPC = CIN / 4, HY = BY + 2, HC = CONV_HX * HY * HZ, P = halo_pitch(HC);
     constexpr int RUNS = (HC + 15) / 16;
     for (int u = threadIdx.x; u < RUNS * 16 * UPC; u += blockDim.x) {
         const int q = (u >> 4) % UPC, cell = (u / (16 * UPC)) * 16 + (u & 15);
         if (cell >= HC) continue;
         const int xc = cell % CONV_HX, yc = (cell / CONV_HX) % HY, zc = cell / (CONV_HX * HY);
-        const int X = x0 - 1 + xc, Y = y0 - 1 + yc, Z = z - 1 + zc;
+        const int X = x0 - 1 + xc, Y = y0 - 1 + yc, Z = z0 + zc;
         v4s v = {0, 0, 0, 0};
         if (X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N)
             v = *(const v4s *)(inb + (((long long)Z * N + Y) * N + X) * CIN + 4 * q);
@@ -89,7 +90,7 @@ __global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const b
         const int x0 = tx * CONV_BX, y0 = ty * CONV_BY;
         const bf16_t *inb = in + b * N3 * CIN;
         __syncthreads(); // the previous block's readers are done (and the weights are in place)
-        stage_halo<CIN, CONV_BY>(tile, inb, N, x0, y0, z);
+        stage_halo<CIN, CONV_BY, CONV_HZ>(tile, inb, N, x0, y0, z - 1);
         __syncthreads();
         const int y = y0 + wave;
         if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
@@ -133,12 +134,17 @@ __global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const b
 
 // Weight gradient dW[t][co][ci] = sum over cells of dout[cell][co] in[cell + off(t)][ci]
 // and bias gradient db[co] = sum of dout[cell][co], on 16x16x16 MFMA with
-// M = co, N = ci, K = the 16 cells of a tile. A workgroup of DW_BY wavefronts
-// takes blocks of 16 x DW_BY x 1 cells (one y-line per wavefront), stages
-// their inputs with the halo in LDS, and each wavefront accumulates its
-// line's 27 tap products; the B operands come from LDS, six cells per
-// (dz, dy) serving the three dx taps. Each workgroup sums its waves in wave
-// order and writes one slot; the slots are summed in slot order later.
+// M = co, N = ci, K = the 16 cells of a tile. The workgroups come in threes
+// per slot, one for each dz, so a workgroup keeps the nine tap tiles of its
+// dz plane (not all 27), which leaves room for more wavefronts per SIMD. A
+// workgroup of DW_BY wavefronts takes blocks of 16 x DW_BY x 1 cells (one
+// y-line per wavefront), stages the inputs of its plane with the x and y
+// halo in LDS, and each wavefront accumulates its line's nine tap products;
+// the B operands come from LDS, six cells per dy serving the three dx taps.
+// The three workgroups of a slot take the same blocks in the same order, so
+// each tap sums exactly as one workgroup with all 27 taps would. Each
+// workgroup sums its waves in wave order and writes its taps of the slot;
+// the slots are summed in slot order later.
 constexpr int DW_BY = 8;
 
 template <int CIN, int COUT>
@@ -146,21 +152,21 @@ __global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const 
                                                           const bf16_t *__restrict__ dout, float *__restrict__ pw,
                                                           float *__restrict__ pb)
 {
-    constexpr int HY = DW_BY + 2;
-    __shared__ float sw[LP_TAPS][16][16];
+    constexpr int HY = DW_BY + 2, P = halo_pitch(CONV_HX * HY);
+    __shared__ float sw[9][16][16];
     __shared__ float sbl[DW_BY][4][16]; // [wave][lane group][co]
-    constexpr int P = halo_pitch(CONV_HX * HY * CONV_HZ);
     __shared__ __attribute__((aligned(16))) bf16_t tile[CIN / 4 * P * 4];
     const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
     const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+    const int dzi = blockIdx.x % 3, slot = blockIdx.x / 3, nslots = gridDim.x / 3; // taps 9 dzi .. 9 dzi + 8
     const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + DW_BY - 1) / DW_BY;
     const long long nblocks = (long long)nb * N * tiles_y * tiles_x;
     const long long N3 = (long long)N * N * N;
-    v4f acc[LP_TAPS];
+    v4f acc[9];
 #pragma unroll
-    for (int t = 0; t < LP_TAPS; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 9; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    for (long long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) { // workgroup-uniform
+    for (long long blk = slot; blk < nblocks; blk += nslots) { // workgroup-uniform
         const int tx = (int)(blk % tiles_x);
         long long r = blk / tiles_x;
         const int ty = (int)(r % tiles_y);
@@ -169,7 +175,7 @@ __global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const 
         const long long b = r / N;
         const int x0 = tx * CONV_BX, y0 = ty * DW_BY;
         __syncthreads(); // the previous block's readers are done
-        stage_halo<CIN, DW_BY>(tile, in + b * N3 * CIN, N, x0, y0, z);
+        stage_halo<CIN, DW_BY, 1>(tile, in + b * N3 * CIN, N, x0, y0, z + dzi - 1);
         __syncthreads();
         const int y = y0 + wave;
         if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
@@ -187,27 +193,26 @@ __global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const 
         // B[k = cell 4g + j][n = ci] = in[cell + off(t)][ci]; columns past the
         // row end meet zero A entries, so their (finite) values do not matter
 #pragma unroll
-        for (int zy = 0; zy < 9; ++zy) {
-            const int dz = zy / 3 - 1, dy = zy % 3 - 1;
+        for (int dy3 = 0; dy3 < 3; ++dy3) {
             short v[6] = {0, 0, 0, 0, 0, 0};
             if (m < CIN) {
-                const int row = ((dz + 1) * HY + (wave + dy + 1)) * CONV_HX + 4 * g;
+                const int row = (wave + dy3) * CONV_HX + 4 * g;
 #pragma unroll
                 for (int i = 0; i < 6; ++i) v[i] = (short)tile[((m >> 2) * P + row + i) * 4 + (m & 3)];
             }
 #pragma unroll
             for (int dx = 0; dx < 3; ++dx) {
                 const v4s bv = {v[dx], v[dx + 1], v[dx + 2], v[dx + 3]};
-                acc[zy * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[zy * 3 + dx], 0, 0, 0);
+                acc[dy3 * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[dy3 * 3 + dx], 0, 0, 0);
             }
         }
     }
-    // workgroup sum in wave order; lane l holds dW[t][4g + j][l % 16]
+    // workgroup sum in wave order; lane l holds dW[9 dzi + t][4g + j][l % 16]
     sbl[wave][g][m] = bsum;
     for (int w = 0; w < waves; ++w) {
         if (wave == w) {
 #pragma unroll
-            for (int t = 0; t < LP_TAPS; ++t)
+            for (int t = 0; t < 9; ++t)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     float &dst = sw[t][4 * g + j][m];
@@ -216,13 +221,13 @@ __global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const 
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < LP_TAPS * 256; e += blockDim.x)
-        pw[(long long)blockIdx.x * LP_TAPS * 256 + e] = (&sw[0][0][0])[e];
-    if (threadIdx.x < 16) {
+    for (int e = threadIdx.x; e < 9 * 256; e += blockDim.x)
+        pw[((long long)slot * LP_TAPS + 9 * dzi) * 256 + e] = (&sw[0][0][0])[e];
+    if (dzi == 0 && threadIdx.x < 16) {
         float t = 0.f;
         for (int w = 0; w < waves; ++w)
             for (int gg = 0; gg < 4; ++gg) t += sbl[w][gg][threadIdx.x];
-        pb[blockIdx.x * 16 + threadIdx.x] = t;
+        pb[slot * 16 + threadIdx.x] = t;
     }
 }
 
@@ -314,6 +319,7 @@ hipError_t launch_lp_conv_dw(int cin, int cout, int nb, int N, const bf16_t *in,
                              float *pb, int grid, hipStream_t s)
 {
     const int block = 64 * DW_BY;
+    grid *= 3; // one workgroup per slot and dz
     if (cin == 16 && cout == 4)
         k_lp_conv_dw<16, 4><<<grid, block, 0, s>>>(nb, N, in, dout, pw, pb);
     else if (cin == 16 && cout == 16)
