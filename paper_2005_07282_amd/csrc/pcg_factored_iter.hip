@@ -17,8 +17,8 @@ __global__ void k_fac_gt(int n, FacPre Pr, const double *__restrict__ r, double 
 }
 
 // Iteration l after the SpMV kernel, first launch. Prologue: merge delta,
-// rho = beta / delta. Per row i: S4 r_i = fma(-rho, w_i, r_i) into the
-// other r buffer (S3 is left to the direction kernel), with the partials of
+// rho = beta / delta. Per row i: S3 x_i = fma(rho, d_i, x_i); S4 r_i =
+// fma(-rho, w_i, r_i) into the other r buffer, with the partials of
 // tau = <r, r> (wt); and t_i = (G^T r)_i, the fma chain of row i of G^T in
 // storage order from +0 over the new r. r_old is only read, so a row
 // recomputes each neighbour's new r_j from w_j and r_old_j (the same bits as
@@ -51,6 +51,7 @@ k_fac_update(int l, int n, FacPre Pr, PcgVecs<double> v, const double *__restric
     const double *__restrict__ w = v.w;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
+        v.x[i] = __builtin_fma(rho, v.d[i], v.x[i]);              // S3
         const double ri = __builtin_fma(-rho, w[i], r_old[i]);     // S4
         r_new[i] = ri;
         Lt.add(ri, ri, sh.acc[1], ee, capture);                    // S8

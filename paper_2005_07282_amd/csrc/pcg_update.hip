@@ -1,15 +1,11 @@
 // Jacobi-PCG iteration, second and third kernels.
 //
 // K2 starts by merging the SpMV kernel's partials of <d, w> (every workgroup
-// alike) into delta and rho = beta / delta (S2), then updates the residual,
-// applies the Jacobi preconditioner (S4, S5) and forms the partials of
+// alike) into delta and rho = beta / delta (S2), then applies the vector
+// updates and the Jacobi preconditioner (S3-S5) and forms the partials of
 // beta = <z, r> and tau = <r, r> (S6, S8).
 // K3 starts by merging those into beta, tau and gamma = beta / beta_old, runs
-// the stopping test of Fig. 1, and updates the iterate with this iteration's
-// direction (S3) and then the direction itself (S7). S3 sits in K3 because
-// K3 loads d anyway: nothing reads x before the solve ends, and the fma has
-// the same operands either way, so the iterate keeps its bits while K2 no
-// longer reads d and x or writes x (8 bytes less per row and iteration).
+// the stopping test of Fig. 1, and updates the search direction (S7).
 //
 // The iteration number l is a launch argument, so the scalars one kernel
 // writes for later iterations (beta history, tau history, done flag) are
@@ -50,7 +46,8 @@ k_pcg_update(int l, int n, PcgVecs<T> v, PcgState *st, SlotView sd, int Gd, Slot
     Lt.init();
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const T wi = v.w[i];
+        const T di = v.d[i], wi = v.w[i];
+        v.x[i] = fma_t(rho, di, v.x[i]);                  // S3
         const T ri = fma_t(-rho, wi, v.r[i]);             // S4
         const T zi = v.dinv[i] * ri;                      // S5
         v.r[i] = ri;
@@ -74,13 +71,12 @@ k_pcg_direction(int l, int n, PcgVecs<T> v, PcgState *st, SlotView wb, SlotView 
     if (wg_read_flag(&st->done, sh)) return;
     const long long i0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long stride = (long long)gridDim.x * blockDim.x;
-    T dv[DIR_PREFETCH], zv[DIR_PREFETCH], xv[DIR_PREFETCH];
+    T dv[DIR_PREFETCH], zv[DIR_PREFETCH];
 #pragma unroll
     for (int j = 0; j < DIR_PREFETCH; ++j) {
         const long long i = i0 + j * stride;
         dv[j] = i < n ? v.d[i] : T(0);
         zv[j] = i < n ? v.z[i] : T(0);
-        xv[j] = i < n ? v.x[i] : T(0);
     }
     long long eb = 0, et = 0;
     const T beta = merge_slots<MODE, P, T>(wb, G, ee, capture, sh.acc[0], &eb, &st->flags, sh, 0);
@@ -102,33 +98,16 @@ k_pcg_direction(int l, int n, PcgVecs<T> v, PcgState *st, SlotView wb, SlotView 
         }
         if (stop) st->done = 1;
     }
-    // S3 belongs to this iteration whether or not it is the last one
-    const T rho = (T)st->rho;
-    if (stop) {
-#pragma unroll
-        for (int j = 0; j < DIR_PREFETCH; ++j) {
-            const long long i = i0 + j * stride;
-            if (i < n) v.x[i] = fma_t(rho, dv[j], xv[j]);  // S3
-        }
-        for (long long i = i0 + DIR_PREFETCH * stride; i < n; i += stride)
-            v.x[i] = fma_t(rho, v.d[i], v.x[i]);
-        return;
-    }
+    if (stop) return;
     const T gamma = beta / (T)v.beta_hist[l];
     if (blockIdx.x == 0 && threadIdx.x == 0) st->gamma = gamma;
 #pragma unroll
     for (int j = 0; j < DIR_PREFETCH; ++j) {
         const long long i = i0 + j * stride;
-        if (i < n) {
-            v.x[i] = fma_t(rho, dv[j], xv[j]);            // S3
-            v.d[i] = fma_t(gamma, dv[j], zv[j]);          // S7
-        }
+        if (i < n) v.d[i] = fma_t(gamma, dv[j], zv[j]);   // S7
     }
-    for (long long i = i0 + DIR_PREFETCH * stride; i < n; i += stride) {
-        const T di = v.d[i];
-        v.x[i] = fma_t(rho, di, v.x[i]);
-        v.d[i] = fma_t(gamma, di, v.z[i]);
-    }
+    for (long long i = i0 + DIR_PREFETCH * stride; i < n; i += stride)
+        v.d[i] = fma_t(gamma, v.d[i], v.z[i]);
 }
 
 template <typename T>
