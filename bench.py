@@ -64,9 +64,9 @@ def k1_traffic():
 
 def iteration_bytes(n, nnz):
     """Algorithmic bytes of one fused PCG iteration (three kernels): K1, then
-    K2 reading w, r, dinv and writing r, z (40 n), then K3 reading d, z, x and
-    writing d, x (40 n)."""
-    return k1_bytes(n, nnz) + 40 * n + 40 * n
+    K2 reading x, d, w, r, dinv and writing x, r, z (64 n), then K3 reading
+    d, z and writing d (24 n)."""
+    return k1_bytes(n, nnz) + 64 * n + 24 * n
 
 
 def run_mixed_precision(N, rpcg, torch, dev):
@@ -189,8 +189,7 @@ def run_batched(seed, rpcg, torch, dev):
         same += int(i1["iterations"] == infos[k]["iterations"] and torch.equal(x1, xs[k]))
     B.close()
     row_it = sum(r * i["iterations"] for r, i in zip(rows, infos))
-    # algorithmic bytes of one iteration of a system: 12 nnz + 4 (n+1) + 104 n (the batched update
-    # kernel applies S3 with S4, so it reads d and x and writes x: 64 n, and the direction kernel 24 n)
+    # algorithmic bytes of one iteration of a system (as for the single solve): 12 nnz + 4 (n+1) + 104 n
     it_bytes = sum((12 * z + 4 * (r + 1) + 104 * r) * i["iterations"] for r, z, i in zip(rows, nnz, infos))
     out = {
         "workload": f"64 systems, 7-point diffusion with exp(N(0,1)) face coefficients on N^3 grids, N uniform "

@@ -7,9 +7,16 @@
 // K3 starts by merging those into beta, tau and gamma = beta / beta_old, runs
 // the stopping test of Fig. 1, and updates the search direction (S7).
 //
-// The iteration number l is a launch argument, so the scalars one kernel
-// writes for later iterations (beta history, tau history, done flag) are
-// never read by another workgroup of the same kernel.
+// The iteration number l is a launch argument, so the beta and tau histories
+// one kernel writes for later iterations are never read by another
+// workgroup of the same kernel. The done flag is: when K3 stops (or K2
+// breaks down), workgroups of the same launch that start after the first one
+// has set it return at once. So everything an iteration must still complete
+// after its stopping test belongs in K2, which runs before the flag can be
+// set by the test; K3 only updates d, which is not needed after a stop. (S3
+// in K3, where d is already loaded, saves 8 bytes per row, but its late
+// workgroups then skip the last update of x whenever the grid is larger than
+// what the chip holds at once.)
 #include "reduce.hpp"
 #include "sell_spmv.hpp"
 

@@ -242,6 +242,15 @@ def test_160_cube_first_iterations_bitexact(R, orc):
     x, info = _solve(R, A, b, "exblas", maxit=3)
     assert _eq(info["hist"].numpy(), ref["hist"])
     assert _eq(x, ref["x"])
+    # vector-kernel grids larger than the chip holds at once: workgroups that
+    # start after the stopping test has set the done flag must find nothing
+    # of the last iteration left to do
+    for grid, block in ((1024, 512), (512, 1024), (2048, 256), (4096, 256)):
+        for mode in ("exblas", "fpe"):
+            print(f"pcg 160^3 maxit=3 {mode} grid={grid} block={block}", flush=True)
+            x, info = _solve(R, A, b, mode, maxit=3, grid_size=grid, block_size=block)
+            assert _eq(info["hist"].numpy(), ref["hist"]), (mode, grid, block)
+            assert _eq(x, ref["x"]), (mode, grid, block)
     print("pcg 160^3 full", flush=True)
     x, info = _solve(R, A, b, "exblas")
     assert info["status"] == 0
