@@ -90,6 +90,20 @@ def test_f32_launch_config_invariance(R, f1, mode):
         assert _bits_eq(x, ref["x"]), (block, grid)
 
 
+def test_f32_160_cube_large_grids(R, orc):
+    """Binary32 iteration at 160^3, first three iterations against the oracle,
+    with vector-kernel grids larger than the chip holds at once (workgroups
+    that start after the stopping test has set the done flag)."""
+    A, b32 = _f32_problem(160, 2)
+    ref = orc.pcg_f32(A, b32, tol=1e-6, maxit=3)
+    for grid, block in ((0, 0), (1024, 512), (4096, 256)):
+        for mode in ("exblas", "fpe"):
+            print(f"pcg_f32 160^3 maxit=3 {mode} grid={grid} block={block}", flush=True)
+            x, info = _solve32(R, A, b32, mode, tol=1e-6, maxit=3, grid_size=grid, block_size=block)
+            assert _bits_eq(info["hist"].numpy(), ref["hist"]), (mode, grid, block)
+            assert _bits_eq(x, ref["x"]), (mode, grid, block)
+
+
 @pytest.mark.parametrize("case", ["spd_small", "stencil7", "ragged_n", "nonzero_x0"])
 def test_f32_other_systems(R, orc, case):
     x0 = None

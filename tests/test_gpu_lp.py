@@ -193,6 +193,30 @@ def test_solve_with_network_factor_bitexact(R, orc, net10):
     assert np.array_equal(x.cpu().numpy(), ref["x"])
 
 
+def test_factored_solve_64_cube_large_grids(R, orc):
+    """The factored iteration at 64^3 (262,144 rows) with the network's G,
+    first five iterations against the oracle, with vector-kernel grids
+    larger than the chip holds at once."""
+    N = 64
+    net = R.LearnedPreconditioner(N, max_batch=1)
+    net.set_params(params(1))
+    A = systems(N, [23])[0]
+    (G, Gt), = net.factor([R.CSR.from_host(A)])
+    grp, gcol, gtrp, gtcol = net.pattern
+    Gh = CSRHost(N ** 3, grp, gcol, G.val.cpu().numpy())
+    Gth = CSRHost(N ** 3, gtrp, gtcol, Gt.val.cpu().numpy())
+    b = uniform_pm1(51, A.n)
+    ref = orc.pcg_factored(A, Gh, Gth, 1e-6, b, tol=1e-10, maxit=5)
+    for grid, block in ((0, 0), (2048, 512), (4096, 256)):
+        print(f"factored 64^3 maxit=5 grid={grid} block={block}", flush=True)
+        x, info = R.pcg_solve_factored(R.CSR.from_host(A), G, Gt, 1e-6, torch.from_numpy(b).cuda(), tol=1e-10,
+                                       maxit=5, raise_on_error=False, grid_size=grid, block_size=block)
+        assert info["iterations"] == ref["iters"], (grid, block)
+        assert np.array_equal(info["hist"].numpy(), ref["hist"]), (grid, block)
+        assert np.array_equal(x.cpu().numpy(), ref["x"]), (grid, block)
+    net.close()
+
+
 @pytest.mark.slow
 def test_trained_network_beats_jacobi(R):
     """The committed parameters (trained on 2,000 instances of 64^3) against
