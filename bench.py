@@ -69,6 +69,27 @@ def iteration_bytes(n, nnz):
     return k1_bytes(n, nnz) + 64 * n + 24 * n
 
 
+def measure_stream_read(torch, dev, nbytes=2 << 30, reps=10):
+    """Read bandwidth of a plain streaming reduction on this GPU (torch's own
+    sum kernel over one binary64 vector of nbytes), as a measured ceiling
+    beside the nominal HBM peak: bytes / fastest of reps timed calls."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    torch.sum(x)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.sum(x)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del x
+    torch.cuda.empty_cache()
+    return nbytes / (best * 1e-3) / 1e9
+
+
 def run_mixed_precision(N, rpcg, torch, dev):
     """Mixed-precision refinement on the 27-point operator of an N^3 grid
     (binary32 inner Jacobi-PCG to 1e-4 with exact binary32 dots, binary64
@@ -554,6 +575,8 @@ def main():
     stress = run_stress(args.stress_n, 100, args.stress_ill_n, 200, rpcg, torch, dev) if args.stress_n > 0 else None
 
     traffic = k1_traffic() if N == 160 else None
+    stream_gbs = measure_stream_read(torch, dev)
+    log(f"[bench] stream read (torch.sum, 2 GiB binary64) {stream_gbs:.1f} GB/s")
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -596,6 +619,8 @@ def main():
             "traffic": traffic,
             "kernel": "k_pcg_spmv_dot<exblas, 3, 16-bit column codes, binary64>",
             "bytes_per_launch": k1_bytes(n, nnz),
+            "stream_read": {"GB_s": round(stream_gbs, 1), "frac": round(k1_gbs / stream_gbs, 4),
+                            "kernel": "torch.sum over a 2 GiB binary64 vector (fastest of 10)"},
         },
         "cpu_baseline": cpu,
     }
