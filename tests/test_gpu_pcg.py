@@ -232,6 +232,23 @@ def test_timing_fields(R, w1):
 
 
 @pytest.mark.slow
+def test_64_cube_full_solve_bitexact(R, orc):
+    """A full solve to 1e-8 at 64^3 (n = 262,144: many workgroups and slots in
+    every kernel), bit-identical to the oracle in both exact modes, with the
+    default launch shapes and with grids larger than the chip holds at once."""
+    A, b, _ = stencil_problem(64, 3)
+    print("pcg 64^3 oracle", flush=True)
+    ref = orc.pcg(A, b, tol=1e-8, maxit=2000)
+    assert ref["status"] == 0
+    for mode in ("exblas", "fpe"):
+        for grid, block, sg in ((0, 0, 0), (2048, 256, 4096)):
+            print(f"pcg 64^3 {mode} grid={grid} block={block} spmv_grid={sg}", flush=True)
+            x, info = _solve(R, A, b, mode, grid_size=grid, block_size=block, spmv_grid_size=sg)
+            assert info["status"] == 0 and info["iterations"] == ref["iters"], (mode, grid)
+            assert _eq(info["hist"].numpy(), ref["hist"]), (mode, grid)
+            assert _eq(x, ref["x"]), (mode, grid)
+
+
 def test_160_cube_first_iterations_bitexact(R, orc):
     """Full-size operator (160^3, the bench configuration): the first three
     iterations match the oracle bit for bit; the full solve converges with
