@@ -36,6 +36,9 @@ def k1_bytes(n, nnz):
 
 K1_SOURCES = ("pcg_spmv_dot.hip", "sell_spmv.hpp", "reduce.hpp", "numerics.hpp", "kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_160cube_hbm_traffic.md")
+# the timed loop brackets the SpMV+dot launch of every 4th iteration with HIP
+# events (the kernel's mean duration over those launches; fewer events in the loop)
+K1_TIMING_STRIDE = 4
 
 
 def k1_source_hash():
@@ -485,8 +488,9 @@ def main():
         log(f"[bench] PCG {mode}: warmup {args.warmup} iterations")
         solve(mode, max(1, args.warmup))
         log(f"[bench] PCG {mode}: timing {args.steps} iterations")
-        # every mode is timed alike: HIP events around each SpMV+dot launch only
-        x, info = solve(mode, args.steps, timing=2)
+        # every mode is timed alike: HIP events around the SpMV+dot launch of
+        # every K1_TIMING_STRIDE-th iteration only
+        x, info = solve(mode, args.steps, timing=K1_TIMING_STRIDE + 1)
         if info["iterations"] != args.steps:
             log(f"[bench] note: {mode} stopped after {info['iterations']} iterations")
         res[mode] = info

@@ -94,9 +94,11 @@ typedef struct {
                               0 = auto, else 64..1024, multiple of 64 */
     int32_t grid_size;     /* workgroups of the dot and vector kernels: 0 = auto, else 1..65536 */
     int32_t timing;        /* 1: bracket every solver kernel with HIP events and report
-                              per-kernel times in rpcg_result (solver only); 2: bracket
-                              only the SpMV+dot kernel (fewer events in the loop);
-                              0: none (default). Other values: RPCG_ERR_INVALID */
+                              per-kernel times in rpcg_result (solver only); 2..65: bracket
+                              only the SpMV+dot kernel, of every (timing-1)-th iteration
+                              (iterations 0, timing-1, ...; 2 = every iteration): fewer
+                              events in the loop; 0: none (default). Other values:
+                              RPCG_ERR_INVALID */
     int32_t xcd_parts;     /* SpMV work split into this many contiguous row ranges, one per
                               XCD (0 = auto = 1, no split). Results do not depend on it. */
     int32_t spmv_block_size; /* solver SpMV kernel: threads per workgroup (0 = auto) */
@@ -120,10 +122,10 @@ typedef struct {
     int64_t fallbacks;     /* FPE mode: dots in which an escape was kept by the long accumulator */
     double setup_ms;       /* wall time of setup (solver) */
     double loop_ms;        /* wall time of the iteration loop (solver) */
-    double k_spmv_dot_ms;  /* timing=1,2: summed HIP-event time of the SpMV+dot kernel */
-    double k_update_ms;    /* timing=1: summed time of the update+two-dot kernel (0 with timing=2) */
-    double k_direction_ms; /* timing=1: summed time of the direction-update kernel (0 with timing=2) */
-    int32_t k_launches;    /* timing=1,2: iterations whose kernels were timed */
+    double k_spmv_dot_ms;  /* timing>=1: summed HIP-event time of the SpMV+dot kernel */
+    double k_update_ms;    /* timing=1: summed time of the update+two-dot kernel (0 with timing>=2) */
+    double k_direction_ms; /* timing=1: summed time of the direction-update kernel (0 with timing>=2) */
+    int32_t k_launches;    /* timing>=1: iterations whose kernels were timed */
     int32_t grid_size;     /* launch configuration actually used */
     int32_t block_size;
 } rpcg_result;

@@ -405,7 +405,8 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
     auto t1 = std::chrono::steady_clock::now();
 
     const bool timing = o.timing != 0;
-    const bool k1_only = o.timing == 2;
+    const bool k1_only = o.timing >= 2;
+    const int kstride = k1_only ? o.timing - 1 : 1; // iterations between timed SpMV launches
     const int batch = 8;
     if (timing) {
         int rc = ensure_events(c->events, (size_t)EV_PER_IT * std::max(1, o.maxit));
@@ -418,7 +419,7 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
         int cnt = std::min(batch, o.maxit - launched);
         for (int it = 0; it < cnt; ++it) {
             const int l = launched + it;
-            hipEvent_t *ev = timing ? &c->events[(size_t)l * EV_PER_IT] : nullptr;
+            hipEvent_t *ev = (timing && l % kstride == 0) ? &c->events[(size_t)l * EV_PER_IT] : nullptr;
             if (ev) RPCG_TRY(hipEventRecord(ev[0], s));
             RPCG_TRY(launch_pcg_spmv_dot<T>(mode, M, v, c->st, c->ws[0], stride, cfg_sl));
             if (ev) RPCG_TRY(hipEventRecord(ev[1], s));
@@ -470,13 +471,14 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
     if (timing) {
         // the first L iterations did the work; later launches were no-ops
         const int L = std::min(S.iter, launched);
-        for (int i = 0; i < L; ++i)
+        int timed = 0;
+        for (int i = 0; i < L; i += kstride, ++timed)
             for (int k = 0; k < (k1_only ? 1 : 3); ++k) {
                 float ms = 0.f;
                 hipEvent_t *ev = &c->events[(size_t)i * EV_PER_IT];
                 if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) == hipSuccess) out->k_ms[k] += ms;
             }
-        out->k_launches = L;
+        out->k_launches = timed;
     }
     return RPCG_OK;
 }

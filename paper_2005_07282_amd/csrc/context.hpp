@@ -89,7 +89,7 @@ inline bool valid_opts(const rpcg_opts &o)
     if (o.spmv_block_size != 0 && (o.spmv_block_size < 64 || o.spmv_block_size > MAX_BLOCK || o.spmv_block_size % 64))
         return false;
     if (o.spmv_grid_size < 0 || o.spmv_grid_size > 65536) return false;
-    if (o.timing < 0 || o.timing > 2) return false;
+    if (o.timing < 0 || o.timing > 65) return false;
     return true;
 }
 

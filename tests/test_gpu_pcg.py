@@ -222,16 +222,21 @@ def test_timing_fields(R, w1):
     assert info["k_launches"] == ref["iters"]
     assert info["k_spmv_dot_ms"] > 0 and info["k_update_ms"] > 0 and info["k_direction_ms"] > 0
     assert _eq(x, ref["x"])
-    # timing = 2 brackets only the SpMV+dot kernel; other values are rejected
+    # timing = 2 brackets only the SpMV+dot kernel; timing = k + 1 only that
+    # of every k-th iteration; other values are rejected
     x, info = _solve(R, A, b, "exblas", timing=2)
     assert info["k_launches"] == ref["iters"]
     assert info["k_spmv_dot_ms"] > 0 and info["k_update_ms"] == 0 and info["k_direction_ms"] == 0
     assert _eq(x, ref["x"])
-    with pytest.raises(R.RpcgError):
-        _solve(R, A, b, "exblas", timing=3)
+    x, info = _solve(R, A, b, "exblas", timing=5)
+    assert info["k_launches"] == (ref["iters"] + 3) // 4
+    assert info["k_spmv_dot_ms"] > 0 and info["k_update_ms"] == 0 and info["k_direction_ms"] == 0
+    assert _eq(x, ref["x"])
+    for bad in (-1, 66):
+        with pytest.raises(R.RpcgError):
+            _solve(R, A, b, "exblas", timing=bad)
 
 
-@pytest.mark.slow
 def test_64_cube_full_solve_bitexact(R, orc):
     """A full solve to 1e-8 at 64^3 (n = 262,144: many workgroups and slots in
     every kernel), bit-identical to the oracle in both exact modes, with the
@@ -249,6 +254,7 @@ def test_64_cube_full_solve_bitexact(R, orc):
             assert _eq(x, ref["x"]), (mode, grid)
 
 
+@pytest.mark.slow
 def test_160_cube_first_iterations_bitexact(R, orc):
     """Full-size operator (160^3, the bench configuration): the first three
     iterations match the oracle bit for bit; the full solve converges with
