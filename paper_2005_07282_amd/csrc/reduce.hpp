@@ -68,6 +68,43 @@ __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags
     if (c.c2) atomicAdd((unsigned long long *)&acc[c.k + 2], (unsigned long long)c.c2);
 }
 
+// Exact product x y added to the long accumulator as one integer: the
+// 106-bit product of the significands, shifted onto the accumulator's word
+// grid, in up to five 32-bit chunks. It is the same exact value as RN(x y)
+// plus its TwoProd error, added with one atomic fewer on average. The caller
+// ensures RN(x y) is finite and at least 2^-969 in magnitude: then x and y
+// are finite and nonzero, TwoProd is exact, and the product's bits lie
+// between the accumulator's lowest weight and its top word.
+__device__ __forceinline__ void acc_add_product_lds(long long *acc, double x, double y)
+{
+    const unsigned long long bx = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long by = __builtin_bit_cast(unsigned long long, y);
+    int ex = (int)((bx >> 52) & 0x7FF), ey = (int)((by >> 52) & 0x7FF);
+    unsigned long long mx = bx & 0xFFFFFFFFFFFFFull, my = by & 0xFFFFFFFFFFFFFull;
+    if (ex) mx |= 1ull << 52;
+    else ex = 1;
+    if (ey) my |= 1ull << 52;
+    else ey = 1;
+    // x y = mx my 2^(ex + ey - 2150); off = offset of its last bit above 2^ACC_EXP0
+    const int off = ex + ey - 2150 - ACC_EXP0;
+    const int k = off >> 5, s = off & 31;
+    const unsigned long long lo = mx * my, hi = __umul64hi(mx, my); // hi < 2^42
+    const unsigned long long w0 = lo << s;
+    const unsigned long long w1 = (hi << s) | (s ? lo >> (64 - s) : 0ull);
+    const unsigned long long w2 = s ? hi >> (64 - s) : 0ull;
+    const long long c[5] = {(long long)(w0 & 0xFFFFFFFFull), (long long)(w0 >> 32), (long long)(w1 & 0xFFFFFFFFull),
+                            (long long)(w1 >> 32), (long long)w2};
+    const bool neg = ((bx ^ by) >> 63) != 0;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        if (c[i]) atomicAdd((unsigned long long *)&acc[k + i], (unsigned long long)(neg ? -c[i] : c[i]));
+}
+
+__device__ __forceinline__ bool product_in_integer_range(double r)
+{
+    return is_finite_bits(r) && __builtin_fabs(r) >= 0x1p-969;
+}
+
 // Per-lane accumulator of one dot product.
 //
 // EXBLAS (Section 4.1, Listing 1): the TwoProd result and error go into one
@@ -81,7 +118,7 @@ __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags
 //
 // ADAPT (standalone dot): when the expansion keeps overflowing (wide exponent
 // ranges, where nearly every product leaves a remainder), the lane adds
-// the TwoProd halves straight into the long accumulator for a while and
+// the exact products straight into the long accumulator for a while and
 // skips the expansion arithmetic that would not have absorbed them; one
 // window in eight measures the overflow rate again. Either path adds the
 // exact products, so the result does not depend on the switching.
@@ -117,8 +154,12 @@ struct LaneDot {
             if (__builtin_fabs(r) < 0x1p-969 && x != 0.0 && y != 0.0) flags |= FLAG_INEXACT;
             if constexpr (MODE == MODE_EXBLAS && ADAPT) {
                 if (direct) {
-                    acc_add_lds(acc, r, flags);
-                    acc_add_lds(acc, t, flags);
+                    if (product_in_integer_range(r)) {
+                        acc_add_product_lds(acc, x, y);
+                    } else {
+                        acc_add_lds(acc, r, flags);
+                        acc_add_lds(acc, t, flags);
+                    }
                 } else {
                     double left = fpe_accumulate<P>(a, r, ee);
                     if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
@@ -141,8 +182,12 @@ struct LaneDot {
                 // in an expansion). Without the fallback the lane never
                 // switches, as remainders are then dropped, not kept.
                 if (direct) {
-                    acc_add_lds(acc, r, flags);
-                    acc_add_lds(acc, t, flags);
+                    if (product_in_integer_range(r)) {
+                        acc_add_product_lds(acc, x, y);
+                    } else {
+                        acc_add_lds(acc, r, flags);
+                        acc_add_lds(acc, t, flags);
+                    }
                     esc += (r != 0.0) + (t != 0.0);
                 } else {
                     double left = fpe_accumulate<P>(a, r, ee);
