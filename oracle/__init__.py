@@ -59,15 +59,16 @@ def lib():
         L.rpcg_oracle_spmv_f32.restype = None
         L.rpcg_oracle_spmv_f32.argtypes = [ctypes.c_int32, P, P, P, P, P]
         L.rpcg_oracle_pcg_f32.restype = ctypes.c_int
-        L.rpcg_oracle_pcg_f32.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, P, P]
+        L.rpcg_oracle_pcg_f32.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, P, P,
+                                          P, P, P, P]
         L.rpcg_oracle_ir_scale.restype = ctypes.c_int
         L.rpcg_oracle_ir_scale.argtypes = [ctypes.c_double]
         L.rpcg_oracle_pcg_factored.restype = ctypes.c_int
         L.rpcg_oracle_pcg_factored.argtypes = [ctypes.c_int32, P, P, P, P, P, P, P, P, P, ctypes.c_double, P, P,
-                                               ctypes.c_double, ctypes.c_int32, P, P]
+                                               ctypes.c_double, ctypes.c_int32, P, P, P, P, P]
         L.rpcg_oracle_ir.restype = ctypes.c_int
         L.rpcg_oracle_ir.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
-                                     ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P]
+                                     ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
         _lib = L
     return _lib
 
@@ -185,18 +186,30 @@ def spmv_f32(A, x):
     return y
 
 
-def pcg_f32(A, b, x0=None, tol=1e-4, maxit=2000):
-    """Jacobi-PCG entirely in binary32. Returns dict(x, iters, hist, status)."""
+def pcg_f32(A, b, x0=None, tol=1e-4, maxit=2000, trace=False):
+    """Jacobi-PCG entirely in binary32. Returns dict(x, iters, hist, status,
+    thr[, trace_r, trace_d, trace_x])."""
     n = A.n
     b = _f32(b)
     x = np.zeros(n, dtype=np.float32) if x0 is None else _f32(x0).copy()
     hist = np.zeros(maxit + 1, dtype=np.float64)
     iters = ctypes.c_int32(0)
+    thr = ctypes.c_float(0.0)
+    tr = td = tx = None
+    if trace:
+        tr = np.zeros((maxit + 1) * n, dtype=np.float32)
+        td = np.zeros_like(tr)
+        tx = np.zeros_like(tr)
     rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f32(A.val)
     st = lib().rpcg_oracle_pcg_f32(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit),
-                                   _p(hist), ctypes.byref(iters))
+                                   _p(hist), ctypes.byref(iters), _p(tr), _p(td), _p(tx), ctypes.byref(thr))
     L = iters.value
-    return dict(x=x, iters=L, hist=hist[:L + 1].copy(), status=st)
+    out = dict(x=x, iters=L, hist=hist[:L + 1].copy(), status=st, thr=np.float32(thr.value))
+    if trace:
+        out["trace_r"] = tr.reshape(maxit + 1, n)[:L + 1]
+        out["trace_d"] = td.reshape(maxit + 1, n)[:L + 1]
+        out["trace_x"] = tx.reshape(maxit + 1, n)[:L + 1]
+    return out
 
 
 def ir_scale(rr: float) -> int:
@@ -207,35 +220,47 @@ def ir(A, b, x0=None, tol=1e-10, maxit_out=50, tol_in=1e-4, maxit_in=2000, adapt
     """Mixed-precision refinement (binary32 inner PCG on the values rounded to
     binary32, binary64 outer loop on the values as given); adaptive: the inner
     tolerance of a step is max(tol_in, 0.25 sqrt(thr / rr)).
-    Returns dict(x, outer, inner, hist (rr per outer step), status)."""
+    Returns dict(x, outer, inner, hist (rr per outer step), tin (inner
+    tolerance per correction), status)."""
     n = A.n
     b = _f64(b)
     x = np.zeros(n, dtype=np.float64) if x0 is None else _f64(x0).copy()
     hist = np.zeros(maxit_out + 1, dtype=np.float64)
+    tin = np.zeros(maxit_out + 1, dtype=np.float64)
     outer, inner = ctypes.c_int32(0), ctypes.c_int32(0)
     rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val)
     st = lib().rpcg_oracle_ir(n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit_out),
                               float(tol_in), int(maxit_in), int(bool(adaptive)), _p(hist), ctypes.byref(outer),
-                              ctypes.byref(inner))
+                              ctypes.byref(inner), _p(tin))
     k = outer.value
-    return dict(x=x, outer=k, inner=inner.value, hist=hist[:k + 1].copy(), status=st)
+    return dict(x=x, outer=k, inner=inner.value, hist=hist[:k + 1].copy(), tin=tin[:k].copy(), status=st)
 
 
-def pcg_factored(A, G, Gt, eps, b, x0=None, tol=1e-8, maxit=2000):
+def pcg_factored(A, G, Gt, eps, b, x0=None, tol=1e-8, maxit=2000, trace=False):
     """PCG with M^-1 = G G^T + eps I (G^T given explicitly as Gt).
-    Returns dict(x, iters, hist, status)."""
+    Returns dict(x, iters, hist, status[, trace_r, trace_d, trace_x])."""
     n = A.n
     b = _f64(b)
     x = np.zeros(n, dtype=np.float64) if x0 is None else _f64(x0).copy()
     hist = np.zeros(maxit + 1, dtype=np.float64)
     iters = ctypes.c_int32(0)
+    tr = td = tx = None
+    if trace:
+        tr = np.zeros((maxit + 1) * n, dtype=np.float64)
+        td = np.zeros_like(tr)
+        tx = np.zeros_like(tr)
     arrs = []
     for M in (A, G, Gt):
         arrs += [_i32(M.row_ptr), _i32(M.col_idx), _f64(M.val)]
     st = lib().rpcg_oracle_pcg_factored(n, *[_p(a) for a in arrs], float(eps), _p(b), _p(x), float(tol), int(maxit),
-                                        _p(hist), ctypes.byref(iters))
+                                        _p(hist), ctypes.byref(iters), _p(tr), _p(td), _p(tx))
     L = iters.value
-    return dict(x=x, iters=L, hist=hist[:L + 1].copy(), status=st)
+    out = dict(x=x, iters=L, hist=hist[:L + 1].copy(), status=st)
+    if trace:
+        out["trace_r"] = tr.reshape(maxit + 1, n)[:L + 1]
+        out["trace_d"] = td.reshape(maxit + 1, n)[:L + 1]
+        out["trace_x"] = tx.reshape(maxit + 1, n)[:L + 1]
+    return out
 
 
 def transpose_csr(M):

@@ -382,10 +382,14 @@ void rpcg_oracle_spmv_f32(int32_t n, const int32_t *row_ptr, const int32_t *col,
 
 /* Jacobi-PCG in binary32, the loop of rpcg_oracle_pcg with every operation
  * in binary32: thr = RN32(RN32(tol32*tol32) * <b,b>), tol32 = RN32(tol).
- * hist (optional, maxit+1) receives tau^(0..L) widened to double. */
+ * hist (optional, maxit+1) receives tau^(0..L) widened to double.
+ * trace_r, trace_d, trace_x (optional, [(maxit+1)*n] floats) receive r, d
+ * and x after each iteration as in rpcg_oracle_pcg; thr_out (optional)
+ * receives the threshold. */
 int rpcg_oracle_pcg_f32(int32_t n, const int32_t *row_ptr, const int32_t *col,
                         const float *val, const float *b, float *x,
-                        double tol, int32_t maxit, double *hist, int32_t *iters)
+                        double tol, int32_t maxit, double *hist, int32_t *iters,
+                        float *trace_r, float *trace_d, float *trace_x, float *thr_out)
 {
     *iters = 0;
     if (n < 0 || maxit < 0) return ORC_ERR_INVALID;
@@ -413,7 +417,11 @@ int rpcg_oracle_pcg_f32(int32_t n, const int32_t *row_ptr, const int32_t *col,
     float bb = rpcg_oracle_exdot_f32(n, b, b);
     float tol32 = (float)tol;
     float thr = (tol32 * tol32) * bb;
+    if (thr_out) *thr_out = thr;
     if (hist) hist[0] = tau;
+    if (trace_r) memcpy(trace_r, r, sizeof(float) * (size_t)n);
+    if (trace_d) memcpy(trace_d, d, sizeof(float) * (size_t)n);
+    if (trace_x) memcpy(trace_x, x, sizeof(float) * (size_t)n);
     if (!isfinite(tau) || !isfinite(bb)) { status = ORC_ERR_NONFINITE; goto out; }
     int32_t l = 0;
     while (tau > thr && l < maxit) {
@@ -431,6 +439,9 @@ int rpcg_oracle_pcg_f32(int32_t n, const int32_t *row_ptr, const int32_t *col,
         for (int32_t i = 0; i < n; ++i) d[i] = fmaf(gamma, d[i], z[i]);
         l += 1;
         if (hist) hist[l] = tau;
+        if (trace_r) memcpy(trace_r + (size_t)l * n, r, sizeof(float) * (size_t)n);
+        if (trace_d) memcpy(trace_d + (size_t)l * n, d, sizeof(float) * (size_t)n);
+        if (trace_x) memcpy(trace_x + (size_t)l * n, x, sizeof(float) * (size_t)n);
         if (!isfinite(tau)) { status = ORC_ERR_NONFINITE; break; }
     }
     *iters = l;
@@ -463,11 +474,13 @@ int rpcg_oracle_ir_scale(double rr)
  *     (the reduction the outer residual still needs, with a margin of 4);
  *     c = PCG32(RN32(A), RN32(r 2^-s), x0 = 0, t, maxit_in);
  *     x = RN(x + (double)c 2^s)
- *   *outer: corrections applied; *inner: total inner iterations.
+ *   *outer: corrections applied; *inner: total inner iterations;
+ *   tin_hist (optional, maxit+1): the inner tolerance t of every correction.
  * Returns the outer status (OK, WARN_MAXIT) or the first inner error. */
 int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val64,
                    const double *b, double *x, double tol, int32_t maxit_out, double tol_in,
-                   int32_t maxit_in, int32_t adaptive, double *hist, int32_t *outer, int32_t *inner)
+                   int32_t maxit_in, int32_t adaptive, double *hist, int32_t *outer, int32_t *inner,
+                   double *tin_hist)
 {
     *outer = 0; *inner = 0;
     size_t nn = (size_t)(n > 0 ? n : 1);
@@ -495,7 +508,8 @@ int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
             if (need > t) t = need;
         }
         int32_t it = 0;
-        int st = rpcg_oracle_pcg_f32(n, row_ptr, col, val32, rf, c, t, maxit_in, NULL, &it);
+        if (tin_hist) tin_hist[k] = t;
+        int st = rpcg_oracle_pcg_f32(n, row_ptr, col, val32, rf, c, t, maxit_in, NULL, &it, NULL, NULL, NULL, NULL);
         *inner += it;
         if (st < 0) { status = st; break; }
         for (int32_t i = 0; i < n; ++i) x[i] = x[i] + ldexp((double)c[i], sc);
@@ -511,7 +525,8 @@ int rpcg_oracle_ir(int32_t n, const int32_t *row_ptr, const int32_t *col, const 
  * both products are row-wise fma chains in storage order, as the SpMV of
  * Section 4.3. Only the preconditioner step S5 of Fig. 1 changes:
  *   t = G^T r,  s = G t,  z_i = fma(eps, r_i, s_i).
- * Every other step, and the exact dots, are those of rpcg_oracle_pcg. */
+ * Every other step, and the exact dots, are those of rpcg_oracle_pcg,
+ * including the optional traces of r, d and x. */
 static void factored_apply(int32_t n, const int32_t *g_rp, const int32_t *g_col, const double *g_val,
                            const int32_t *gt_rp, const int32_t *gt_col, const double *gt_val, double eps,
                            const double *r, double *t, double *z)
@@ -524,7 +539,8 @@ static void factored_apply(int32_t n, const int32_t *g_rp, const int32_t *g_col,
 int rpcg_oracle_pcg_factored(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
                              const int32_t *g_rp, const int32_t *g_col, const double *g_val,
                              const int32_t *gt_rp, const int32_t *gt_col, const double *gt_val, double eps,
-                             const double *b, double *x, double tol, int32_t maxit, double *hist, int32_t *iters)
+                             const double *b, double *x, double tol, int32_t maxit, double *hist, int32_t *iters,
+                             double *trace_r, double *trace_d, double *trace_x)
 {
     *iters = 0;
     if (n < 0 || maxit < 0) return ORC_ERR_INVALID;
@@ -545,6 +561,9 @@ int rpcg_oracle_pcg_factored(int32_t n, const int32_t *row_ptr, const int32_t *c
     double bb = rpcg_oracle_exdot(n, b, b);
     double thr = (tol * tol) * bb;
     if (hist) hist[0] = tau;
+    if (trace_r) memcpy(trace_r, r, sizeof(double) * nn);
+    if (trace_d) memcpy(trace_d, d, sizeof(double) * nn);
+    if (trace_x) memcpy(trace_x, x, sizeof(double) * nn);
     if (!isfinite(tau) || !isfinite(bb) || !isfinite(beta)) { status = ORC_ERR_NONFINITE; goto out; }
     int32_t l = 0;
     while (tau > thr && l < maxit) {
@@ -562,6 +581,9 @@ int rpcg_oracle_pcg_factored(int32_t n, const int32_t *row_ptr, const int32_t *c
         for (int32_t i = 0; i < n; ++i) d[i] = fma(gamma, d[i], z[i]);
         l += 1;
         if (hist) hist[l] = tau;
+        if (trace_r) memcpy(trace_r + (size_t)l * n, r, sizeof(double) * (size_t)n);
+        if (trace_d) memcpy(trace_d + (size_t)l * n, d, sizeof(double) * (size_t)n);
+        if (trace_x) memcpy(trace_x + (size_t)l * n, x, sizeof(double) * (size_t)n);
         if (!isfinite(tau) || !isfinite(beta)) { status = ORC_ERR_NONFINITE; break; }
     }
     *iters = l;
