@@ -27,7 +27,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc: no contraction of a*b+c, hardware fma for fma()."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-mfma", "-fPIC", "-shared",
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-mfma", "-fopenmp", "-fPIC", "-shared",
                         "-o", tmp, _SRC, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -69,8 +69,34 @@ def lib():
         L.rpcg_oracle_ir.restype = ctypes.c_int
         L.rpcg_oracle_ir.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32,
                                      ctypes.c_double, ctypes.c_int32, ctypes.c_int32, P, P, P, P]
+        L.rpcg_oracle_set_threads.restype = ctypes.c_int
+        L.rpcg_oracle_set_threads.argtypes = [ctypes.c_int32]
+        L.rpcg_oracle_get_threads.restype = ctypes.c_int
+        L.rpcg_cpu_plain_pcg.restype = ctypes.c_int
+        L.rpcg_cpu_plain_pcg.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_double, ctypes.c_int32, P]
         _lib = L
     return _lib
+
+
+def set_threads(t: int) -> int:
+    """Threads of the oracle's parallel loops (< 1: the OpenMP default); returns the count in effect."""
+    return lib().rpcg_oracle_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return lib().rpcg_oracle_get_threads()
+
+
+def cpu_plain_pcg(A, b, tol=1e-8, maxit=2000):
+    """Host comparison loop: the same iteration with ordinary (threaded) binary64
+    dots. Not a reference; returns dict(x, iters, status)."""
+    b = _f64(b)
+    x = np.zeros(A.n, dtype=np.float64)
+    iters = ctypes.c_int32(0)
+    rp, ci, va = _i32(A.row_ptr), _i32(A.col_idx), _f64(A.val)
+    st = lib().rpcg_cpu_plain_pcg(A.n, _p(rp), _p(ci), _p(va), _p(b), _p(x), float(tol), int(maxit),
+                                  ctypes.byref(iters))
+    return dict(x=x, iters=iters.value, status=st)
 
 
 def _p(a):

@@ -22,10 +22,18 @@
  *    (Section 4.3), preconditioner by the precomputed inverse diagonal times
  *    the vector (Section 4.3, preconditioner paragraph).
  *
- * Build: gcc -O2 -std=c11 -ffp-contract=off -mfma -fPIC -shared
+ * Threads (OpenMP): rows of the SpMV and of the exact residual, and the
+ * element-wise loops, are split over threads; every element is computed
+ * by the same operations whatever thread computes it. The exact dot gives
+ * each thread a contiguous range of the terms and its own accumulator, and
+ * the accumulators are added as integers, which is exact: the result does
+ * not depend on the number of threads (a test compares 1 thread with all).
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -mfma -fopenmp -fPIC -shared
  * (-ffp-contract=off: no multiply-add is fused unless fma() is written).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -125,6 +133,37 @@ static void limbs_sub(uint32_t *D, const uint32_t *A, const uint32_t *B)
     }
 }
 
+/* A += B (both magnitudes; the headroom above keeps the sum in range). */
+static void limbs_add(uint32_t *A, const uint32_t *B)
+{
+    uint64_t carry = 0;
+    for (int k = 0; k < ORC_LIMBS; ++k) {
+        uint64_t t = (uint64_t)A[k] + B[k] + carry;
+        A[k] = (uint32_t)t;
+        carry = t >> 32;
+    }
+}
+
+/* Exact sum of a[0..n) x b[0..n) products into acc: one accumulator per
+ * thread over a contiguous range, then the accumulators added exactly. */
+static void acc_add_dot(orc_acc *acc, int64_t n, const double *x, const double *y)
+{
+    #pragma omp parallel
+    {
+        orc_acc *t = (orc_acc *)malloc(sizeof(orc_acc));
+        acc_clear(t);
+        #pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) acc_add_product(t, x[i], y[i]);
+        #pragma omp critical
+        {
+            limbs_add(acc->pos, t->pos);
+            limbs_add(acc->neg, t->neg);
+            acc->nonfinite |= t->nonfinite;
+        }
+        free(t);
+    }
+}
+
 static int limbs_bit(const uint32_t *D, int k)
 {
     if (k < 0 || k >= 32 * ORC_LIMBS) return 0;
@@ -191,7 +230,7 @@ double rpcg_oracle_exdot(int64_t n, const double *x, const double *y)
 {
     orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
     acc_clear(a);
-    for (int64_t i = 0; i < n; ++i) acc_add_product(a, x[i], y[i]);
+    acc_add_dot(a, n, x, y);
     double r = acc_round(a);
     free(a);
     return r;
@@ -208,7 +247,7 @@ int rpcg_oracle_exdot_exact(int64_t n, const double *x, const double *y,
 {
     orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
     acc_clear(a);
-    for (int64_t i = 0; i < n; ++i) acc_add_product(a, x[i], y[i]);
+    acc_add_dot(a, n, x, y);
     int rc = a->nonfinite ? -1 : 0;
     int c = limbs_cmp(a->pos, a->neg);
     if (c >= 0) { limbs_sub(limbs, a->pos, a->neg); *sign = 0; }
@@ -228,6 +267,7 @@ double rpcg_oracle_round_limbs(const uint32_t *limbs, int sign)
 void rpcg_oracle_spmv(int32_t n, const int32_t *row_ptr, const int32_t *col,
                       const double *val, const double *x, double *y)
 {
+    #pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i) {
         double acc = 0.0;
         for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
@@ -242,21 +282,26 @@ void rpcg_oracle_true_residual(int32_t n, const int32_t *row_ptr, const int32_t 
                                const double *val, const double *b, const double *x,
                                double *r)
 {
-    orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
-    for (int32_t i = 0; i < n; ++i) {
-        acc_clear(a);
-        acc_add_value(a, b[i]);
-        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
-            acc_add_product(a, -val[k], x[col[k]]);
-        r[i] = acc_round(a);
+    #pragma omp parallel
+    {
+        orc_acc *a = (orc_acc *)malloc(sizeof(orc_acc));
+        #pragma omp for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            acc_clear(a);
+            acc_add_value(a, b[i]);
+            for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+                acc_add_product(a, -val[k], x[col[k]]);
+            r[i] = acc_round(a);
+        }
+        free(a);
     }
-    free(a);
 }
 
 /* Jacobi preconditioner apply (Section 4.3): z_i = RN(dinv_i * r_i), with
  * dinv_i = RN(1 / a_ii) formed once at setup. */
 static void jacobi_apply(int32_t n, const double *dinv, const double *r, double *z)
 {
+    #pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
 }
 
@@ -328,12 +373,15 @@ int rpcg_oracle_pcg(int32_t n, const int32_t *row_ptr, const int32_t *col,
         double delta = rpcg_oracle_exdot(n, d, w);              /* S2 */
         if (!(delta > 0.0)) { status = isfinite(delta) ? ORC_ERR_BREAKDOWN : ORC_ERR_NONFINITE; break; }
         double rho = beta / delta;
+        #pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) x[i] = fma(rho, d[i], x[i]);   /* S3 */
+        #pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) r[i] = fma(-rho, w[i], r[i]);  /* S4 */
         jacobi_apply(n, dinv, r, z);                            /* S5 */
         beta = rpcg_oracle_exdot(n, z, r);                      /* S6 */
         tau = rpcg_oracle_exdot(n, r, r);                       /* S8 */
         double gamma = beta / beta_old;
+        #pragma omp parallel for schedule(static)
         for (int32_t i = 0; i < n; ++i) d[i] = fma(gamma, d[i], z[i]); /* S7 */
         l += 1;
         if (hist) hist[l] = tau;
@@ -590,5 +638,81 @@ int rpcg_oracle_pcg_factored(int32_t n, const int32_t *row_ptr, const int32_t *c
     if (status == ORC_OK && tau > thr) status = ORC_WARN_MAXIT;
 out:
     free(r); free(z); free(d); free(w); free(t);
+    return status;
+}
+
+/* ---- threads ------------------------------------------------------------ */
+
+/* Threads used by the parallel loops above (OpenMP); values < 1 select the
+ * OpenMP default. Returns the number now in effect. */
+int rpcg_oracle_set_threads(int32_t t)
+{
+    if (t >= 1) omp_set_num_threads(t);
+    return omp_get_max_threads();
+}
+
+int rpcg_oracle_get_threads(void) { return omp_get_max_threads(); }
+
+/* ---- host comparison loop (not a reference) -----------------------------
+ * The iteration of rpcg_oracle_pcg with ordinary binary64 dot products: each
+ * thread sums its range of products in order, and OpenMP adds the thread
+ * sums in an unspecified order (the paper's Regular variant on a CPU). It
+ * computes nothing the tests compare against; the benchmark times it beside
+ * the exact loop to give the host's own cost of the exact dots. */
+static double plain_dot(int32_t n, const double *x, const double *y)
+{
+    double s = 0.0;
+    #pragma omp parallel for schedule(static) reduction(+:s)
+    for (int32_t i = 0; i < n; ++i) s += x[i] * y[i];
+    return s;
+}
+
+int rpcg_cpu_plain_pcg(int32_t n, const int32_t *row_ptr, const int32_t *col, const double *val,
+                       const double *b, double *x, double tol, int32_t maxit, int32_t *iters)
+{
+    *iters = 0;
+    if (n < 0 || maxit < 0) return ORC_ERR_INVALID;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *dinv = malloc(sizeof(double) * nn), *r = malloc(sizeof(double) * nn);
+    double *z = malloc(sizeof(double) * nn), *d = malloc(sizeof(double) * nn);
+    double *w = malloc(sizeof(double) * nn);
+    int status = ORC_OK;
+    for (int32_t i = 0; i < n && status == ORC_OK; ++i) {
+        double aii = 0.0; int found = 0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            if (col[k] == i) { aii = val[k]; found = 1; }
+        if (!found || !(aii > 0.0)) status = ORC_ERR_NOT_SPD;
+        else dinv[i] = 1.0 / aii;
+    }
+    if (status != ORC_OK) goto out;
+    rpcg_oracle_spmv(n, row_ptr, col, val, x, w);
+    #pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) { r[i] = b[i] - w[i]; z[i] = dinv[i] * r[i]; d[i] = z[i]; }
+    double beta = plain_dot(n, z, r), tau = plain_dot(n, r, r), bb = plain_dot(n, b, b);
+    double thr = (tol * tol) * bb;
+    int32_t l = 0;
+    while (tau > thr && l < maxit) {
+        double beta_old = beta;
+        rpcg_oracle_spmv(n, row_ptr, col, val, d, w);
+        double delta = plain_dot(n, d, w);
+        if (!(delta > 0.0)) { status = ORC_ERR_BREAKDOWN; break; }
+        double rho = beta / delta;
+        #pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            x[i] = fma(rho, d[i], x[i]);
+            r[i] = fma(-rho, w[i], r[i]);
+            z[i] = dinv[i] * r[i];
+        }
+        beta = plain_dot(n, z, r);
+        tau = plain_dot(n, r, r);
+        double gamma = beta / beta_old;
+        #pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) d[i] = fma(gamma, d[i], z[i]);
+        l += 1;
+    }
+    *iters = l;
+    if (status == ORC_OK && tau > thr) status = ORC_WARN_MAXIT;
+out:
+    free(dinv); free(r); free(z); free(d); free(w);
     return status;
 }
