@@ -49,7 +49,7 @@ def _case(kind, n, seed):
 
 
 SIZES = [0, 1, 2, 3, 63, 64, 65, 255, 1000, 4097, 65539, 1 << 20]
-KINDS = ["narrow", "wide", "cond:1e8", "cond:1e16", "cond:1e32"]
+KINDS = ["narrow", "wide", "cond:1e0", "cond:1e8", "cond:1e16", "cond:1e24", "cond:1e32"]
 
 
 @pytest.mark.parametrize("mode", ["exblas", "fpe"])
@@ -275,3 +275,54 @@ def test_async_call_without_result(R, orc):
     assert info is None
     torch.cuda.synchronize()
     assert _same(out.item(), orc.exdot(x, y))
+
+
+def _direct_edges(threads: int, seed: int):
+    """Input that sends every lane of a launch with `threads` lanes into the
+    direct path of the exact dot (wide-exponent products overflow the lane's
+    expansion on every add for 20 element pairs per lane, i.e. more than one
+    measurement window), followed, while the lanes stay direct, by the edge
+    cases of that path: subnormal operands times large ones (the ex = 0
+    branch), products of few significant bits below 2^-969 (added as two
+    doubles, exact; they raise the inexact-domain warning), and products
+    near 2^1021 that cancel (the top accumulator words)."""
+    rng = np.random.default_rng(seed)
+    px, py = exdot_wide(seed, 2 * 20 * threads)
+    m = 2 * 40 * threads
+    kind = rng.integers(0, 3, m)
+    x = np.empty(m)
+    y = np.empty(m)
+    sub = kind == 0
+    x[sub] = np.ldexp(rng.integers(1, 1 << 52, int(sub.sum())).astype(np.float64), -1074)
+    y[sub] = np.ldexp(1.0 + rng.random(int(sub.sum())), rng.integers(980, 1023, int(sub.sum())))
+    tiny = kind == 1
+    a = rng.integers(-600, -400, int(tiny.sum()))
+    b = rng.integers(-1070, -970, int(tiny.sum())) - a
+    x[tiny] = np.ldexp(rng.choice([-1.0, 1.0, 3.0, -5.0], int(tiny.sum())), a)
+    y[tiny] = np.ldexp(rng.choice([1.0, -1.0, 0.75], int(tiny.sum())), b)
+    wide = kind == 2
+    wx, wy = exdot_wide(seed + 1, int(wide.sum()))
+    x[wide], y[wide] = wx, wy
+    # two cancelling products of about 1.5 * 2^1021 (sum of magnitudes below 2^1023)
+    hx = 1.5 * 2.0 ** 511
+    x[5], y[5] = hx, 2.0 ** 510 * (1 + 2.0 ** -40)
+    x[m // 2 + 7], y[m // 2 + 7] = -hx, 2.0 ** 510
+    tx, ty = exdot_wide(seed + 2, 2 * 10 * threads)
+    return np.concatenate([px, x, tx]), np.concatenate([py, y, ty])
+
+
+@pytest.mark.parametrize("mode", ["exblas", "fpe"])
+def test_direct_path_edge_cases(R, orc, mode):
+    """The exact dot's direct path on its edge cases equals the oracle bit for
+    bit under several launch shapes (each input built for its shape so that
+    the edge cases reach lanes in direct mode)."""
+    for grid, block in ((1, 64), (2, 128), (4, 256), (3, 1024), (0, 0)):
+        threads = grid * block if grid else 1024  # default shape: sized for 1024 lanes only
+        x, y = _direct_edges(threads, 300 + grid + block)
+        want = orc.exdot(x, y)
+        print(f"exdot direct-path edges {mode} grid={grid} block={block} n={x.size}", flush=True)
+        out, info = R.exdot(_dev(x), _dev(y), mode=mode, grid_size=grid, block_size=block)
+        assert _same(out.item(), want), (mode, grid, block, out.item(), want)
+        assert info["status"] == R.WARN_FPE_INEXACT, info  # the tiny products
+        if mode == "fpe" and grid:
+            assert info["fpe_escapes"] > x.size // 4  # direct adds count as escapes

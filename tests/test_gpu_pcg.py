@@ -281,3 +281,60 @@ def test_160_cube_first_iterations_bitexact(R, orc):
     assert h[-1] <= info["threshold"] < h[-2]
     idx = np.random.default_rng(0).choice(A.n, 2000, replace=False)
     assert np.max(np.abs(x[idx] - xs[idx])) < 1e-5
+
+
+@pytest.fixture(scope="module")
+def w2(orc):
+    """The bench configuration: 27-point operator on 160^3 (n = 4,096,000,
+    nnz = 109,215,352), b = A x*, x* ~ U[-1,1) (seed 2), tol 1e-8; the
+    oracle's full solve, computed once for the module."""
+    A, b, xs = stencil_problem(160, 2)
+    print("pcg 160^3 oracle full solve", flush=True)
+    ref = orc.pcg(A, b, tol=1e-8, maxit=2000)
+    assert ref["status"] == 0
+    return A, b, xs, ref
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_160_cube_full_solve_bitexact(R, w2):
+    """Section 5.3 / Table 3: the exact variants reproduce the reference at
+    every iteration. Here: the whole bench solve (iteration count, every
+    tau of the history and every bit of x) equals the oracle in both exact
+    modes, with the default launch shapes and with grids larger than the chip
+    holds at once."""
+    A, b, xs, ref = w2
+    Ad = R.CSR.from_host(A)
+    bd = torch.from_numpy(b).cuda()
+    for mode in ("exblas", "fpe"):
+        for grid, block, sg in ((0, 0, 0), (1024, 512, 4096)):
+            print(f"pcg 160^3 full {mode} grid={grid} block={block} spmv_grid={sg}", flush=True)
+            x, info = R.pcg_solve(Ad, bd, mode=mode, grid_size=grid, block_size=block, spmv_grid_size=sg)
+            assert info["status"] == 0 and info["iterations"] == ref["iters"], (mode, grid)
+            assert _eq(info["hist"].numpy(), ref["hist"]), (mode, grid)
+            assert _eq(x.cpu().numpy(), ref["x"]), (mode, grid)
+            if mode == "fpe":
+                assert info["fpe_escapes"] == 0
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_160_cube_plain_within_tolerance(R, orc, w2):
+    """Plain fp64 at the bench configuration: converges, and at the oracle's
+    iteration count its true relative residual (exact row sums) is within
+    1e-12 of the oracle's."""
+    A, b, xs, ref = w2
+    Ad = R.CSR.from_host(A)
+    bd = torch.from_numpy(b).cuda()
+    print("pcg 160^3 plain", flush=True)
+    x, info = R.pcg_solve(Ad, bd, mode="plain")
+    assert info["status"] == 0 and abs(info["iterations"] - ref["iters"]) <= 2
+    x2, info2 = R.pcg_solve(Ad, bd, mode="plain", maxit=ref["iters"])
+    print("pcg 160^3 plain true residuals", flush=True)
+    rr_plain = orc.relres_true(A, b, x2.cpu().numpy())
+    rr_orc = orc.relres_true(A, b, ref["x"])
+    print("160^3 relres plain", rr_plain, "oracle", rr_orc, flush=True)
+    assert abs(rr_plain - rr_orc) <= 1e-12
+    h = info["hist"].numpy()
+    L = min(len(h), len(ref["hist"]))
+    assert np.max(np.abs(h[:L] / ref["hist"][:L] - 1)) < 1e-6
