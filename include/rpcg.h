@@ -155,6 +155,25 @@ void rpcg_destroy(rpcg_ctx *ctx);
 int rpcg_exdot(rpcg_ctx *ctx, rpcg_mode mode, int64_t n, const double *x, const double *y,
                double *out, const rpcg_opts *opts, rpcg_result *res, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the dot
+ * product of rpcg_exdot, same arguments, same kernels and same results,
+ * without a context. Its workgroup slots and counters live in a static
+ * device array of about 1.3 MB per GPU (allocated when the library is
+ * loaded, held until the process ends), so the call allocates nothing; it
+ * runs on the current device. It holds at most RPCG_NOALLOC_MAX_GROUPS
+ * workgroups: opts->grid_size above that gives RPCG_ERR_INVALID, and the
+ * automatic grid is capped there (n itself is unbounded). Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (on different
+ * streams or host threads) race and give undefined results; calls ordered
+ * on one stream are safe. The counters are cleared by a small kernel at the
+ * start of each call (no memset node, so the call can be captured into a
+ * graph when res is NULL). res: as rpcg_exdot (when given, the call waits
+ * for the stream, which a capturing caller must avoid). */
+#define RPCG_NOALLOC_MAX_GROUPS 2048
+int rpcg_exdot_noalloc(rpcg_mode mode, int64_t n, const double *x, const double *y, double *out,
+                       const rpcg_opts *opts, rpcg_result *res, void *stream);
+
 /* y = A x (Section 4.3 SpMV): y_i = fold over the stored entries of row i in
  * order of acc = fma(a_ik, x[col_k], acc), acc starting at +0. A: device CSR
  * (see rpcg_csr; its structure is not checked here, a malformed matrix is

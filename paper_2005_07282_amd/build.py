@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "librpcg.so")
 # (source, object suffix, extra flags): the templated solver kernels are built
 # once per value type so the compiles run in parallel
 _TYPED = ["pcg_setup.hip", "pcg_spmv_dot.hip", "pcg_update.hip"]
-SOURCES = ([("exdot.hip", "", []), ("sell.hip", "", []), ("ir.hip", "", []), ("batch_setup.hip", "", []),
+SOURCES = ([("exdot.hip", "", []), ("exdot_noalloc.hip", "", []), ("sell.hip", "", []), ("ir.hip", "", []), ("batch_setup.hip", "", []),
             ("batch_iter.hip", "", []), ("pcg_factored_setup.hip", "", []), ("pcg_factored_iter.hip", "", []), ("api.cpp", "", []),
             ("batch_api.cpp", "", []), ("lp_conv.hip", "", []),
             ("lp_factor.hip", "", []), ("lp_api.cpp", "", [])] +

@@ -105,6 +105,8 @@ def lib():
         L.rpcg_destroy.restype = None
         L.rpcg_exdot.argtypes = [P, ctypes.c_int, I64, P, P, P, ctypes.POINTER(_Opts), ctypes.POINTER(_Result), P]
         L.rpcg_exdot.restype = ctypes.c_int
+        L.rpcg_exdot_noalloc.argtypes = [ctypes.c_int, I64, P, P, P, ctypes.POINTER(_Opts), ctypes.POINTER(_Result), P]
+        L.rpcg_exdot_noalloc.restype = ctypes.c_int
         L.rpcg_fpe_size_auto.argtypes = [P, ctypes.POINTER(_Csr), P, P, P, P]
         L.rpcg_fpe_size_auto.restype = ctypes.c_int
         L.rpcg_spmv.argtypes = [P, ctypes.POINTER(_Csr), P, P, P]
@@ -167,7 +169,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot", "rpcg_fpe_size_auto",
+EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot", "rpcg_exdot_noalloc",
+            "rpcg_fpe_size_auto",
             "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_factored", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
             "rpcg_batch_create", "rpcg_batch_destroy", "rpcg_batch_get_tuning", "rpcg_batch_set_tuning",
             "rpcg_batch_tune", "rpcg_batch_solve", "rpcg_lp_pattern_nnz", "rpcg_lp_pattern", "rpcg_lp_create",
@@ -273,6 +276,26 @@ def exdot(x: torch.Tensor, y: torch.Tensor, mode: str = "exblas", out: torch.Ten
     if rc < 0:
         raise RpcgError(rc, "rpcg_exdot")
     return out, (_result_dict(r) if sync else None)
+
+
+def exdot_noalloc(x: torch.Tensor, y: torch.Tensor, out: torch.Tensor, mode: str = "exblas", sync: bool = True,
+                  **opts):
+    """<x, y> into the caller's out (one double on the GPU) through the
+    entry point that allocates nothing. Returns the info dict, or None with
+    sync=False."""
+    _check(x, torch.float64, "x")
+    _check(y, torch.float64, "y")
+    _check(out, torch.float64, "out")
+    if x.numel() != y.numel() or x.device != y.device or out.device != x.device:
+        raise ValueError("x, y and out must be on one device and x, y of one length")
+    o = _opts(**opts)
+    r = _Result()
+    with torch.cuda.device(x.device):
+        rc = lib().rpcg_exdot_noalloc(MODES[mode], x.numel(), x.data_ptr(), y.data_ptr(), out.data_ptr(),
+                                      ctypes.byref(o), ctypes.byref(r) if sync else None, _stream(x.device))
+    if rc < 0:
+        raise RpcgError(rc, "rpcg_exdot_noalloc")
+    return _result_dict(r) if sync else None
 
 
 def exdot_partial(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
