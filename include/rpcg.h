@@ -83,7 +83,10 @@ typedef struct {
     int32_t maxit;         /* default 2000 */
     int32_t fpe_size;      /* expansion length p, 1..8 (Section 4.2: tunable); 0 = auto (default):
                               4 in FPE mode, 3 in EXBLAS mode (whose result does not depend on it) */
-    int32_t early_exit;    /* stop propagating zero errors (Section 4.2); default 1 */
+    int32_t early_exit;    /* FPE mode: stop propagating zero errors (Section 4.2); default 1.
+                              Results do not depend on it. The EXBLAS lane path always runs
+                              every level (a divergent exit saves nothing on a 64-wide
+                              wavefront) */
     int32_t fpe_fallback;  /* FPE mode: what an expansion cannot hold (an escape, the
                               capacity warning of Section 4.3) is kept exactly in a long
                               accumulator, so the result stays exact (default 1); 0 drops

@@ -262,7 +262,7 @@ int rpcg_spmv(rpcg_ctx *c, const rpcg_csr *A, const double *x, double *y, void *
 {
     if (!c || !valid_csr(A) || (A->n > 0 && (!x || !y)) || (A->n > 0 && x == y)) return RPCG_ERR_INVALID;
     RPCG_TRY(hipSetDevice(c->device));
-    RPCG_TRY(launch_spmv_csr(A->n, A->row_ptr, A->col_idx, A->val, x, y, (hipStream_t)stream));
+    RPCG_TRY(launch_spmv_csr(A->n, A->row_ptr, A->col_idx, A->val, x, y, 0, (hipStream_t)stream));
     return RPCG_OK;
 }
 
@@ -434,7 +434,8 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
                     RPCG_TRY(launch_fac_update(mode, l, n, *fp, vl, (l & 1) ? v.r : r2, t, c->st, c->ws[0],
                                                cfg_sl.grid, c->ws, stride, cfg_rows));
                     if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
-                    RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws, cfg_rows.grid, stride, cfg_rows));
+                    RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws, cfg_rows.grid, stride, cfg_rows,
+                                                     false));
                     done_fac = true;
                 }
             }
@@ -442,7 +443,8 @@ static int run_pcg(rpcg_ctx *c, int mode, const SellMat<T> &M, const T *b, T *x,
                 RPCG_TRY(launch_pcg_update<T>(mode, l, n, v, c->st, c->ws[0], cfg_sl.grid, c->ws + 1, stride,
                                               cfg_rows));
                 if (ev) RPCG_TRY(hipEventRecord(ev[2], s));
-                RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws + 1, cfg_rows.grid, stride, cfg_rows));
+                RPCG_TRY(launch_pcg_direction<T>(mode, l, n, v, c->st, c->ws + 1, cfg_rows.grid, stride, cfg_rows,
+                                                 true));
             }
             if (ev) RPCG_TRY(hipEventRecord(ev[3], s));
         }

@@ -92,17 +92,73 @@ __global__ void k_acc_round(const long long *digits, double *out)
 }
 
 // ---------------------------------------------------------------------------
-// SpMV on CSR: one lane per row, sequential fma chain in storage order.
+// SpMV on CSR (Section 4.3): y_i = fold over the stored entries of row i, in
+// storage order, of acc = fma(a_ik, x[col_k], acc), acc from +0.
+//
+// A workgroup owns SPMV_R consecutive rows (one per thread); their entries
+// form one contiguous range of the CSR arrays. The range is staged through
+// LDS in chunks of SPMV_E entries: consecutive threads load consecutive
+// values and columns (coalesced, streamed once) and gather the x entries;
+// then every thread continues its own row's fma chain over the part of the
+// row inside the chunk, reading LDS. The accumulator stays in the row's
+// thread across chunks, so a row of any length is one sequential chain in
+// storage order, exactly as the definition reads.
 
-__global__ void k_spmv_csr(int n, const int *__restrict__ rp, const int *__restrict__ col,
-                           const double *__restrict__ val, const double *__restrict__ x,
-                           double *__restrict__ y)
+#ifndef RPCG_SPMV_R
+#define RPCG_SPMV_R 512
+#endif
+#ifndef RPCG_SPMV_E
+#define RPCG_SPMV_E 4096
+#endif
+constexpr int SPMV_R = RPCG_SPMV_R; // rows per workgroup (= threads)
+constexpr int SPMV_E = RPCG_SPMV_E; // chunk of entries staged at a time
+
+template <int R, int E>
+__global__ void __launch_bounds__(R)
+k_spmv_csr(int n, const int *__restrict__ rp, const int *__restrict__ col, const double *__restrict__ val,
+           const double *__restrict__ x, double *__restrict__ y)
 {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
+    constexpr int PER = E / R; // entries each thread stages per chunk
+    static_assert(E % R == 0, "chunk shape");
+    __shared__ double2 st[E]; // (a_k, x[col_k]) of the chunk's entries
+    const int t = threadIdx.x;
+    for (long long r0 = (long long)blockIdx.x * R; r0 < n; r0 += (long long)gridDim.x * R) {
+        const long long r1 = r0 + R < n ? r0 + R : n;
+        const long long i = r0 + t;
+        const long long b0 = rp[r0], b1 = rp[r1];
+        long long rs = b1, re = b1;
+        if (i < r1) { rs = rp[i]; re = rp[i + 1]; }
         double acc = 0.0;
-        for (int k = rp[i]; k < rp[i + 1]; ++k) acc = __builtin_fma(val[k], x[col[k]], acc);
-        y[i] = acc;
+        for (long long k0 = b0; k0 < b1; k0 += E) {
+            double a[PER], g[PER];
+            int c[PER];
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const long long k = k0 + j * R + t;
+                const bool in = k < b1;
+                a[j] = in ? __builtin_nontemporal_load(val + k) : 0.0;
+                c[j] = in ? __builtin_nontemporal_load(col + k) : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < PER; ++j) g[j] = x[c[j]]; // c = 0 off the range: a valid index
+            if (k0 != b0) __syncthreads(); // the previous chunk has been read
+#pragma unroll
+            for (int j = 0; j < PER; ++j) st[j * R + t] = make_double2(a[j], g[j]);
+            __syncthreads();
+            const int lo = (int)((rs > k0 ? rs : k0) - k0);
+            const int hi = (int)((re < k0 + E ? re : k0 + E) - k0);
+            int k = lo;
+            for (; k + 4 <= hi; k += 4) {
+                const double2 e0 = st[k], e1 = st[k + 1], e2 = st[k + 2], e3 = st[k + 3];
+                acc = __builtin_fma(e0.x, e0.y, acc);
+                acc = __builtin_fma(e1.x, e1.y, acc);
+                acc = __builtin_fma(e2.x, e2.y, acc);
+                acc = __builtin_fma(e3.x, e3.y, acc);
+            }
+            for (; k < hi; ++k) acc = __builtin_fma(st[k].x, st[k].y, acc);
+        }
+        if (i < r1) y[i] = acc;
+        __syncthreads(); // the next block's first chunk overwrites st
     }
 }
 
@@ -138,13 +194,15 @@ hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s)
 }
 
 hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
-                           const double *x, double *y, hipStream_t s)
+                           const double *x, double *y, int grid, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    int block = 256;
-    long long grid = ((long long)n + block - 1) / block;
-    if (grid > 65536) grid = 65536;
-    hipLaunchKernelGGL(k_spmv_csr, dim3((unsigned)grid), dim3(block), 0, s, n, row_ptr, col, val, x, y);
+    const long long blocks = ((long long)n + SPMV_R - 1) / SPMV_R;
+    long long g = grid > 0 ? grid : blocks;
+    if (g > blocks) g = blocks;
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL((k_spmv_csr<SPMV_R, SPMV_E>), dim3((unsigned)g), dim3(SPMV_R), 0, s, n, row_ptr, col, val, x,
+                       y);
     return hipGetLastError();
 }
 

@@ -58,7 +58,9 @@ struct PcgState {
     int status;    // rpcg status code
     int maxit;
     int flags;
-    int pad;
+    int ended;     // the first iteration whose x update (S3) is not owed once the solve has
+                   // ended (0 at setup, l at a breakdown in iteration l, l + 1 when the
+                   // stopping test of iteration l stops); INT_MAX while running
     long long escapes;
     long long fallbacks;
 };
@@ -124,8 +126,10 @@ hipError_t launch_exdot_partial(long long n, const double *x, const double *y, l
 hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s);
 // Exponent range (floor(log2 |v|)) of the nonzero finite entries of v, merged into *emin, *emax.
 hipError_t launch_exp_range(long long n, const double *v, int *emin, int *emax, hipStream_t s);
+// CSR SpMV; grid = workgroups of 512 rows each (0: one per row block, else a
+// grid-stride loop over the blocks).
 hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
-                           const double *x, double *y, hipStream_t s);
+                           const double *x, double *y, int grid, hipStream_t s);
 
 // CSR structural check (*bad set if malformed), slice widths rounded up to a
 // multiple of vec (off_plus1), longest row, and the range of the 16-bit column
@@ -167,9 +171,11 @@ hipError_t launch_pcg_spmv_dot(int mode, const SellMat<T> &A, const PcgVecs<T> &
 template <typename T>
 hipError_t launch_pcg_update(int mode, int l, int n, const PcgVecs<T> &v, PcgState *st, const DotWs &wsd, int Gd,
                              const DotWs *ws2, int stride, const LaunchCfg &cfg);
+// s3: also apply the iterate update of iteration l (the Jacobi solver; the
+// factored solver's update kernel applies it itself).
 template <typename T>
 hipError_t launch_pcg_direction(int mode, int l, int n, const PcgVecs<T> &v, PcgState *st, const DotWs *ws2, int G,
-                                int stride, const LaunchCfg &cfg);
+                                int stride, const LaunchCfg &cfg, bool s3);
 
 // ---- mixed-precision refinement (binary64 outer loop) ----
 

@@ -133,11 +133,11 @@ int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *
         if (rc != RPCG_OK) return rc;
         for (int m = 0; m < nu; ++m) {
             const double *uk = u[(size_t)k * nu + m];
-            RPCG_TRY(launch_spmv_csr((int)n, A[k].row_ptr, A[k].col_idx, A[k].val, uk, v, s));   // v = A u
-            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, v, y, s));                          // y = G^T v
-            RPCG_TRY(launch_spmv_csr((int)n, grp, gcol, G, y, w, s));                             // G y
+            RPCG_TRY(launch_spmv_csr((int)n, A[k].row_ptr, A[k].col_idx, A[k].val, uk, v, 0, s));   // v = A u
+            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, v, y, 0, s));                          // y = G^T v
+            RPCG_TRY(launch_spmv_csr((int)n, grp, gcol, G, y, w, 0, s));                             // G y
             RPCG_TRY(launch_lp_resid(n, eps, w, v, uk, r, s));                                    // r
-            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, r, q, s));                          // q = G^T r
+            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, r, q, 0, s));                          // q = G^T r
             RPCG_TRY(launch_exdot(MODE_EXBLAS, n, uk, uk, sc, L->ctx->ws[0], L->ctx->ws_groups, L->ctx->info, cd));
             RPCG_TRY(launch_exdot(MODE_EXBLAS, n, r, r, sc + 1, L->ctx->ws[0], L->ctx->ws_groups, L->ctx->info, cd));
             RPCG_TRY(launch_lp_dodg(L->N, scale, sc, sc + 1, (const float *)L->o.p + k * n * 4,

@@ -54,6 +54,23 @@ __host__ __device__ __forceinline__ double fpe_accumulate(double (&a)[P], double
     return x;
 }
 
+// Alg. 4 without the early exit: all P levels run, branch-free. On a 64-wide
+// wavefront a divergent exit saves nothing (the wavefront runs every level
+// as long as one lane continues) and costs the exec-mask bookkeeping of each
+// branch; the result is the same since TwoSum(a, 0) = (a, 0).
+template <int P>
+__host__ __device__ __forceinline__ double fpe_accumulate_all(double (&a)[P], double x)
+{
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        double r, s;
+        two_sum(a[i], x, r, s);
+        a[i] = r;
+        x = s;
+    }
+    return x;
+}
+
 // Alg. 3 (fpesum): a += b component by component. Returns the number of
 // components whose accumulation left a nonzero remainder.
 template <int P>

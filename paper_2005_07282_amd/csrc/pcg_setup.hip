@@ -29,6 +29,7 @@ static __global__ void k_state_init(PcgState *st, int maxit)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     PcgState z = {};
     z.maxit = maxit;
+    z.ended = 0x7FFFFFFF;
     *st = z;
 }
 
@@ -109,6 +110,7 @@ k_pcg_fin_setup(int G, PcgVecs<T> v, PcgState *st, SlotView w0, SlotView w1, Slo
             st->status = -6;
             st->done = 1;
         } else st->done = (tau <= thr || st->maxit <= 0) ? 1 : 0;
+        if (st->done) st->ended = 0;
     }
 }
 

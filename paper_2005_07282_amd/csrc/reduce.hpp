@@ -5,9 +5,11 @@
 // Reduction structure (Section 3.2 / 4.3 mapped onto one GPU): each lane
 // keeps its own accumulator (an expansion, or a plain sum); the lanes of a
 // workgroup combine into one workgroup partial written to a slot: a plain
-// sum in a fixed tree, or, in both exact modes, a long accumulator in LDS
-// that receives each wavefront's expansion after a fixed lane tree (in FPE
-// mode the escapes of that tree are counted, as in Section 4.3). The kernel that
+// sum in a fixed tree, or, in both exact modes, a long accumulator in LDS.
+// In EXBLAS mode each wavefront adds its lanes' expansions to it word by
+// word as exact integer sums; in FPE mode each wavefront's expansions are
+// first merged in a fixed lane tree whose escapes are counted (Section 4.3),
+// and the merged expansion is added exactly. The kernel that
 // needs the scalar next merges all slots in a fixed order at its start, in
 // every workgroup alike, and rounds once; the kernel boundary makes the slots
 // visible, so no device-scope fence or atomic ticket is needed inside the
@@ -161,9 +163,9 @@ struct LaneDot {
                         acc_add_lds(acc, t, flags);
                     }
                 } else {
-                    double left = fpe_accumulate<P>(a, r, ee);
+                    double left = fpe_accumulate_all<P>(a, r);
                     if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
-                    left = fpe_accumulate<P>(a, t, ee);
+                    left = fpe_accumulate_all<P>(a, t);
                     if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
                 }
                 if (++win == ADAPT_WINDOW) {
@@ -172,9 +174,9 @@ struct LaneDot {
                     win = wfl = 0;
                 }
             } else if constexpr (MODE == MODE_EXBLAS) {
-                double left = fpe_accumulate<P>(a, r, ee);
+                double left = fpe_accumulate_all<P>(a, r);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
-                left = fpe_accumulate<P>(a, t, ee);
+                left = fpe_accumulate_all<P>(a, t);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
             } else if constexpr (ADAPT) {
                 // FPE with the fallback: the same switching; what goes to the
@@ -250,6 +252,57 @@ __device__ __forceinline__ int fpe_sum_capture(double (&a)[P], const double (&b)
     return esc;
 }
 
+// Exact sum of the lanes' expansions of one wavefront added to the long
+// accumulator (EXBLAS): every lane cuts its components into the
+// accumulator's 32-bit digit chunks, the wavefront sums each word's chunks
+// over its lanes with integer shuffles (exact: at most 64 * 3 * P chunks
+// below 2^32 each), and one lane adds each word sum to the accumulator.
+// Integers add exactly in any order, so this is the same value as merging
+// the expansions and flushing the remainders; the words are independent,
+// so there is no chain of dependent TwoSums. Words outside the wavefront's
+// range of chunks hold nothing and are skipped.
+template <int P>
+__device__ __forceinline__ void wave_flush_exact(const double (&a)[P], long long *acc, int &flags)
+{
+    int k[P];
+    long long c0[P], c1[P], c2[P];
+    int lo = ACC_DIGITS, hi = -1;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        k[i] = -8; // matches no word
+        c0[i] = c1[i] = c2[i] = 0;
+        if (a[i] != 0.0) {
+            if (!is_finite_bits(a[i])) {
+                flags |= FLAG_NONFINITE;
+            } else {
+                const AccChunks c = acc_chunks(a[i]);
+                k[i] = c.k;
+                c0[i] = c.c0;
+                c1[i] = c.c1;
+                c2[i] = c.c2;
+                lo = min(lo, c.k);
+                hi = max(hi, c.k + 2);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off, 64));
+        hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    for (int w = lo; w <= hi; ++w) {
+        long long v = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int d = w - k[i];
+            v += d == 0 ? c0[i] : (d == 1 ? c1[i] : (d == 2 ? c2[i] : 0ll));
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane_id() == 0 && v != 0) atomicAdd((unsigned long long *)&acc[w], (unsigned long long)v);
+    }
+}
+
 // Merge the expansions of one wavefront into lane 0 (fixed tree order).
 template <int P>
 __device__ __forceinline__ int wave_fpe_merge(double (&a)[P], bool ee, bool capture, long long *acc, int &flags)
@@ -312,15 +365,9 @@ __device__ __forceinline__ void block_finish(LaneDot<MODE, P, ADAPT> &L, long lo
         return;
     } else {
         if constexpr (MODE == MODE_EXBLAS) {
-            // merge the lane expansions of the wavefront first (what does not
-            // fit goes into the accumulator), then one lane flushes the rest:
-            // far fewer same-address LDS atomics than a flush from every lane
-            wave_fpe_merge<P>(L.a, ee, true, acc, L.flags);
-            if (lane_id() == 0) {
-#pragma unroll
-                for (int i = 0; i < P; ++i)
-                    if (L.a[i] != 0.0) acc_add_lds(acc, L.a[i], L.flags);
-            }
+            // the lanes' expansions go into the accumulator word by word, one
+            // atomic per word and wavefront
+            wave_flush_exact<P>(L.a, acc, L.flags);
         } else {
             // each lane merges its result and error expansions, the
             // wavefront merges its lanes' expansions (fixed tree, escapes

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from rpcg_workloads import CSRHost, stencil27_csr, stencil7_varcoef_csr, uniform_pm1
+from rpcg_workloads import CSRHost, band_csr, stencil27_csr, stencil7_varcoef_csr, uniform_pm1
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -64,3 +64,53 @@ def test_spmv_rejects_aliasing_and_bad_dtype(R):
         R.spmv(Ad, x, x)
     with pytest.raises(TypeError):
         R.spmv(Ad, x.float())
+
+
+def _long_rows_csr(n, seed):
+    """Mostly short rows, with rows of 256..300 entries, rows longer than the
+    kernel's 4096-entry staging chunk (one of 9000 entries) and empty rows
+    scattered in; unsorted columns, values spread over 60 binades."""
+    rng = np.random.default_rng(seed)
+    lens = rng.integers(0, 12, n)
+    lens[rng.choice(n, 40, replace=False)] = rng.integers(256, 301, 40)
+    lens[rng.choice(n, 3, replace=False)] = [4097, 5000, 9000]
+    lens[rng.random(n) < 0.05] = 0
+    rp = np.zeros(n + 1, dtype=np.int64)
+    rp[1:] = np.cumsum(lens)
+    col = rng.integers(0, n, rp[-1]).astype(np.int32)
+    val = rng.standard_normal(rp[-1]) * np.exp2(rng.integers(-30, 30, rp[-1]))
+    return CSRHost(n, rp.astype(np.int32), col, val)
+
+
+@pytest.mark.parametrize("case", ["band100", "long_rows", "ragged_blocks", "one_long_row"])
+def test_spmv_bitexact_long_and_ragged(R, orc, case):
+    """Rows longer than 255 entries and longer than the staging chunk, a band
+    of 201 entries per row (the paper's band transform, bandL = bandU = 100),
+    and row counts that end inside a 512-row block."""
+    print(f"spmv {case}", flush=True)
+    if case == "band100":
+        A = band_csr(100_003, 100)
+    elif case == "long_rows":
+        A = _long_rows_csr(20_011, 4)
+    elif case == "ragged_blocks":
+        A = _random_csr(512 * 7 + 301, 6, maxrow=70)
+    else:
+        n = 3
+        A = CSRHost(n, np.array([0, 0, 20_000, 20_001], np.int32),
+                    np.concatenate([np.arange(20_000) % n, [2]]).astype(np.int32),
+                    np.random.default_rng(2).standard_normal(20_001))
+    x = uniform_pm1(7, A.n) * 3.3
+    want = orc.spmv(A, x)
+    y = R.spmv(R.CSR.from_host(A), torch.from_numpy(x).cuda())
+    assert np.array_equal(y.cpu().numpy().view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.slow
+def test_spmv_full_size_stencil(R, orc):
+    """The 27-point operator on 160^3 (109 M entries), every row bit-exact."""
+    A = stencil27_csr(160)
+    x = uniform_pm1(8, A.n)
+    print("spmv 160^3", flush=True)
+    want = orc.spmv(A, x)
+    y = R.spmv(R.CSR.from_host(A), torch.from_numpy(x).cuda())
+    assert np.array_equal(y.cpu().numpy().view(np.uint64), want.view(np.uint64))
