@@ -105,8 +105,7 @@ __global__ void __launch_bounds__(MAX_BLOCK) k_batch_update(BatchArgs a, SlotVie
             Lb.add(zi, ri, sh.acc[0], ee, capture);                // S6
             Lt.add(ri, ri, sh.acc[1], ee, capture);                // S8
         }
-        block_finish<MODE, P>(Lb, sh.acc[0], wb, R.slot, ee, capture, &a.st[R.sys].flags, sh);
-        block_finish<MODE, P>(Lt, sh.acc[1], wt, R.slot, ee, capture, &a.st[R.sys].flags, sh);
+        block_finish_pair<MODE, P>(Lb, sh.acc[0], wb, Lt, sh.acc[1], wt, R.slot, ee, capture, &a.st[R.sys].flags, sh);
     }
 }
 

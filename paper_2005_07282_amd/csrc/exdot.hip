@@ -108,7 +108,7 @@ __global__ void k_acc_round(const long long *digits, double *out)
 #define RPCG_SPMV_R 512
 #endif
 #ifndef RPCG_SPMV_E
-#define RPCG_SPMV_E 4096
+#define RPCG_SPMV_E 2048
 #endif
 constexpr int SPMV_R = RPCG_SPMV_R; // rows per workgroup (= threads)
 constexpr int SPMV_E = RPCG_SPMV_E; // chunk of entries staged at a time

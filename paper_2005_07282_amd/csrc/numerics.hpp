@@ -71,6 +71,23 @@ __host__ __device__ __forceinline__ double fpe_accumulate_all(double (&a)[P], do
     return x;
 }
 
+// The same, entering at level L (0 <= L < P): x is added to a[L], the
+// remainder carried through a[L+1..P). Any component may receive any value:
+// every level is error-free and what is left is returned, so the exact sum
+// of the components plus the remainders is unchanged.
+template <int P, int L>
+__host__ __device__ __forceinline__ double fpe_accumulate_from(double (&a)[P], double x)
+{
+#pragma unroll
+    for (int i = L; i < P; ++i) {
+        double r, s;
+        two_sum(a[i], x, r, s);
+        a[i] = r;
+        x = s;
+    }
+    return x;
+}
+
 // Alg. 3 (fpesum): a += b component by component. Returns the number of
 // components whose accumulation left a nonzero remainder.
 template <int P>

@@ -68,8 +68,7 @@ k_pcg_update(int l, int n, PcgVecs<T> v, PcgState *st, SlotView sd, int Gd, Slot
         Lb.add(zi, ri, sh.acc[0], ee, capture);           // S6
         Lt.add(ri, ri, sh.acc[1], ee, capture);           // S8
     }
-    block_finish<MODE, P>(Lb, sh.acc[0], wb, blockIdx.x, ee, capture, &st->flags, sh);
-    block_finish<MODE, P>(Lt, sh.acc[1], wt, blockIdx.x, ee, capture, &st->flags, sh);
+    block_finish_pair<MODE, P>(Lb, sh.acc[0], wb, Lt, sh.acc[1], wt, blockIdx.x, ee, capture, &st->flags, sh);
 }
 
 // Elements per thread whose operands K3 loads before merging the dots, so

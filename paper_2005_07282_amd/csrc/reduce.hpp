@@ -47,6 +47,7 @@ struct RedShared {
     long long red_ll[MAX_WAVES];
     double part[MAX_WAVES];
     int rng[2];
+    int rng2[2];
     int flag;
     double val[3];
 };
@@ -165,7 +166,7 @@ struct LaneDot {
                 } else {
                     double left = fpe_accumulate_all<P>(a, r);
                     if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
-                    left = fpe_accumulate_all<P>(a, t);
+                    left = fpe_accumulate_from<P, (P > 1 ? 1 : 0)>(a, t);
                     if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
                 }
                 if (++win == ADAPT_WINDOW) {
@@ -174,9 +175,11 @@ struct LaneDot {
                     win = wfl = 0;
                 }
             } else if constexpr (MODE == MODE_EXBLAS) {
+                // the TwoProd error is about 2^-53 of the product: it enters
+                // the expansion one level down
                 double left = fpe_accumulate_all<P>(a, r);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
-                left = fpe_accumulate_all<P>(a, t);
+                left = fpe_accumulate_from<P, (P > 1 ? 1 : 0)>(a, t);
                 if (left != 0.0) acc_add_lds(acc, left, flags);
             } else if constexpr (ADAPT) {
                 // FPE with the fallback: the same switching; what goes to the
@@ -303,6 +306,76 @@ __device__ __forceinline__ void wave_flush_exact(const double (&a)[P], long long
     }
 }
 
+// Lane chunks of an expansion (see wave_flush_exact); lo/hi widened to the
+// lane's word range.
+template <int P>
+struct LaneChunks {
+    int k[P];
+    long long c0[P], c1[P], c2[P];
+
+    __device__ __forceinline__ void cut(const double (&a)[P], int &lo, int &hi, int &flags)
+    {
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            k[i] = -8; // matches no word
+            c0[i] = c1[i] = c2[i] = 0;
+            if (a[i] != 0.0) {
+                if (!is_finite_bits(a[i])) {
+                    flags |= FLAG_NONFINITE;
+                } else {
+                    const AccChunks c = acc_chunks(a[i]);
+                    k[i] = c.k;
+                    c0[i] = c.c0;
+                    c1[i] = c.c1;
+                    c2[i] = c.c2;
+                    lo = min(lo, c.k);
+                    hi = max(hi, c.k + 2);
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ long long word(int w) const
+    {
+        long long v = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int d = w - k[i];
+            v += d == 0 ? c0[i] : (d == 1 ? c1[i] : (d == 2 ? c2[i] : 0ll));
+        }
+        return v;
+    }
+};
+
+// wave_flush_exact for two dots at once: one loop over the union of their
+// word ranges, the two word sums reduced side by side.
+template <int P>
+__device__ __forceinline__ void wave_flush_exact2(const double (&a0)[P], long long *acc0, int &flags0,
+                                                  const double (&a1)[P], long long *acc1, int &flags1)
+{
+    LaneChunks<P> q0, q1;
+    int lo = ACC_DIGITS, hi = -1;
+    q0.cut(a0, lo, hi, flags0);
+    q1.cut(a1, lo, hi, flags1);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        lo = min(lo, __shfl_xor(lo, off, 64));
+        hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    for (int w = lo; w <= hi; ++w) {
+        long long v0 = q0.word(w), v1 = q1.word(w);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            v0 += __shfl_xor(v0, off, 64);
+            v1 += __shfl_xor(v1, off, 64);
+        }
+        if (lane_id() == 0) {
+            if (v0 != 0) atomicAdd((unsigned long long *)&acc0[w], (unsigned long long)v0);
+            if (v1 != 0) atomicAdd((unsigned long long *)&acc1[w], (unsigned long long)v1);
+        }
+    }
+}
+
 // Merge the expansions of one wavefront into lane 0 (fixed tree order).
 template <int P>
 __device__ __forceinline__ int wave_fpe_merge(double (&a)[P], bool ee, bool capture, long long *acc, int &flags)
@@ -398,6 +471,47 @@ __device__ __forceinline__ void block_finish(LaneDot<MODE, P, ADAPT> &L, long lo
         __syncthreads();
         if (threadIdx.x == 0) { sv.ws.range[2 * g] = sh.rng[0]; sv.ws.range[2 * g + 1] = sh.rng[1]; }
         if (L.flags) atomicOr(gflags, L.flags);
+    }
+}
+
+// The partials of two dots into slot g of sv0 and sv1 (as two block_finish
+// calls; in EXBLAS mode in one pass, the wavefront word sums of both dots
+// side by side and one carry step over both accumulators).
+template <int MODE, int P, bool ADAPT>
+__device__ __forceinline__ void block_finish_pair(LaneDot<MODE, P, ADAPT> &L0, long long *acc0, const SlotView &sv0,
+                                                  LaneDot<MODE, P, ADAPT> &L1, long long *acc1, const SlotView &sv1,
+                                                  int g, bool ee, bool capture, int *gflags, RedShared &sh)
+{
+    if constexpr (MODE != MODE_EXBLAS) {
+        block_finish<MODE, P>(L0, acc0, sv0, g, ee, capture, gflags, sh);
+        block_finish<MODE, P>(L1, acc1, sv1, g, ee, capture, gflags, sh);
+    } else {
+        wave_flush_exact2<P>(L0.a, acc0, L0.flags, L1.a, acc1, L1.flags);
+        if (threadIdx.x == 0) { sh.rng[0] = ACC_DIGITS; sh.rng[1] = -1; sh.rng2[0] = ACC_DIGITS; sh.rng2[1] = -1; }
+        __syncthreads();
+        for (int q = threadIdx.x; q < 2 * ACC_DIGITS; q += blockDim.x) {
+            const bool second = q >= ACC_DIGITS;
+            const int k = second ? q - ACC_DIGITS : q;
+            const long long *acc = second ? acc1 : acc0;
+            long long v = acc[k];
+            long long cin = k ? (acc[k - 1] >> 32) : 0;
+            long long o = (k == ACC_DIGITS - 1) ? v + cin : (v & 0xFFFFFFFFll) + cin;
+            (second ? sv1 : sv0).ws.digits[(long long)k * (second ? sv1 : sv0).stride + g] = o;
+            if (o != 0) {
+                int *rng = second ? sh.rng2 : sh.rng;
+                atomicMin(&rng[0], k);
+                atomicMax(&rng[1], k);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            sv0.ws.range[2 * g] = sh.rng[0];
+            sv0.ws.range[2 * g + 1] = sh.rng[1];
+            sv1.ws.range[2 * g] = sh.rng2[0];
+            sv1.ws.range[2 * g + 1] = sh.rng2[1];
+        }
+        const int fl = L0.flags | L1.flags;
+        if (fl) atomicOr(gflags, fl);
     }
 }
 
