@@ -65,11 +65,38 @@ def k1_traffic():
     return None
 
 
+def time_spmv(rpcg, torch, Ad, n, nnz, reps=20):
+    """The exported CSR SpMV (rpcg_spmv) on the caller's CSR: median of reps
+    event-timed calls against its algorithmic bytes 12 nnz + 4 (n+1) + 8 n
+    (x read once) + 8 n (y written)."""
+    import numpy as np
+    dev = Ad.row_ptr.device
+    x = torch.ones(n, dtype=torch.float64, device=dev)
+    y = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        rpcg.spmv(Ad, x, y)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rpcg.spmv(Ad, x, y)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    tm = float(np.median(times))
+    byt = 12 * nnz + 4 * (n + 1) + 16 * n
+    gbs = byt / (tm * 1e-3) / 1e9
+    del x, y
+    return {"kernel": "k_spmv_csr (rpcg_spmv)", "ms": round(tm, 5), "bytes": byt, "GB_s": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def iteration_bytes(n, nnz):
     """Algorithmic bytes of one fused PCG iteration (three kernels): K1, then
-    K2 reading x, d, w, r, dinv and writing x, r, z (64 n), then K3 reading
-    d, z and writing d (24 n)."""
-    return k1_bytes(n, nnz) + 64 * n + 24 * n
+    K2 reading w, r, dinv and writing r, z (40 n), then K3 reading d, z, x
+    and writing d, x (40 n): 12 nnz + 4 (n+1) + 96 n."""
+    return k1_bytes(n, nnz) + 40 * n + 40 * n
 
 
 def measure_stream_read(torch, dev, nbytes=2 << 30, reps=10):
@@ -284,9 +311,12 @@ def run_stress(n, w, n_ill, w_ill, rpcg, torch, dev):
         hs[mode] = info["hist"]
         log(f"[bench]   {mode}: {runs[mode]['iterations']} it, {runs[mode]['ms_per_iteration']} ms/it")
     k1_bytes_band = 10 * nnz + 4 * (n + 1) + 16 * n  # 16-bit codes + values, row pointers, d, w (SELL-64)
+    spmv_band = time_spmv(rpcg, torch, Ad, n, nnz)
+    log(f"[bench]   rpcg_spmv on the band: {spmv_band['ms']} ms, {spmv_band['GB_s']} GB/s")
     out["band"] = {
         "workload": f"band matrix n={n}, bandL = bandU = {w} (nnz={nnz}), 2w+1 on the diagonal, -1 in the band, "
                     f"b = A 1, x0 = 0, tol 1e-8",
+        "rpcg_spmv": spmv_band,
         "fpe_size_auto": p_auto, "exponent_range": rng,
         "runs": runs,
         "exblas_over_plain": round(runs["exblas"]["ms_per_iteration"] / runs["plain"]["ms_per_iteration"], 4),
@@ -332,6 +362,163 @@ def run_stress(n, w, n_ill, w_ill, rpcg, torch, dev):
         del Ad, bd, xs
         torch.cuda.empty_cache()
     return out
+
+
+EXDOT_KINDS = ("narrow", "wide", "cond:1e0", "cond:1e8", "cond:1e16", "cond:1e24", "cond:1e32")
+EXDOT_CHUNK_LOG2 = 20
+
+
+def exdot_chunk(kind, seed, n):
+    """One chunk of an exdot input distribution (host, rpcg_workloads)."""
+    from rpcg_workloads import exdot_conditioned, exdot_narrow, exdot_wide
+    if kind == "narrow":
+        return exdot_narrow(seed, n)
+    if kind == "wide":
+        return exdot_wide(seed, n)
+    x, y, _ = exdot_conditioned(seed, n, float(kind.split(":")[1]))
+    return x, y
+
+
+def fill_exdot(kind, ne, torch, dev, seed=1000):
+    """x, y of ne elements on the device: tile k is one 2^20-element chunk of
+    the distribution (one host draw per kind), its pairs reordered by a
+    seeded permutation of its own and x scaled by 2^s_k, s_k cycling through
+    -3..3 (-1..1 for the narrow kind). The exponent range and the condition
+    number Sum|x_i y_i| / |Sum x_i y_i| of any whole number of tiles stay
+    those of the chunk (a permutation changes neither sum, the scale
+    multiplies both alike), while no two tiles hold the same values at the
+    same positions, so a lane's grid-stride walk meets no repeated pairs."""
+    c = 1 << EXDOT_CHUNK_LOG2
+    xs, ys = exdot_chunk(kind, seed, c)
+    xc = torch.from_numpy(xs).to(dev)
+    yc = torch.from_numpy(ys).to(dev)
+    X = torch.empty(ne, dtype=torch.float64, device=dev)
+    Y = torch.empty(ne, dtype=torch.float64, device=dev)
+    span = 3 if kind == "narrow" else 7
+    gen = torch.Generator(device=dev)
+    for k in range(ne // c):
+        gen.manual_seed(seed * 100003 + k)
+        perm = torch.randperm(c, generator=gen, device=dev)
+        X[k * c:(k + 1) * c].copy_(xc[perm] * 2.0 ** ((k % span) - span // 2))
+        Y[k * c:(k + 1) * c].copy_(yc[perm])
+    return X, Y
+
+
+def time_exdot(rpcg, torch, X, Y, mode, reps, warm=10):
+    """Median, min and max of reps event-timed calls (after warm calls) and the
+    counters of one synchronous call."""
+    import numpy as np
+    out = torch.empty(1, dtype=torch.float64, device=X.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(warm):
+        rpcg.exdot(X, Y, mode=mode, out=out, sync=False)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rpcg.exdot(X, Y, mode=mode, out=out, sync=False)
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    _, info = rpcg.exdot(X, Y, mode=mode, out=out)
+    return float(np.median(times)), float(min(times)), float(max(times)), info
+
+
+def run_exdot_grid(log2_max, reps, rpcg, torch, dev):
+    """Standalone exact dot over lengths 2^20..2^log2_max (every second power)
+    and the seven input distributions, in the three modes: GB/s of the 16 n
+    algorithmic bytes and the fraction of the 8 TB/s HBM peak."""
+    ne = 1 << log2_max
+    sizes = [1 << k for k in range(EXDOT_CHUNK_LOG2, log2_max + 1, 2)]
+    if sizes[-1] != ne:
+        sizes.append(ne)
+    grid = {}
+    for kind in EXDOT_KINDS:
+        log(f"[bench] exdot grid {kind}: filling 2^{log2_max}")
+        X, Y = fill_exdot(kind, ne, torch, dev)
+        grid[kind] = {}
+        for n in sizes:
+            row = {}
+            for mode in ("exblas", "fpe", "plain"):
+                tm, tmin, tmax, info = time_exdot(rpcg, torch, X[:n], Y[:n], mode, reps)
+                gbs = 16 * n / (tm * 1e-3) / 1e9
+                row[mode] = {"ms": round(tm, 5), "GB_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                             "GB_s_best": round(16 * n / (tmin * 1e-3) / 1e9, 1),
+                             "GB_s_worst": round(16 * n / (tmax * 1e-3) / 1e9, 1),
+                             "escapes": info["fpe_escapes"], "status": info["status"]}
+            grid[kind][f"2^{n.bit_length() - 1}"] = row
+            log(f"[bench]   n=2^{n.bit_length() - 1}: " +
+                ", ".join(f"{m} {row[m]['GB_s']:.0f}" for m in row) + " GB/s")
+        del X, Y
+        torch.cuda.empty_cache()
+    return {"workload": "two binary64 vectors of n elements, tiles of one 2^20-element chunk, each tile permuted "
+                        "(seeded) and scaled by a power of two "
+                        "(narrow: U[-1,1); wide: exponents uniform in [-200, 200], random signs; cond:c: wide "
+                        "pairs with cancelling mirrored pairs and a signal giving condition number about c)",
+            "reps": reps, "grid": grid}
+
+
+def cpu_model():
+    try:
+        import subprocess
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(A, b, N, iters, reps):
+    """The oracle (exact dots) on this machine's host cores on a bounded sample
+    of the same solve: at one thread, and at all threads (median of reps);
+    and the host plain loop (ordinary dots) at all threads beside it."""
+    import numpy as np
+    import oracle
+    if not os.path.exists(oracle._LIB):
+        oracle.build()
+    all_threads = oracle.set_threads(0)
+
+    def rate(fn, k):
+        t0 = time.perf_counter()
+        fn(0)
+        t1 = time.perf_counter()
+        r = fn(k)
+        t2 = time.perf_counter()
+        return r, r["iters"] / ((t2 - t1) - (t1 - t0))
+
+    exact = lambda k: oracle.pcg(A, b, tol=1e-8, maxit=k)
+    plain = lambda k: oracle.cpu_plain_pcg(A, b, tol=1e-8, maxit=k)
+    oracle.set_threads(1)
+    log(f"[bench] oracle on the host: {iters} iterations at 1 thread")
+    r1, one = rate(exact, iters)
+    oracle.set_threads(all_threads)
+    rN = exact(iters)
+    same = bool(np.array_equal(r1["x"].view(np.uint64), rN["x"].view(np.uint64))
+                and np.array_equal(r1["hist"].view(np.uint64), rN["hist"].view(np.uint64)))
+    log(f"[bench] oracle on the host: {reps} x {4 * iters} iterations at {all_threads} threads")
+    rates = sorted(rate(exact, 4 * iters)[1] for _ in range(reps))
+    log(f"[bench] host plain loop: {reps} x {8 * iters} iterations at {all_threads} threads")
+    prates = sorted(rate(plain, 8 * iters)[1] for _ in range(reps))
+    med, pmed = float(np.median(rates)), float(np.median(prates))
+    log(f"[bench]   oracle {one:.2f} it/s (1 thread), {med:.2f} it/s ({all_threads} threads); plain {pmed:.2f} it/s")
+    return {"value": round(med, 4), "unit": "iterations/s", "cores": all_threads, "kind": "oracle",
+            "sample": f"first {4 * iters} PCG iterations of the {N}^3 exact-dot solve (setup timed separately "
+                      f"and subtracted), C oracle with OpenMP, median of {reps} runs; at 1 thread the first "
+                      f"{iters}",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "oracle_1_thread": round(one, 4), "oracle_all_threads_min_max": [round(rates[0], 4), round(rates[-1], 4)],
+            "identical_bits_1_vs_all_threads": same,
+            "cpu_plain": {"value": round(pmed, 4), "unit": "iterations/s", "cores": all_threads,
+                          "sample": f"first {8 * iters} iterations, same loop with ordinary OpenMP dot sums, "
+                                    f"median of {reps} runs"},
+            "exact_over_plain": round(pmed / med, 3)}
 
 
 LP_FWD_FLOP_PER_CELL = 2 * 27 * (4 * 16 + 16 * 16 + 16 * 4)  # three convolutions, algorithmic
@@ -399,9 +586,12 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--grid", type=int, default=160, help="N of the N^3 grid")
+    ap.add_argument("--reps", type=int, default=5, help="timed loops per mode (the median is reported)")
     ap.add_argument("--exdot-log2", type=int, default=28)
     ap.add_argument("--exdot-reps", type=int, default=20)
+    ap.add_argument("--exdot-only", action="store_true", help="only the exdot grid; prints its JSON")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for cpu_baseline")
+    ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ir-grid", type=int, default=256,
                     help="N of the N^3 grid of the mixed-precision refinement section (0 = skip)")
@@ -433,7 +623,7 @@ def main():
     import torch
 
     from paper_2005_07282_amd import rpcg
-    from rpcg_workloads import (exdot_narrow, exdot_wide, stencil27_csr, stencil27_rhs_from_int52,
+    from rpcg_workloads import (stencil27_csr, stencil27_rhs_from_int52,
                                 uniform_pm1_int52)
 
     if not os.path.exists(rpcg.LIB_PATH):
@@ -450,6 +640,9 @@ def main():
         return
     if args.lp_only:
         print(json.dumps(run_learned(args.lp_eval, rpcg, torch, dev)), flush=True)
+        return
+    if args.exdot_only:
+        print(json.dumps(run_exdot_grid(args.exdot_log2, args.exdot_reps, rpcg, torch, dev)), flush=True)
         return
     if args.stress_only:
         print(json.dumps(run_stress(args.stress_n, 100, args.stress_ill_n, 200, rpcg, torch, dev)), flush=True)
@@ -483,27 +676,42 @@ def main():
         torch.cuda.synchronize()
         return x, info
 
-    res = {}
+    def median_run(runs):
+        """The run whose loop time is the median of the repetitions."""
+        order = sorted(runs, key=lambda r: r["loop_ms"])
+        return order[len(order) // 2]
+
+    res, spread = {}, {}
+    reps = max(1, args.reps)
     for mode in ("exblas", "fpe", "plain"):
         log(f"[bench] PCG {mode}: warmup {args.warmup} iterations")
         solve(mode, max(1, args.warmup))
-        log(f"[bench] PCG {mode}: timing {args.steps} iterations")
+        log(f"[bench] PCG {mode}: timing {reps} x {args.steps} iterations")
         # every mode is timed alike: HIP events around the SpMV+dot launch of
         # every K1_TIMING_STRIDE-th iteration only
-        x, info = solve(mode, args.steps, timing=K1_TIMING_STRIDE + 1)
-        if info["iterations"] != args.steps:
-            log(f"[bench] note: {mode} stopped after {info['iterations']} iterations")
-        res[mode] = info
-        log(f"[bench]   {info['iterations']} it in {info['loop_ms']:.2f} ms "
-            f"-> {info['iterations'] / info['loop_ms'] * 1e3:.1f} it/s")
+        runs = [solve(mode, args.steps, timing=K1_TIMING_STRIDE + 1)[1] for _ in range(reps)]
+        for info in runs:
+            if info["iterations"] != args.steps:
+                log(f"[bench] note: {mode} stopped after {info['iterations']} iterations")
+        res[mode] = median_run(runs)
+        its = sorted(r["iterations"] / r["loop_ms"] * 1e3 for r in runs)
+        spread[mode] = {"median": round(float(np.median(its)), 2), "min": round(its[0], 2), "max": round(its[-1], 2)}
+        log(f"[bench]   {res[mode]['iterations']} it; it/s median {spread[mode]['median']} "
+            f"(min {spread[mode]['min']}, max {spread[mode]['max']})")
     # the same iterations with no events at all (what the events cost), and
     # with every kernel bracketed (durations of the update and direction kernels)
-    _, bare = solve("exblas", args.steps, timing=0)
-    _, inst = solve("exblas", args.steps, timing=1)
+    bare_runs = [solve("exblas", args.steps, timing=0)[1] for _ in range(reps)]
+    bare = median_run(bare_runs)
+    its = sorted(r["iterations"] / r["loop_ms"] * 1e3 for r in bare_runs)
+    spread["exblas_no_events"] = {"median": round(float(np.median(its)), 2), "min": round(its[0], 2),
+                                  "max": round(its[-1], 2)}
+    inst = median_run([solve("exblas", args.steps, timing=1)[1] for _ in range(reps)])
+    # the headline: the loop with no events in it (the median of the bare
+    # repetitions); the kernel durations come from the bracketed loops
     ex = res["exblas"]
-    L = ex["iterations"]
-    ms_per_step = ex["loop_ms"] / L
-    value = L / (ex["loop_ms"] / 1e3)
+    L = bare["iterations"]
+    ms_per_step = bare["loop_ms"] / L
+    value = L / (bare["loop_ms"] / 1e3)
     k1_ms = ex["k_spmv_dot_ms"] / max(1, ex["k_launches"])
     k2_ms = inst["k_update_ms"] / max(1, inst["k_launches"])
     k3_ms = inst["k_direction_ms"] / max(1, inst["k_launches"])
@@ -514,64 +722,19 @@ def main():
     # full solve to 1e-8 (the paper's stopping rule) for the iteration count
     log("[bench] exblas full solve to tol 1e-8")
     _, full = solve("exblas", 2000)
+    spmv160 = time_spmv(rpcg, torch, Ad, n, nnz)
+    log(f"[bench] rpcg_spmv {N}^3: {spmv160['ms']} ms, {spmv160['GB_s']} GB/s")
     del Ad, bd
     torch.cuda.empty_cache()
 
-    # standalone exact dot
+    # standalone exact dot over the length x distribution grid
     ne = 1 << args.exdot_log2
-    exd = {}
-    for kind, gen in (("wide", exdot_wide), ("narrow", exdot_narrow)):
-        log(f"[bench] exdot {kind} n=2^{args.exdot_log2}: generating")
-        X = torch.empty(ne, dtype=torch.float64, device=dev)
-        Y = torch.empty(ne, dtype=torch.float64, device=dev)
-        chunk = 1 << 24
-        for c0 in range(0, ne, chunk):
-            m = min(chunk, ne - c0)
-            xs, ys = gen(1000 + c0 // chunk, m)
-            X[c0:c0 + m].copy_(torch.from_numpy(xs))
-            Y[c0:c0 + m].copy_(torch.from_numpy(ys))
-        out = torch.empty(1, dtype=torch.float64, device=dev)
-        for mode in ("exblas", "fpe", "plain"):
-            stream = torch.cuda.current_stream()
-            # about 30 ms of warm-up: the GPU idled while the host generated the data
-            for _ in range(30):
-                rpcg.exdot(X, Y, mode=mode, out=out, sync=False)
-            times = []
-            for _ in range(args.exdot_reps):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                rpcg.exdot(X, Y, mode=mode, out=out, sync=False)
-                e1.record(stream)
-                e1.synchronize()
-                times.append(e0.elapsed_time(e1))
-            _, info = rpcg.exdot(X, Y, mode=mode, out=out)
-            tm = float(np.median(times))
-            gbs = 16 * ne / (tm * 1e-3) / 1e9
-            exd[f"{kind}_{mode}"] = {"ms": round(tm, 4), "GB_s": round(gbs, 1),
-                                     "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-                                     "escapes": info["fpe_escapes"], "fallbacks": info["fallbacks"]}
-            log(f"[bench]   exdot {kind} {mode}: {tm:.3f} ms, {gbs:.0f} GB/s")
-        del X, Y
-        torch.cuda.empty_cache()
+    exgrid = run_exdot_grid(args.exdot_log2, args.exdot_reps, rpcg, torch, dev)
+    top = f"2^{args.exdot_log2}"
+    exd = {f"{kind}_{mode}": exgrid["grid"][kind][top][mode] for kind in ("wide", "narrow")
+           for mode in ("exblas", "fpe", "plain")}
 
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        if not os.path.exists(oracle._LIB):
-            oracle.build()
-        k = args.cpu_iters
-        log(f"[bench] oracle on the host: setup, then {k} iterations of the same 160^3 solve")
-        t0 = time.perf_counter()
-        oracle.pcg(A, b, tol=1e-8, maxit=0)
-        t1 = time.perf_counter()
-        r = oracle.pcg(A, b, tol=1e-8, maxit=k)
-        t2 = time.perf_counter()
-        t_loop = (t2 - t1) - (t1 - t0)
-        cpu = {"value": round(r["iters"] / t_loop, 4), "unit": "iterations/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {r['iters']} PCG iterations of the {N}^3 exact-dot solve "
-                         f"(setup timed separately and subtracted), single-threaded C oracle, "
-                         f"{os.cpu_count()} host cores visible"}
-        log(f"[bench]   oracle {cpu['value']} it/s")
+    cpu = None if args.no_cpu else run_cpu_baseline(A, b, N, args.cpu_iters, args.cpu_reps)
 
     mixed = run_mixed_precision(args.ir_grid, rpcg, torch, dev) if args.ir_grid > 0 else None
     batched = run_batched(args.batch_seed, rpcg, torch, dev) if args.batch_seed >= 0 else None
@@ -599,7 +762,9 @@ def main():
                         f"(exblas mode), b = A x*, x* ~ U[-1,1) seed 2, x0 = 0",
             "mode": "exblas",
             "iterations_to_1e-8": full["iterations"],
-            "exblas_it_s_without_kernel_events": round(bare["iterations"] / bare["loop_ms"] * 1e3, 2),
+            "timed_loops": reps,
+            "it_s_spread": spread,
+            "exblas_it_s_with_k1_events": round(ex["iterations"] / ex["loop_ms"] * 1e3, 2),
             "plain_it_s": round(1e3 / per_it["plain"], 2),
             "fpe_it_s": round(1e3 / per_it["fpe"], 2),
             "exblas_over_plain": round(per_it["exblas"] / per_it["plain"], 4),
@@ -607,8 +772,10 @@ def main():
             "iteration_GB_s": round(it_gbs, 1),
             "kernel_ms": {"spmv_dot": round(k1_ms, 5), "update_dots": round(k2_ms, 5),
                           "direction": round(k3_ms, 5)},
+            "rpcg_spmv": spmv160,
             "exdot_n": ne,
             "exdot": exd,
+            "exdot_grid": exgrid,
             "mixed_precision": mixed,
             "batched": batched,
             "learned_preconditioner": learned_pc,
