@@ -12,6 +12,7 @@ __global__ void k_batch_state_init(BatchArgs a, int maxit)
     if (sys >= a.nsys) return;
     PcgState z = {};
     z.maxit = maxit;
+    z.ended = 0x7FFFFFFF;
     a.st[sys] = z;
 }
 
@@ -109,6 +110,7 @@ k_batch_fin_setup(BatchArgs a, SlotView w0, SlotView w1, SlotView w2, double tol
         if (capture) st->fallbacks += (e0 > 0) + (e1 > 0) + (e2 > 0);
         const int f = batch_flags(st);
         st->beta = beta;
+        st->beta_par[0] = beta;
         st->tau = tau;
         st->tau0 = tau;
         st->bb = bb;
@@ -116,12 +118,16 @@ k_batch_fin_setup(BatchArgs a, SlotView w0, SlotView w1, SlotView w2, double tol
         st->thr = thr;
         if (a.hist && a.hist[sys]) a.hist[sys][0] = tau;
         st->iter = 0;
+        st->it_cur = 0;
         int done;
         if (f & FLAG_NOT_SPD) { st->status = -4; done = 1; }
         else if ((f & FLAG_NONFINITE) || !is_finite_bits(tau) || !is_finite_bits(bb)) { st->status = -6; done = 1; }
         else done = (tau <= thr || st->maxit <= 0) ? 1 : 0;
         st->done = done;
-        if (done) atomicSub(a.active, 1);
+        if (done) {
+            st->ended = 0;
+            atomicSub(a.active, 1);
+        }
     }
 }
 

@@ -61,6 +61,10 @@ struct PcgState {
     int ended;     // the first iteration whose x update (S3) is not owed once the solve has
                    // ended (0 at setup, l at a breakdown in iteration l, l + 1 when the
                    // stopping test of iteration l stops); INT_MAX while running
+    int it_cur;    // batched solves: iterations completed, as the kernels of the current
+                   // iteration see it (committed by the SpMV kernel from iter)
+    int pad2;
+    double beta_par[2]; // batched solves: beta of iteration j in beta_par[j & 1]
     long long escapes;
     long long fallbacks;
 };

@@ -123,19 +123,36 @@ __device__ __forceinline__ T sell_row(const SellMat<T> &A, long long base, int w
                 }
             }
     }
-    for (; g0 < groups; ++g0) {
-        int c[V];
-        T a[V];
-        sell_group<T, COL16>(A, p0 + 64ll * V * g0, V * g0, first, cur, c, a);
+    // the remaining groups (fewer than a batch; wavefront-uniform count) as
+    // one more batch whose loads are issued together, so a short row (a
+    // 7-point row is four groups) waits for memory once
+    const int rest = groups - g0;
+    if (rest > 0) {
+        int c[BG][V];
+        T a[BG][V];
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const bool in = V * g0 + v < len;
-            const T t = fma_t(a[v], x[c[v]], sum);
-            sum = in ? t : sum;
-            if constexpr (DIAG) {
-                if (in && c[v] == (int)i) { *aii = a[v]; *found = true; }
+        for (int u = 0; u < BG; ++u)
+            if (u < rest) sell_group<T, COL16>(A, p0 + 64ll * V * (g0 + u), V * (g0 + u), first, cur, c[u], a[u]);
+        T g[BG][V];
+#pragma unroll
+        for (int u = 0; u < BG; ++u)
+            if (u < rest) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) g[u][v] = x[c[u][v]];
             }
-        }
+#pragma unroll
+        for (int u = 0; u < BG; ++u)
+            if (u < rest) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const bool in = V * (g0 + u) + v < len;
+                    const T t = fma_t(a[u][v], g[u][v], sum);
+                    sum = in ? t : sum;
+                    if constexpr (DIAG) {
+                        if (in && c[u][v] == (int)i) { *aii = a[u][v]; *found = true; }
+                    }
+                }
+            }
     }
     return sum;
 }
