@@ -28,7 +28,7 @@ struct rpcg_lpnet {
     int step = 0;           // Adam steps taken
     static constexpr int DW_GRID = 256; // slots of the weight-gradient sums (fixed: fixed order)
     Buffer params, grad, am, av, w1, w2, w3, w2t, w3t;
-    Buffer feat, s, pre1, h1, pre2, h2, o, do64, dob, d2, d1, pw, pb;
+    Buffer feat, s, h1, h2, o, do64, dob, d2, d1, pw, pb;
     Buffer g_rp, g_col, gt_rp, gt_col, g_val, gt_val, vecs, scal;
 };
 
@@ -82,9 +82,9 @@ int lp_forward(rpcg_lpnet *L, int nb, const rpcg_csr *A, hipStream_t s)
                                     (float *)L->s.p + k * L->n, bad, s));
     const float *p = (const float *)L->params.p;
     RPCG_TRY(launch_lp_conv(4, 16, EPI_RELU, nb, L->N, (const bf16_t *)L->feat.p, (const bf16_t *)L->w1.p,
-                            p + LP_OFF_B1, nullptr, (float *)L->pre1.p, (bf16_t *)L->h1.p, s));
+                            p + LP_OFF_B1, nullptr, nullptr, (bf16_t *)L->h1.p, s));
     RPCG_TRY(launch_lp_conv(16, 16, EPI_RELU, nb, L->N, (const bf16_t *)L->h1.p, (const bf16_t *)L->w2.p,
-                            p + LP_OFF_B2, nullptr, (float *)L->pre2.p, (bf16_t *)L->h2.p, s));
+                            p + LP_OFF_B2, nullptr, nullptr, (bf16_t *)L->h2.p, s));
     RPCG_TRY(launch_lp_conv(16, 4, EPI_LINEAR, nb, L->N, (const bf16_t *)L->h2.p, (const bf16_t *)L->w3.p,
                             p + LP_OFF_B3, nullptr, (float *)L->o.p, nullptr, s));
     DotInfo inf;
@@ -157,16 +157,17 @@ int lp_backward(rpcg_lpnet *L, int nb, hipStream_t s)
 {
     const int N = L->N, G = rpcg_lpnet::DW_GRID;
     float *gr = (float *)L->grad.p, *pw = (float *)L->pw.p, *pb = (float *)L->pb.p;
-    const float *pre1 = (const float *)L->pre1.p, *pre2 = (const float *)L->pre2.p;
+    // the relu masks of layers 2 and 1 are their stored activations h2, h1
+    const bf16_t *mask2 = (const bf16_t *)L->h2.p, *mask1 = (const bf16_t *)L->h1.p;
     // layer 3
     RPCG_TRY(launch_lp_conv_dw(16, 4, nb, N, (const bf16_t *)L->h2.p, (const bf16_t *)L->dob.p, pw, pb, G, s));
     RPCG_TRY(launch_lp_reduce(G, 4, 16, pw, pb, gr + LP_OFF_W3, gr + LP_OFF_B3, s));
-    RPCG_TRY(launch_lp_conv(4, 16, EPI_MASK, nb, N, (const bf16_t *)L->dob.p, (const bf16_t *)L->w3t.p, nullptr, pre2,
+    RPCG_TRY(launch_lp_conv(4, 16, EPI_MASK, nb, N, (const bf16_t *)L->dob.p, (const bf16_t *)L->w3t.p, nullptr, mask2,
                             nullptr, (bf16_t *)L->d2.p, s));
     // layer 2
     RPCG_TRY(launch_lp_conv_dw(16, 16, nb, N, (const bf16_t *)L->h1.p, (const bf16_t *)L->d2.p, pw, pb, G, s));
     RPCG_TRY(launch_lp_reduce(G, 16, 16, pw, pb, gr + LP_OFF_W2, gr + LP_OFF_B2, s));
-    RPCG_TRY(launch_lp_conv(16, 16, EPI_MASK, nb, N, (const bf16_t *)L->d2.p, (const bf16_t *)L->w2t.p, nullptr, pre1,
+    RPCG_TRY(launch_lp_conv(16, 16, EPI_MASK, nb, N, (const bf16_t *)L->d2.p, (const bf16_t *)L->w2t.p, nullptr, mask1,
                             nullptr, (bf16_t *)L->d1.p, s));
     // layer 1
     RPCG_TRY(launch_lp_conv_dw(4, 16, nb, N, (const bf16_t *)L->feat.p, (const bf16_t *)L->d1.p, pw, pb, G, s));
@@ -187,9 +188,7 @@ int lp_create_body(rpcg_lpnet *L)
     RPCG_TRY(L->w3t.ensure(sizeof(bf16_t) * LP_TAPS * 16 * 4));
     RPCG_TRY(L->feat.ensure(sizeof(bf16_t) * 4 * cells));
     RPCG_TRY(L->s.ensure(sizeof(float) * cells));
-    RPCG_TRY(L->pre1.ensure(sizeof(float) * 16 * cells));
     RPCG_TRY(L->h1.ensure(sizeof(bf16_t) * 16 * cells));
-    RPCG_TRY(L->pre2.ensure(sizeof(float) * 16 * cells));
     RPCG_TRY(L->h2.ensure(sizeof(bf16_t) * 16 * cells));
     RPCG_TRY(L->o.ensure(sizeof(float) * 4 * cells));
     RPCG_TRY(L->do64.ensure(sizeof(double) * 4 * cells));
@@ -239,7 +238,7 @@ void rpcg_lp_destroy(rpcg_lpnet *L)
     hipSetDevice(L->ctx->device);
     hipDeviceSynchronize();
     for (Buffer *b : {&L->params, &L->grad, &L->am, &L->av, &L->w1, &L->w2, &L->w3, &L->w2t, &L->w3t, &L->feat, &L->s,
-                      &L->pre1, &L->h1, &L->pre2, &L->h2, &L->o, &L->do64, &L->dob, &L->d2, &L->d1, &L->pw, &L->pb,
+                      &L->h1, &L->h2, &L->o, &L->do64, &L->dob, &L->d2, &L->d1, &L->pw, &L->pb,
                       &L->g_rp, &L->g_col, &L->gt_rp, &L->gt_col, &L->g_val, &L->gt_val, &L->vecs, &L->scal})
         b->release();
     delete L;

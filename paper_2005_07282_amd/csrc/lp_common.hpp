@@ -40,11 +40,13 @@ enum { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2 };
 
 // ---- launchers (lp_conv.hip) ----
 // out = conv(in) with prepared weights wt [27][16][CIN] (bfloat16, output
-// channels padded to 16). EPI_RELU: pre (float32 [cell][COUT]) = acc + bias,
-// act (bfloat16) = relu(pre). EPI_LINEAR: pre = acc + bias. EPI_MASK: act =
-// acc where mask [cell][COUT] > 0, else 0 (the adjoint pass of a relu layer).
+// channels padded to 16). EPI_RELU: act (bfloat16 [cell][COUT]) =
+// relu(acc + bias), and pre (float32, when not null) = acc + bias.
+// EPI_LINEAR: pre = acc + bias. EPI_MASK: act = acc where the forward
+// activation mask (bfloat16 [cell][COUT], the relu layer's output) is
+// nonzero, else 0 (the adjoint pass of a relu layer).
 hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_t *in, const bf16_t *wt,
-                          const float *bias, const float *mask, float *pre, bf16_t *act, hipStream_t s);
+                          const float *bias, const bf16_t *mask, float *pre, bf16_t *act, hipStream_t s);
 // Partial weight and bias gradients in grid slots (three workgroups per slot, one per dz):
 // pw[g][27][16][16] (out, in), pb[g][16]; then a fixed-order sum over slots.
 hipError_t launch_lp_conv_dw(int cin, int cout, int nb, int N, const bf16_t *in, const bf16_t *dout, float *pw,

@@ -14,22 +14,159 @@ __device__ __forceinline__ void tap_offset(int t, int &dz, int &dy, int &dx)
     dx = t % 3 - 1;
 }
 
-// Implicit-GEMM convolution on 16x16x16 bfloat16 MFMA. A wavefront computes a
-// tile of 16 cells along x (rows M) by 16 output channels (columns N); K runs
-// over (tap, input channel) in chunks of 16: one tap per chunk with 16 input
-// channels, four taps per chunk with 4. Lane l supplies A[m = l%16][k = 4(l/16)
-// + j] and B[k][n = l%16] for j < 4 and receives D[4(l/16) + j][l%16].
+// Implicit-GEMM convolution on gfx950's 16x16x32 bfloat16 MFMA. A wavefront
+// computes tiles of 16 cells along x (rows M) by 16 output channels (columns
+// N); K runs over (tap, input channel) in chunks of 32: two taps of 16 input
+// channels, or eight taps of 4. Lane l supplies A[m = l%16][k = 8(l/16) + j]
+// and B[k][n = l%16] for j < 8 and receives D[4(l/16) + j][l%16] for j < 4.
 //
-// A workgroup of four wavefronts takes a block of 16 x 4 x 1 cells (one
-// y-line per wavefront) and first stages the block's inputs with their halo
-// (18 x 6 x 3 cells, zeros outside the grid) in LDS with coalesced loads;
-// the A operands are then read from LDS, so each input is fetched from
-// memory once per block instead of once per tap.
-constexpr int CONV_BX = 16, CONV_BY = 4;                       // block of output cells (x, y)
-constexpr int CONV_HX = CONV_BX + 2, CONV_HY = CONV_BY + 2, CONV_HZ = 3; // with halo
+// A workgroup of four wavefronts takes a block of 16 x 4 x 2 output cells
+// (one y-line and two z-planes per wavefront: two independent accumulator
+// chains) and first stages the block's inputs with their halo (18 x 6 x 4
+// cells, zeros outside the grid) in LDS with coalesced loads, so each input
+// is fetched from memory once per block. The weights are packed once per
+// workgroup in the B-operand order, 16 bytes per lane and chunk.
+constexpr int CONV_BX = 16, CONV_BY = 4, CONV_BZ = 2;          // block of output cells (x, y, z)
+constexpr int CONV_HX = CONV_BX + 2, CONV_HY = CONV_BY + 2, CONV_HZ = CONV_BZ + 2; // with halo
 constexpr int CONV_HCELLS = CONV_HX * CONV_HY * CONV_HZ;
 
-// The staged inputs are kept in groups of four channels: group q of cell c
+template <int CIN>
+__host__ __device__ constexpr int conv_chunks() { return CIN == 16 ? 14 : 4; }
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+// Stage the inputs of the block at (x0, y0, z0) of one system with its
+// halo: the 8 channels of group q of halo cell c at tile[(q * HC + c) * 8]
+// (CIN = 16, two groups), or the 4 channels of cell c at tile[c * 4] (CIN =
+// 4). Consecutive threads take consecutive 16- or 8-byte units along x, so
+// a wavefront reads whole runs of the input.
+template <int CIN>
+__device__ __forceinline__ void stage_block(bf16_t *tile, const bf16_t *__restrict__ inb, int N, int x0, int y0, int z0)
+{
+    constexpr int Q = CIN == 16 ? 2 : 1, HC = CONV_HCELLS;
+    for (int u = threadIdx.x; u < HC * Q; u += blockDim.x) {
+        const int q = u % Q, cell = u / Q;
+        const int xc = cell % CONV_HX, yc = (cell / CONV_HX) % CONV_HY, zc = cell / (CONV_HX * CONV_HY);
+        const int X = x0 - 1 + xc, Y = y0 - 1 + yc, Z = z0 - 1 + zc;
+        const bool in = X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N;
+        const long long src = (((long long)Z * N + Y) * N + X) * CIN;
+        if constexpr (CIN == 16) {
+            v8s v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (in) v = *(const v8s *)(inb + src + 8 * q);
+            *(v8s *)&tile[(q * HC + cell) * 8] = v;
+        } else {
+            v4s v = {0, 0, 0, 0};
+            if (in) v = *(const v4s *)(inb + src);
+            *(v4s *)&tile[cell * 4] = v;
+        }
+    }
+}
+
+// Halo cell of output cell (m, wave line, plane zo) shifted by tap t.
+__device__ __forceinline__ int halo_cell(int t, int m, int wave, int zo)
+{
+    int dz, dy, dx;
+    tap_offset(t, dz, dy, dx);
+    return ((zo + dz + 1) * CONV_HY + (wave + dy + 1)) * CONV_HX + (m + dx + 1);
+}
+
+template <int CIN, int COUT, int EPI>
+__global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const bf16_t *__restrict__ in,
+                                                          const bf16_t *__restrict__ wt, const float *__restrict__ bias,
+                                                          const bf16_t *__restrict__ mask, float *__restrict__ pre,
+                                                          bf16_t *__restrict__ act)
+{
+    constexpr int NCH = conv_chunks<CIN>();
+    // B operands: wp[((c * 4 + kb) * 16 + co) * 8 + j] = W[tap][co][ci] of k = 8 kb + j in chunk c
+    __shared__ __attribute__((aligned(16))) bf16_t wp[NCH * 4 * 16 * 8];
+    __shared__ __attribute__((aligned(16))) bf16_t tile[CONV_HCELLS * CIN];
+    for (int u = threadIdx.x; u < NCH * 4 * 16 * 8; u += blockDim.x) {
+        const int j = u & 7, co = (u >> 3) & 15, kb = (u >> 7) & 3, c = u >> 9;
+        int t, ci;
+        if (CIN == 16) { t = 2 * c + (kb >> 1); ci = 8 * (kb & 1) + j; }
+        else { t = 8 * c + 2 * kb + (j >> 2); ci = j & 3; }
+        wp[u] = t < LP_TAPS ? wt[(t * 16 + co) * CIN + ci] : (bf16_t)0;
+    }
+    const int lane = threadIdx.x & 63, kb = lane >> 4, m = lane & 15;
+    const int wave = threadIdx.x >> 6;
+    const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + CONV_BY - 1) / CONV_BY;
+    const int tiles_z = (N + CONV_BZ - 1) / CONV_BZ;
+    const long long nblocks = (long long)nb * tiles_z * tiles_y * tiles_x;
+    const long long N3 = (long long)N * N * N;
+    for (long long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) { // workgroup-uniform
+        const int tx = (int)(blk % tiles_x);
+        long long r = blk / tiles_x;
+        const int ty = (int)(r % tiles_y);
+        r /= tiles_y;
+        const int tz = (int)(r % tiles_z);
+        const long long b = r / tiles_z;
+        const int x0 = tx * CONV_BX, y0 = ty * CONV_BY, z0 = tz * CONV_BZ;
+        __syncthreads(); // the previous block's readers are done (and the weights are in place)
+        stage_block<CIN>(tile, in + b * N3 * CIN, N, x0, y0, z0);
+        __syncthreads();
+        const int y = y0 + wave;
+        if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
+        v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int c = 0; c < NCH; ++c) {
+            const v8bf bw = __builtin_bit_cast(v8bf, *(const v8s *)&wp[((c * 4 + kb) * 16 + m) * 8]);
+            v8s a0 = {0, 0, 0, 0, 0, 0, 0, 0}, a1 = a0;
+            if constexpr (CIN == 16) {
+                const int t = 2 * c + (kb >> 1);
+                if (t < LP_TAPS) { // rows m past the grid's edge read valid LDS cells; their outputs are not stored
+                    a0 = *(const v8s *)&tile[((kb & 1) * CONV_HCELLS + halo_cell(t, m, wave, 0)) * 8];
+                    a1 = *(const v8s *)&tile[((kb & 1) * CONV_HCELLS + halo_cell(t, m, wave, 1)) * 8];
+                }
+            } else {
+                const int t = 8 * c + 2 * kb;
+                if (t < LP_TAPS) {
+                    const v4s p0 = *(const v4s *)&tile[halo_cell(t, m, wave, 0) * 4];
+                    const v4s p1 = *(const v4s *)&tile[halo_cell(t, m, wave, 1) * 4];
+                    a0[0] = p0[0]; a0[1] = p0[1]; a0[2] = p0[2]; a0[3] = p0[3];
+                    a1[0] = p1[0]; a1[1] = p1[1]; a1[2] = p1[2]; a1[3] = p1[3];
+                }
+                if (t + 1 < LP_TAPS) {
+                    const v4s p0 = *(const v4s *)&tile[halo_cell(t + 1, m, wave, 0) * 4];
+                    const v4s p1 = *(const v4s *)&tile[halo_cell(t + 1, m, wave, 1) * 4];
+                    a0[4] = p0[0]; a0[5] = p0[1]; a0[6] = p0[2]; a0[7] = p0[3];
+                    a1[4] = p1[0]; a1[5] = p1[1]; a1[6] = p1[2]; a1[7] = p1[3];
+                }
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a0), bw, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a1), bw, acc1, 0, 0, 0);
+        }
+        const int co = m;
+        if (co < COUT) {
+#pragma unroll
+            for (int zo = 0; zo < CONV_BZ; ++zo) {
+                const int z = z0 + zo;
+                if (z >= N) continue;
+                const v4f acc = zo ? acc1 : acc0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int x = x0 + 4 * kb + j;
+                    if (x >= N) continue;
+                    const long long cell = b * N3 + ((long long)z * N + y) * N + x;
+                    const float v = acc[j];
+                    if (EPI == EPI_RELU) {
+                        const float p = v + bias[co];
+                        if (pre) pre[cell * COUT + co] = p;
+                        act[cell * COUT + co] = f32_to_bf16(p > 0.f ? p : 0.f);
+                    } else if (EPI == EPI_LINEAR) {
+                        pre[cell * COUT + co] = v + bias[co];
+                    } else {
+                        // the relu of the forward layer was active where its stored
+                        // (bfloat16) activation is nonzero
+                        act[cell * COUT + co] = f32_to_bf16(mask[cell * COUT + co] != 0 ? v : 0.f);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Weight gradients: the staged inputs are kept in groups of four channels: group q of cell c
 // is the 8 bytes at tile[(q * P + c) * 4], with a pitch P = 1 (mod 16) cells
 // so that the four groups of one cell fall in different LDS banks.
 __host__ __device__ constexpr int halo_pitch(int cells) { return cells + (17 - cells % 16) % 16; }
@@ -54,81 +191,6 @@ __device__ __forceinline__ void stage_halo(bf16_t *tile, const bf16_t *__restric
         if (X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N)
             v = *(const v4s *)(inb + (((long long)Z * N + Y) * N + X) * CIN + 4 * q);
         *(v4s *)&tile[(q * P + cell) * 4] = v;
-    }
-}
-
-template <int CIN, int COUT, int EPI>
-__global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const bf16_t *__restrict__ in,
-                                                          const bf16_t *__restrict__ wt, const float *__restrict__ bias,
-                                                          const float *__restrict__ mask, float *__restrict__ pre,
-                                                          bf16_t *__restrict__ act)
-{
-    constexpr int TPC = 16 / CIN;                       // taps per chunk
-    constexpr int NCH = (LP_TAPS + TPC - 1) / TPC;      // chunks
-    constexpr int UPC = CIN / 4, P = halo_pitch(CONV_HCELLS);
-    // weights by channel group: w[((t * UPC + q) * 16 + co) * 4 + j] = W[t][co][4q + j]
-    __shared__ __attribute__((aligned(16))) bf16_t w[NCH * TPC * UPC * 16 * 4];
-    __shared__ __attribute__((aligned(16))) bf16_t tile[UPC * P * 4];
-    for (int u = threadIdx.x; u < NCH * TPC * UPC * 16; u += blockDim.x) {
-        const int co = u & 15, q = (u >> 4) % UPC, t = u / (16 * UPC);
-        v4s v = {0, 0, 0, 0};
-        if (t < LP_TAPS) v = *(const v4s *)(wt + (t * 16 + co) * CIN + 4 * q);
-        *(v4s *)&w[u * 4] = v;
-    }
-    const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
-    const int wave = threadIdx.x >> 6;
-    const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + CONV_BY - 1) / CONV_BY;
-    const long long nblocks = (long long)nb * N * tiles_y * tiles_x;
-    const long long N3 = (long long)N * N * N;
-    for (long long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) { // workgroup-uniform
-        const int tx = (int)(blk % tiles_x);
-        long long r = blk / tiles_x;
-        const int ty = (int)(r % tiles_y);
-        r /= tiles_y;
-        const int z = (int)(r % N);
-        const long long b = r / N;
-        const int x0 = tx * CONV_BX, y0 = ty * CONV_BY;
-        const bf16_t *inb = in + b * N3 * CIN;
-        __syncthreads(); // the previous block's readers are done (and the weights are in place)
-        stage_halo<CIN, CONV_BY, CONV_HZ>(tile, inb, N, x0, y0, z - 1);
-        __syncthreads();
-        const int y = y0 + wave;
-        if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
-        v4f acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 3
-        for (int c = 0; c < NCH; ++c) {
-            const int t = c * TPC + (CIN == 16 ? 0 : g);
-            const int q = CIN == 16 ? g : 0; // channel group
-            v4s a = {0, 0, 0, 0};
-            if (t < LP_TAPS) {
-                int dz, dy, dx;
-                tap_offset(t, dz, dy, dx);
-                // rows m past the grid's edge read valid LDS cells; their outputs are not stored
-                const int hc = ((dz + 1) * CONV_HY + (wave + dy + 1)) * CONV_HX + (m + dx + 1);
-                a = *(const v4s *)&tile[(q * P + hc) * 4];
-            }
-            const v4s bw = *(const v4s *)&w[((t * UPC + q) * 16 + m) * 4];
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw, acc, 0, 0, 0);
-        }
-        const int co = m;
-        if (co < COUT) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int x = x0 + 4 * g + j;
-                if (x >= N) continue;
-                const long long cell = b * N3 + ((long long)z * N + y) * N + x;
-                const float v = acc[j];
-                if (EPI == EPI_RELU) {
-                    const float p = v + bias[co];
-                    pre[cell * COUT + co] = p;
-                    act[cell * COUT + co] = f32_to_bf16(p > 0.f ? p : 0.f);
-                } else if (EPI == EPI_LINEAR) {
-                    pre[cell * COUT + co] = v + bias[co];
-                } else {
-                    act[cell * COUT + co] = f32_to_bf16(mask[cell * COUT + co] > 0.f ? v : 0.f);
-                }
-            }
-        }
     }
 }
 
@@ -294,9 +356,10 @@ __global__ void k_lp_adam(int n, float *__restrict__ p, const float *__restrict_
 }
 
 hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_t *in, const bf16_t *wt,
-                          const float *bias, const float *mask, float *pre, bf16_t *act, hipStream_t s)
+                          const float *bias, const bf16_t *mask, float *pre, bf16_t *act, hipStream_t s)
 {
-    const long long blocks = (long long)nb * N * ((N + CONV_BY - 1) / CONV_BY) * ((N + CONV_BX - 1) / CONV_BX);
+    const long long blocks = (long long)nb * ((N + CONV_BZ - 1) / CONV_BZ) * ((N + CONV_BY - 1) / CONV_BY) *
+                             ((N + CONV_BX - 1) / CONV_BX);
     const int grid = (int)std::min<long long>(blocks, 8192);
     const int block = 64 * CONV_BY;
     if (grid <= 0) return hipSuccess;
