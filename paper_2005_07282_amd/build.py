@@ -24,7 +24,7 @@ _TYPED = ["pcg_setup.hip", "pcg_spmv_dot.hip", "pcg_update.hip"]
 SOURCES = ([("exdot.hip", "", []), ("exdot_noalloc.hip", "", []), ("sell.hip", "", []), ("ir.hip", "", []), ("batch_setup.hip", "", []),
             ("batch_iter.hip", "", []), ("pcg_factored_setup.hip", "", []), ("pcg_factored_iter.hip", "", []), ("api.cpp", "", []),
             ("batch_api.cpp", "", []), ("lp_conv.hip", "", []),
-            ("lp_factor.hip", "", []), ("lp_api.cpp", "", [])] +
+            ("lp_factor.hip", "", []), ("lp_loss.hip", "", []), ("lp_api.cpp", "", [])] +
            [(f, "." + t, [f"-DRPCG_VALUE_TYPE={t}"]) for f in _TYPED for t in ("double", "float")])
 ARCH = os.environ.get("RPCG_OFFLOAD_ARCH", "gfx950")
 

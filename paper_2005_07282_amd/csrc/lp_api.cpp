@@ -29,7 +29,13 @@ struct rpcg_lpnet {
     static constexpr int DW_GRID = 256; // slots of the weight-gradient sums (fixed: fixed order)
     Buffer params, grad, am, av, w1, w2, w3, w2t, w3t;
     Buffer feat, s, h1, h2, o, do64, dob, d2, d1, pw, pb;
-    Buffer g_rp, g_col, gt_rp, gt_col, g_val, gt_val, vecs, scal;
+    Buffer g_rp, g_col, gt_rp, gt_col, g_val, gt_val, scal;
+    // loss over (instance, probe) pairs: v, y, r, q per pair, the exact-dot
+    // slots and results, and the matrix / probe pointer table
+    Buffer lvec, lws, dots, tab;
+    int lws_slots = 0;
+    DotWs wu{}, wr{};
+    std::vector<unsigned char> tab_host;
 };
 
 namespace {
@@ -98,55 +104,78 @@ int lp_forward(rpcg_lpnet *L, int nb, const rpcg_csr *A, hipStream_t s)
 // G, G^T values of instance k into g_val / gt_val.
 int lp_factor_one(rpcg_lpnet *L, int k, double *g_val, double *gt_val, hipStream_t s)
 {
-    RPCG_TRY(launch_lp_factor(L->N, (const float *)L->o.p + k * L->n * 4, (const float *)L->s.p + k * L->n,
-                              (const int *)L->g_rp.p, (const int *)L->gt_rp.p, g_val, gt_val, s));
+    RPCG_TRY(launch_lp_factor(L->N, 1, (const float *)L->o.p + k * L->n * 4, (const float *)L->s.p + k * L->n,
+                              (const int *)L->g_rp.p, (const int *)L->gt_rp.p, g_val, gt_val, 0, s));
     return RPCG_OK;
 }
 
-// Loss and dL/do (binary64, into do64) over the cached forward pass.
+// Two exact-dot workspaces of `slots` slots each.
+int lp_ensure_dot_ws(rpcg_lpnet *L, int slots)
+{
+    if (slots <= L->lws_slots) return RPCG_OK;
+    const size_t per = (size_t)slots * (ACC_WORDS * sizeof(long long) + MAX_FPE * sizeof(double) +
+                                        2 * sizeof(int) + sizeof(int));
+    RPCG_TRY(L->lws.ensure(2 * per));
+    char *base = (char *)L->lws.p;
+    for (DotWs *w : {&L->wu, &L->wr}) {
+        char *b = base;
+        w->digits = (long long *)b;
+        b += (size_t)slots * ACC_WORDS * sizeof(long long);
+        w->part = (double *)b;
+        b += (size_t)slots * MAX_FPE * sizeof(double);
+        w->range = (int *)b;
+        b += (size_t)slots * 2 * sizeof(int);
+        w->esc = (int *)b;
+        base += per;
+    }
+    L->lws_slots = slots;
+    return RPCG_OK;
+}
+
+// Loss and dL/do (binary64 into do64, bfloat16 into dob) over the cached
+// forward pass, for the nb x nu (instance, probe) pairs at once.
 int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *u, int nu, double eps, double *loss,
                  hipStream_t s)
 {
     const long long n = L->n;
-    double *V = (double *)L->vecs.p;
-    double *v = V, *y = V + n, *w = V + 2 * n, *r = V + 3 * n, *q = V + 4 * n;
+    const long long P = (long long)nb * nu;
+    if (P * LP_DOT_CHUNKS > (1ll << 30)) return RPCG_ERR_INVALID;
+    RPCG_TRY(L->lvec.ensure(sizeof(double) * 4 * n * P));
+    RPCG_TRY(L->dots.ensure(sizeof(double) * 2 * P));
+    int rc = lp_ensure_dot_ws(L, (int)(P * LP_DOT_CHUNKS));
+    if (rc != RPCG_OK) return rc;
+    // pointer table: A, G, G^T of each instance, then the probe of each pair
+    const size_t mat_bytes = sizeof(LpMat) * 3 * nb, tab_bytes = mat_bytes + sizeof(double *) * P;
+    RPCG_TRY(L->tab.ensure(tab_bytes));
+    L->tab_host.resize(tab_bytes);
+    LpMat *hm = (LpMat *)L->tab_host.data();
+    const double **hu = (const double **)(L->tab_host.data() + mat_bytes);
     double *G = (double *)L->g_val.p, *Gt = (double *)L->gt_val.p;
-    double *sc = (double *)L->scal.p; // uu, rr, loss
-    RPCG_TRY(hipMemsetAsync(L->do64.p, 0, sizeof(double) * 4 * n * nb, s));
-    RPCG_TRY(hipMemsetAsync(sc + 2, 0, sizeof(double), s));
-    rpcg_opts o;
-    rpcg_opts_default(&o);
-    o.fpe_size = 3;
-    LaunchCfg cd{};
-    cd.grid = (int)std::min<long long>(std::max<long long>((n + 2047) / 2048, 1), 8ll * L->ctx->num_cus);
-    cd.block = 256;
-    cd.early_exit = true;
-    cd.fpe_size = 3;
-    cd.fallback = true;
-    cd.xcd_parts = 1;
-    cd.stream = s;
     const int *grp = (const int *)L->g_rp.p, *gcol = (const int *)L->g_col.p;
     const int *gtrp = (const int *)L->gt_rp.p, *gtcol = (const int *)L->gt_col.p;
-    const double scale = 1.0 / ((double)nu * nb);
     for (int k = 0; k < nb; ++k) {
-        int rc = lp_factor_one(L, k, G, Gt, s);
-        if (rc != RPCG_OK) return rc;
-        for (int m = 0; m < nu; ++m) {
-            const double *uk = u[(size_t)k * nu + m];
-            RPCG_TRY(launch_spmv_csr((int)n, A[k].row_ptr, A[k].col_idx, A[k].val, uk, v, 0, s));   // v = A u
-            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, v, y, 0, s));                          // y = G^T v
-            RPCG_TRY(launch_spmv_csr((int)n, grp, gcol, G, y, w, 0, s));                             // G y
-            RPCG_TRY(launch_lp_resid(n, eps, w, v, uk, r, s));                                    // r
-            RPCG_TRY(launch_spmv_csr((int)n, gtrp, gtcol, Gt, r, q, 0, s));                          // q = G^T r
-            RPCG_TRY(launch_exdot(MODE_EXBLAS, n, uk, uk, sc, L->ctx->ws[0], L->ctx->ws_groups, L->ctx->info, cd));
-            RPCG_TRY(launch_exdot(MODE_EXBLAS, n, r, r, sc + 1, L->ctx->ws[0], L->ctx->ws_groups, L->ctx->info, cd));
-            RPCG_TRY(launch_lp_dodg(L->N, scale, sc, sc + 1, (const float *)L->o.p + k * n * 4,
-                                    (const float *)L->s.p + k * n, grp, G, r, y, v, q, (double *)L->do64.p + k * n * 4,
-                                    sc + 2, s));
-        }
+        hm[k] = LpMat{A[k].row_ptr, A[k].col_idx, A[k].val};
+        hm[nb + k] = LpMat{grp, gcol, G + (long long)k * L->gnnz};
+        hm[2 * nb + k] = LpMat{gtrp, gtcol, Gt + (long long)k * L->gnnz};
     }
+    for (long long p = 0; p < P; ++p) hu[p] = u[p];
+    RPCG_TRY(hipMemcpyAsync(L->tab.p, L->tab_host.data(), tab_bytes, hipMemcpyHostToDevice, s));
+    const LpMat *mA = (const LpMat *)L->tab.p, *mG = mA + nb, *mGt = mA + 2 * nb;
+    const double *const *ut = (const double *const *)((const char *)L->tab.p + mat_bytes);
+    double *v = (double *)L->lvec.p, *y = v + P * n, *r = y + P * n, *q = r + P * n;
+    int *flags = &L->ctx->info->flags;
+    const double scale = 1.0 / (double)P;
+    RPCG_TRY(launch_lp_factor(L->N, nb, (const float *)L->o.p, (const float *)L->s.p, grp, gtrp, G, Gt, L->gnnz, s));
+    RPCG_TRY(launch_lp_mv(n, nb, nu, mA, ut, nullptr, v, s));                                      // v = A u
+    RPCG_TRY(launch_lp_mv(n, nb, nu, mGt, nullptr, v, y, s));                                      // y = G^T v
+    RPCG_TRY(launch_lp_resid_dots(n, nb, nu, eps, mG, ut, y, v, r, L->wu, L->wr, L->lws_slots, flags, s)); // r
+    RPCG_TRY(launch_lp_dots_merge((int)P, L->wu, L->wr, L->lws_slots, (double *)L->dots.p, flags, s));
+    RPCG_TRY(launch_lp_mv(n, nb, nu, mGt, nullptr, r, q, s));                                      // q = G^T r
+    RPCG_TRY(launch_lp_dodg_all(L->N, nb, nu, scale, (const double *)L->dots.p, (const float *)L->o.p,
+                                (const float *)L->s.p, mG, r, y, v, q, (double *)L->do64.p, (bf16_t *)L->dob.p,
+                                (double *)L->scal.p + 2, s));
     if (loss) {
-        RPCG_TRY(hipMemcpyAsync(loss, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        RPCG_TRY(hipMemcpyAsync(loss, (double *)L->scal.p + 2, sizeof(double), hipMemcpyDeviceToHost, s));
         RPCG_TRY(hipStreamSynchronize(s));
     }
     return RPCG_OK;
@@ -201,9 +230,8 @@ int lp_create_body(rpcg_lpnet *L)
     RPCG_TRY(L->gt_rp.ensure(sizeof(int) * (L->n + 1)));
     RPCG_TRY(L->g_col.ensure(sizeof(int) * nz));
     RPCG_TRY(L->gt_col.ensure(sizeof(int) * nz));
-    RPCG_TRY(L->g_val.ensure(sizeof(double) * nz));
-    RPCG_TRY(L->gt_val.ensure(sizeof(double) * nz));
-    RPCG_TRY(L->vecs.ensure(sizeof(double) * 5 * L->n));
+    RPCG_TRY(L->g_val.ensure(sizeof(double) * nz * L->max_batch));
+    RPCG_TRY(L->gt_val.ensure(sizeof(double) * nz * L->max_batch));
     RPCG_TRY(L->scal.ensure(sizeof(double) * 8));
     std::vector<int32_t> grp(L->n + 1), gcol(nz), gtrp(L->n + 1), gtcol(nz);
     lp_pattern_host(L->N, grp.data(), gcol.data(), gtrp.data(), gtcol.data());
@@ -239,7 +267,8 @@ void rpcg_lp_destroy(rpcg_lpnet *L)
     hipDeviceSynchronize();
     for (Buffer *b : {&L->params, &L->grad, &L->am, &L->av, &L->w1, &L->w2, &L->w3, &L->w2t, &L->w3t, &L->feat, &L->s,
                       &L->h1, &L->h2, &L->o, &L->do64, &L->dob, &L->d2, &L->d1, &L->pw, &L->pb,
-                      &L->g_rp, &L->g_col, &L->gt_rp, &L->gt_col, &L->g_val, &L->gt_val, &L->vecs, &L->scal})
+                      &L->g_rp, &L->g_col, &L->gt_rp, &L->gt_col, &L->g_val, &L->gt_val, &L->scal, &L->lvec,
+                      &L->lws, &L->dots, &L->tab})
         b->release();
     delete L;
 }
@@ -363,7 +392,6 @@ int rpcg_lp_train_step(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const doubl
     if (rc != RPCG_OK) return rc;
     rc = lp_loss_grad(L, nb, A, u, nu, eps, nullptr, s);
     if (rc != RPCG_OK) return rc;
-    RPCG_TRY(launch_lp_to_bf16(4 * L->n * nb, (const double *)L->do64.p, (bf16_t *)L->dob.p, s));
     rc = lp_backward(L, nb, s);
     if (rc != RPCG_OK) return rc;
     L->step += 1;

@@ -1,6 +1,5 @@
-// Learned preconditioner: per-cell input features from the matrix, the factor
-// G (and G^T) from the network outputs, and the training loss's gradient with
-// respect to the outputs.
+// Learned preconditioner: per-cell input features from the matrix and the
+// factor G (and G^T) from the network outputs.
 //
 // G sits on the lower-triangle pattern of a 7-point operator on an N^3 grid:
 // row i holds the -z, -y, -x neighbours and the diagonal (ascending columns);
@@ -43,12 +42,18 @@ __global__ void k_lp_features(int N, const int *__restrict__ rp, const int *__re
     }
 }
 
-// G and G^T values at the positions of the structure (lp_pattern).
+// G and G^T values at the positions of the structure (lp_pattern); instance
+// k = blockIdx.y reads o, s and writes g_val, gt_val at k times their strides.
 __global__ void k_lp_factor(int N, const float *__restrict__ o, const float *__restrict__ s,
                             const int *__restrict__ g_rp, const int *__restrict__ gt_rp, double *__restrict__ g_val,
-                            double *__restrict__ gt_val)
+                            double *__restrict__ gt_val, long long val_stride)
 {
     const long long n = (long long)N * N * N, NN = (long long)N * N;
+    const int k = blockIdx.y;
+    o += (long long)k * n * 4;
+    s += (long long)k * n;
+    g_val += (long long)k * val_stride;
+    gt_val += (long long)k * val_stride;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / NN);
         const float si = s[i];
@@ -64,40 +69,6 @@ __global__ void k_lp_factor(int N, const float *__restrict__ o, const float *__r
         if (x < N - 1) gt_val[q++] = (double)(s[i + 1] * o[(i + 1) * 4 + 1]);
         if (y < N - 1) gt_val[q++] = (double)(s[i + N] * o[(i + N) * 4 + 2]);
         if (z < N - 1) gt_val[q] = (double)(s[i + NN] * o[(i + NN) * 4 + 3]);
-    }
-}
-
-// r = (G y + eps v) - u
-__global__ void k_lp_resid(long long n, double eps, const double *__restrict__ w, const double *__restrict__ v,
-                           const double *__restrict__ u, double *__restrict__ r)
-{
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
-        r[i] = (w[i] + eps * v[i]) - u[i];
-}
-
-// do += c (r_i y_j + v_i q_j) dG/do on the pattern, c = scale * 2 / <u,u>;
-// loss += scale * <r,r> / <u,u> (thread 0).
-__global__ void k_lp_dodg(int N, double scale, const double *__restrict__ uu, const double *__restrict__ rr,
-                          const float *__restrict__ o, const float *__restrict__ s, const int *__restrict__ g_rp,
-                          const double *__restrict__ g_val, const double *__restrict__ r, const double *__restrict__ y,
-                          const double *__restrict__ v, const double *__restrict__ q, double *__restrict__ do64,
-                          double *loss)
-{
-    const long long n = (long long)N * N * N, NN = (long long)N * N;
-    const double c = scale * 2.0 / uu[0];
-    if (blockIdx.x == 0 && threadIdx.x == 0) loss[0] += scale * rr[0] / uu[0];
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-        const int x = (int)(i % N), yy = (int)((i / N) % N), z = (int)(i / NN);
-        const double si = s[i];
-        const double gdiag = g_val[g_rp[i + 1] - 1];
-        const double d0 = c * (r[i] * y[i] + v[i] * q[i]);
-        if (fabsf(o[i * 4]) < LP_OCLAMP) do64[i * 4] += d0 * gdiag;
-        const long long nbr[3] = {x > 0 ? i - 1 : -1, yy > 0 ? i - N : -1, z > 0 ? i - NN : -1};
-        for (int k = 0; k < 3; ++k) {
-            const long long j = nbr[k];
-            if (j < 0) continue;
-            do64[i * 4 + 1 + k] += c * (r[i] * y[j] + v[i] * q[j]) * si;
-        }
     }
 }
 
@@ -117,27 +88,11 @@ hipError_t launch_lp_features(int N, const int *rp, const int *col, const double
     return hipGetLastError();
 }
 
-hipError_t launch_lp_factor(int N, const float *o, const float *s, const int *g_rp, const int *gt_rp, double *g_val,
-                            double *gt_val, hipStream_t st)
+hipError_t launch_lp_factor(int N, int nb, const float *o, const float *s, const int *g_rp, const int *gt_rp,
+                            double *g_val, double *gt_val, long long val_stride, hipStream_t st)
 {
     const long long n = (long long)N * N * N;
-    k_lp_factor<<<lp_grid(n), 256, 0, st>>>(N, o, s, g_rp, gt_rp, g_val, gt_val);
-    return hipGetLastError();
-}
-
-hipError_t launch_lp_resid(long long n, double eps, const double *w, const double *v, const double *u, double *r,
-                           hipStream_t st)
-{
-    k_lp_resid<<<lp_grid(n), 256, 0, st>>>(n, eps, w, v, u, r);
-    return hipGetLastError();
-}
-
-hipError_t launch_lp_dodg(int N, double scale, const double *uu, const double *rr, const float *o, const float *s,
-                          const int *g_rp, const double *g_val, const double *r, const double *y, const double *v,
-                          const double *q, double *do64, double *loss, hipStream_t st)
-{
-    const long long n = (long long)N * N * N;
-    k_lp_dodg<<<lp_grid(n), 256, 0, st>>>(N, scale, uu, rr, o, s, g_rp, g_val, r, y, v, q, do64, loss);
+    k_lp_factor<<<dim3(lp_grid(n), nb), 256, 0, st>>>(N, o, s, g_rp, gt_rp, g_val, gt_val, val_stride);
     return hipGetLastError();
 }
 

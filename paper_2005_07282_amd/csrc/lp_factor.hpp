@@ -5,6 +5,7 @@
 
 #include <algorithm>
 
+#include "kernels.hpp"
 #include "lp_common.hpp"
 
 namespace rpcg {
@@ -14,13 +15,35 @@ constexpr float LP_OCLAMP = 4.0f;  // clamp of the diagonal output
 
 hipError_t launch_lp_features(int N, const int *rp, const int *col, const double *val, bf16_t *feat, float *s, int *bad,
                               hipStream_t st);
-hipError_t launch_lp_factor(int N, const float *o, const float *s, const int *g_rp, const int *gt_rp, double *g_val,
-                            double *gt_val, hipStream_t st);
-hipError_t launch_lp_resid(long long n, double eps, const double *w, const double *v, const double *u, double *r,
-                           hipStream_t st);
-hipError_t launch_lp_dodg(int N, double scale, const double *uu, const double *rr, const float *o, const float *s,
-                          const int *g_rp, const double *g_val, const double *r, const double *y, const double *v,
-                          const double *q, double *do64, double *loss, hipStream_t st);
+// G, G^T values of nb instances (grid.y = instance): o, s, g_val, gt_val of
+// instance k at k times the given strides (in elements).
+hipError_t launch_lp_factor(int N, int nb, const float *o, const float *s, const int *g_rp, const int *gt_rp,
+                            double *g_val, double *gt_val, long long val_stride, hipStream_t st);
 hipError_t launch_lp_to_bf16(long long n, const double *a, bf16_t *b, hipStream_t st);
+
+// ---- loss over a batch of (instance, probe) pairs (lp_loss.hip) ----
+// A CSR matrix in device memory (32-bit row pointers and column indices).
+struct LpMat {
+    const int *rp;
+    const int *col;
+    const double *val;
+};
+constexpr int LP_DOT_P = 3;         // lane expansion length of the exact dots
+constexpr int LP_DOT_CHUNKS = 64;   // workgroups (slots) per pair and dot
+// y_p = M_k x_p, p = k nu + m (mats[k], k < nb); x_p = xtab[p] if xtab, else xbase + p n.
+hipError_t launch_lp_mv(long long n, int nb, int nu, const LpMat *mats, const double *const *xtab, const double *xbase,
+                        double *ybase, hipStream_t st);
+// r_p = (G_k y_p + eps v_p) - u_p and the slot partials of <u_p, u_p>, <r_p, r_p>
+// (slots p * LP_DOT_CHUNKS + c of wu, wr; capacity stride >= nb nu LP_DOT_CHUNKS).
+hipError_t launch_lp_resid_dots(long long n, int nb, int nu, double eps, const LpMat *gm, const double *const *utab,
+                                const double *y, const double *v, double *r, const DotWs &wu, const DotWs &wr,
+                                int stride, int *flags, hipStream_t st);
+// dots[2p] = <u_p, u_p>, dots[2p + 1] = <r_p, r_p>, each correctly rounded.
+hipError_t launch_lp_dots_merge(int npairs, const DotWs &wu, const DotWs &wr, int stride, double *dots, int *flags,
+                                hipStream_t st);
+// dL/do of every instance (binary64 into do64, bfloat16 into dob) and the loss.
+hipError_t launch_lp_dodg_all(int N, int nb, int nu, double scale, const double *dots, const float *o, const float *s,
+                              const LpMat *gm, const double *r, const double *y, const double *v, const double *q,
+                              double *do64, bf16_t *dob, double *loss, hipStream_t st);
 
 } // namespace rpcg
