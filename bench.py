@@ -424,7 +424,7 @@ def time_exdot(rpcg, torch, X, Y, mode, reps, warm=10):
     return float(np.median(times)), float(min(times)), float(max(times)), info
 
 
-def run_exdot_grid(log2_max, reps, rpcg, torch, dev):
+def run_exdot_grid(log2_max, reps, rpcg, torch, dev, kinds=EXDOT_KINDS):
     """Standalone exact dot over lengths 2^20..2^log2_max (every second power)
     and the seven input distributions, in the three modes: GB/s of the 16 n
     algorithmic bytes and the fraction of the 8 TB/s HBM peak."""
@@ -433,7 +433,7 @@ def run_exdot_grid(log2_max, reps, rpcg, torch, dev):
     if sizes[-1] != ne:
         sizes.append(ne)
     grid = {}
-    for kind in EXDOT_KINDS:
+    for kind in kinds:
         log(f"[bench] exdot grid {kind}: filling 2^{log2_max}")
         X, Y = fill_exdot(kind, ne, torch, dev)
         grid[kind] = {}
@@ -590,6 +590,8 @@ def main():
     ap.add_argument("--exdot-log2", type=int, default=28)
     ap.add_argument("--exdot-reps", type=int, default=20)
     ap.add_argument("--exdot-only", action="store_true", help="only the exdot grid; prints its JSON")
+    ap.add_argument("--exdot-kinds", default=",".join(EXDOT_KINDS),
+                    help="comma-separated input distributions of the exdot grid")
     ap.add_argument("--cpu-iters", type=int, default=12, help="oracle iterations timed for cpu_baseline")
     ap.add_argument("--cpu-reps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
@@ -642,7 +644,8 @@ def main():
         print(json.dumps(run_learned(args.lp_eval, rpcg, torch, dev)), flush=True)
         return
     if args.exdot_only:
-        print(json.dumps(run_exdot_grid(args.exdot_log2, args.exdot_reps, rpcg, torch, dev)), flush=True)
+        print(json.dumps(run_exdot_grid(args.exdot_log2, args.exdot_reps, rpcg, torch, dev,
+                                        args.exdot_kinds.split(","))), flush=True)
         return
     if args.stress_only:
         print(json.dumps(run_stress(args.stress_n, 100, args.stress_ill_n, 200, rpcg, torch, dev)), flush=True)
@@ -729,10 +732,10 @@ def main():
 
     # standalone exact dot over the length x distribution grid
     ne = 1 << args.exdot_log2
-    exgrid = run_exdot_grid(args.exdot_log2, args.exdot_reps, rpcg, torch, dev)
+    exgrid = run_exdot_grid(args.exdot_log2, args.exdot_reps, rpcg, torch, dev, args.exdot_kinds.split(","))
     top = f"2^{args.exdot_log2}"
     exd = {f"{kind}_{mode}": exgrid["grid"][kind][top][mode] for kind in ("wide", "narrow")
-           for mode in ("exblas", "fpe", "plain")}
+           if kind in exgrid["grid"] for mode in ("exblas", "fpe", "plain")}
 
     cpu = None if args.no_cpu else run_cpu_baseline(A, b, N, args.cpu_iters, args.cpu_reps)
 
