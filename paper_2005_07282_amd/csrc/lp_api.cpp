@@ -24,7 +24,8 @@ struct rpcg_lpnet {
     int N = 0, max_batch = 0;
     long long n = 0;        // N^3
     int gnnz = 0;           // entries of G (and G^T)
-    int fwd_nb = 0;         // batch of the cached forward pass
+    int *bad = nullptr;     // pinned host flag: the generation of the last forward pass that met a bad diagonal
+    int gen = 0;            // forward-pass generation
     int step = 0;           // Adam steps taken
     static constexpr int DW_GRID = 256; // slots of the weight-gradient sums (fixed: fixed order)
     Buffer params, grad, am, av, w1, w2, w3, w2t, w3t;
@@ -79,25 +80,28 @@ int lp_prep(rpcg_lpnet *L, hipStream_t s)
     return RPCG_OK;
 }
 
-int lp_forward(rpcg_lpnet *L, int nb, const rpcg_csr *A, hipStream_t s)
+// Forward pass of nb systems: features, three convolutions; the outputs go to
+// out (device, [nb][N^3][4]) if given, else to the network's own buffer.
+// Waits for completion (the diagonal check).
+int lp_forward(rpcg_lpnet *L, int nb, const rpcg_csr *A, float *out, hipStream_t s)
 {
-    int *bad = &L->ctx->info->flags;
-    RPCG_TRY(hipMemsetAsync(L->ctx->info, 0, sizeof(DotInfo), s));
-    for (int k = 0; k < nb; ++k)
-        RPCG_TRY(launch_lp_features(L->N, A[k].row_ptr, A[k].col_idx, A[k].val, (bf16_t *)L->feat.p + k * L->n * 4,
-                                    (float *)L->s.p + k * L->n, bad, s));
+    const int gen = L->gen = (L->gen % 0x3FFFFFFF) + 1;
+    for (int k0 = 0; k0 < nb; k0 += LP_MAT_ARGS) {
+        LpMatSet set{};
+        const int m = std::min(LP_MAT_ARGS, nb - k0);
+        for (int j = 0; j < m; ++j) set.m[j] = LpMat{A[k0 + j].row_ptr, A[k0 + j].col_idx, A[k0 + j].val};
+        RPCG_TRY(launch_lp_features(L->N, m, set, (bf16_t *)L->feat.p + k0 * L->n * 4, (float *)L->s.p + k0 * L->n,
+                                    L->bad, gen, s));
+    }
     const float *p = (const float *)L->params.p;
     RPCG_TRY(launch_lp_conv(4, 16, EPI_RELU, nb, L->N, (const bf16_t *)L->feat.p, (const bf16_t *)L->w1.p,
                             p + LP_OFF_B1, nullptr, nullptr, (bf16_t *)L->h1.p, s));
     RPCG_TRY(launch_lp_conv(16, 16, EPI_RELU, nb, L->N, (const bf16_t *)L->h1.p, (const bf16_t *)L->w2.p,
                             p + LP_OFF_B2, nullptr, nullptr, (bf16_t *)L->h2.p, s));
     RPCG_TRY(launch_lp_conv(16, 4, EPI_LINEAR, nb, L->N, (const bf16_t *)L->h2.p, (const bf16_t *)L->w3.p,
-                            p + LP_OFF_B3, nullptr, (float *)L->o.p, nullptr, s));
-    DotInfo inf;
-    RPCG_TRY(hipMemcpyAsync(&inf, L->ctx->info, sizeof inf, hipMemcpyDeviceToHost, s));
+                            p + LP_OFF_B3, nullptr, out ? out : (float *)L->o.p, nullptr, s));
     RPCG_TRY(hipStreamSynchronize(s));
-    if (inf.flags) return RPCG_ERR_NOT_SPD;
-    L->fwd_nb = nb;
+    if (__atomic_load_n(L->bad, __ATOMIC_ACQUIRE) == gen) return RPCG_ERR_NOT_SPD;
     return RPCG_OK;
 }
 
@@ -163,7 +167,7 @@ int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *
     const LpMat *mA = (const LpMat *)L->tab.p, *mG = mA + nb, *mGt = mA + 2 * nb;
     const double *const *ut = (const double *const *)((const char *)L->tab.p + mat_bytes);
     double *v = (double *)L->lvec.p, *y = v + P * n, *r = y + P * n, *q = r + P * n;
-    int *flags = &L->ctx->info->flags;
+    int *flags = (int *)((double *)L->scal.p + 4); // exact-dot flags of the loss (not reported)
     const double scale = 1.0 / (double)P;
     RPCG_TRY(launch_lp_factor(L->N, nb, (const float *)L->o.p, (const float *)L->s.p, grp, gtrp, G, Gt, L->gnnz, s));
     RPCG_TRY(launch_lp_mv(n, nb, nu, mA, ut, nullptr, v, s));                                      // v = A u
@@ -239,6 +243,8 @@ int lp_create_body(rpcg_lpnet *L)
     RPCG_TRY(hipMemcpy(L->gt_rp.p, gtrp.data(), sizeof(int) * (L->n + 1), hipMemcpyHostToDevice));
     RPCG_TRY(hipMemcpy(L->g_col.p, gcol.data(), sizeof(int) * nz, hipMemcpyHostToDevice));
     RPCG_TRY(hipMemcpy(L->gt_col.p, gtcol.data(), sizeof(int) * nz, hipMemcpyHostToDevice));
+    RPCG_TRY(hipHostMalloc((void **)&L->bad, sizeof(int), hipHostMallocDefault));
+    *L->bad = 0;
     RPCG_TRY(hipMemset(L->params.p, 0, sizeof(float) * LP_NPARAMS));
     RPCG_TRY(hipMemset(L->am.p, 0, sizeof(float) * LP_NPARAMS));
     RPCG_TRY(hipMemset(L->av.p, 0, sizeof(float) * LP_NPARAMS));
@@ -270,6 +276,7 @@ void rpcg_lp_destroy(rpcg_lpnet *L)
                       &L->g_rp, &L->g_col, &L->gt_rp, &L->gt_col, &L->g_val, &L->gt_val, &L->scal, &L->lvec,
                       &L->lws, &L->dots, &L->tab})
         b->release();
+    if (L->bad) hipHostFree(L->bad);
     delete L;
 }
 
@@ -320,10 +327,7 @@ int rpcg_lp_forward(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, float *o, void
     if (rc != RPCG_OK) return rc;
     RPCG_TRY(hipSetDevice(L->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    rc = lp_forward(L, nb, A, s);
-    if (rc != RPCG_OK) return rc;
-    if (o) RPCG_TRY(hipMemcpyAsync(o, L->o.p, sizeof(float) * 4 * L->n * nb, hipMemcpyDeviceToDevice, s));
-    return RPCG_OK;
+    return lp_forward(L, nb, A, o, s);
 }
 
 int rpcg_lp_factor(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, rpcg_csr *G, rpcg_csr *Gt, void *stream)
@@ -336,7 +340,7 @@ int rpcg_lp_factor(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, rpcg_csr *G, rp
             return RPCG_ERR_INVALID;
     RPCG_TRY(hipSetDevice(L->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    rc = lp_forward(L, nb, A, s);
+    rc = lp_forward(L, nb, A, nullptr, s);
     if (rc != RPCG_OK) return rc;
     for (int k = 0; k < nb; ++k) {
         rc = lp_factor_one(L, k, (double *)G[k].val, (double *)Gt[k].val, s);
@@ -354,7 +358,7 @@ int rpcg_lp_loss_grad(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const double
     if (rc != RPCG_OK) return rc;
     RPCG_TRY(hipSetDevice(L->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    rc = lp_forward(L, nb, A, s);
+    rc = lp_forward(L, nb, A, nullptr, s);
     if (rc != RPCG_OK) return rc;
     rc = lp_loss_grad(L, nb, A, u, nu, eps, loss, s);
     if (rc != RPCG_OK) return rc;
@@ -370,7 +374,7 @@ int rpcg_lp_backward(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const double 
     if (rc != RPCG_OK) return rc;
     RPCG_TRY(hipSetDevice(L->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    rc = lp_forward(L, nb, A, s);
+    rc = lp_forward(L, nb, A, nullptr, s);
     if (rc != RPCG_OK) return rc;
     RPCG_TRY(launch_lp_to_bf16(4 * L->n * nb, dout, (bf16_t *)L->dob.p, s));
     rc = lp_backward(L, nb, s);
@@ -388,7 +392,7 @@ int rpcg_lp_train_step(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const doubl
     if (rc != RPCG_OK) return rc;
     RPCG_TRY(hipSetDevice(L->ctx->device));
     hipStream_t s = (hipStream_t)stream;
-    rc = lp_forward(L, nb, A, s);
+    rc = lp_forward(L, nb, A, nullptr, s);
     if (rc != RPCG_OK) return rc;
     rc = lp_loss_grad(L, nb, A, u, nu, eps, nullptr, s);
     if (rc != RPCG_OK) return rc;

@@ -14,155 +14,181 @@ __device__ __forceinline__ void tap_offset(int t, int &dz, int &dy, int &dx)
     dx = t % 3 - 1;
 }
 
-// Implicit-GEMM convolution on gfx950's 16x16x32 bfloat16 MFMA. A wavefront
-// computes tiles of 16 cells along x (rows M) by 16 output channels (columns
-// N); K runs over (tap, input channel) in chunks of 32: two taps of 16 input
-// channels, or eight taps of 4. Lane l supplies A[m = l%16][k = 8(l/16) + j]
-// and B[k][n = l%16] for j < 8 and receives D[4(l/16) + j][l%16] for j < 4.
+// Implicit-GEMM convolution on gfx950's 16x16x32 bfloat16 MFMA, computing
+// D[co][cell] = sum_k W[co][k] In[k][cell] for 16 output channels (rows M,
+// padded) by 16 cells along x (columns N). Lane l supplies A[m = l%16][k =
+// 8(l/16) + j] and B[k][n = l%16] for j < 8 and receives D[4(l/16) + j][l%16]
+// for j < 4: four output channels of one cell, stored as one 8-byte unit.
 //
-// A workgroup of four wavefronts takes a block of 16 x 4 x 2 output cells
-// (one y-line and two z-planes per wavefront: two independent accumulator
-// chains) and first stages the block's inputs with their halo (18 x 6 x 4
-// cells, zeros outside the grid) in LDS with coalesced loads, so each input
-// is fetched from memory once per block. The weights are packed once per
-// workgroup in the B-operand order, 16 bytes per lane and chunk.
-constexpr int CONV_BX = 16, CONV_BY = 4, CONV_BZ = 2;          // block of output cells (x, y, z)
-constexpr int CONV_HX = CONV_BX + 2, CONV_HY = CONV_BY + 2, CONV_HZ = CONV_BZ + 2; // with halo
-constexpr int CONV_HCELLS = CONV_HX * CONV_HY * CONV_HZ;
-
-template <int CIN>
-__host__ __device__ constexpr int conv_chunks() { return CIN == 16 ? 14 : 4; }
+// The weights are the A operands and stay in registers for the whole kernel.
+// K runs over the taps of one input plane: for each dz, the nine (dy, dx)
+// taps go in chunks of 32 = two taps of 16 input channels (five chunks, the
+// last half empty) or eight taps of 4 (two chunks). A wavefront owns one
+// y-line of 16 cells and a run of CONV_ZR z-planes and streams the input
+// planes along z: the B operands of input plane p (read straight from memory,
+// zeros outside the grid) feed the three output planes p + 1, p, p - 1
+// (dz = -1, 0, +1) with that dz's weights, so each input fragment is loaded
+// once per line and used three times; output plane p - 1 is complete after
+// plane p and is written. The next plane's fragments are loaded while the
+// current plane's products run. No LDS, no barriers.
+constexpr int CONV_BX = 16, CONV_HX = CONV_BX + 2; // cells along x of a line (and with the x halo)
+constexpr int CONV_LINES = 4;                      // wavefronts (y-lines) per workgroup
+constexpr int CONV_ZR = 16;                        // output planes per wavefront
 
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef short v8s __attribute__((ext_vector_type(8)));
 
-// Stage the inputs of the block at (x0, y0, z0) of one system with its
-// halo: the 8 channels of group q of halo cell c at tile[(q * HC + c) * 8]
-// (CIN = 16, two groups), or the 4 channels of cell c at tile[c * 4] (CIN =
-// 4). Consecutive threads take consecutive 16- or 8-byte units along x, so
-// a wavefront reads whole runs of the input.
 template <int CIN>
-__device__ __forceinline__ void stage_block(bf16_t *tile, const bf16_t *__restrict__ inb, int N, int x0, int y0, int z0)
+__host__ __device__ constexpr int conv_chunks() { return CIN == 16 ? 5 : 2; }
+
+// Tap (dy, dx) of entry e < 9 of the nine taps of a plane (row-major in dy, dx).
+__device__ __forceinline__ int tap9_dy(int e) { return e / 3 - 1; }
+__device__ __forceinline__ int tap9_dx(int e) { return e % 3 - 1; }
+
+// Taps of chunk q held by operand lanes of group kb: CIN = 16, tap e =
+// 2q + kb/2, channels 8(kb%2) .. + 7; CIN = 4, taps e = 8q + 2kb and
+// 8q + 2kb + 1, channels 0 .. 3 of each. e >= 9 is an empty half.
+template <int CIN>
+__device__ __forceinline__ int chunk_tap(int q, int kb, int h)
 {
-    constexpr int Q = CIN == 16 ? 2 : 1, HC = CONV_HCELLS;
-    for (int u = threadIdx.x; u < HC * Q; u += blockDim.x) {
-        const int q = u % Q, cell = u / Q;
-        const int xc = cell % CONV_HX, yc = (cell / CONV_HX) % CONV_HY, zc = cell / (CONV_HX * CONV_HY);
-        const int X = x0 - 1 + xc, Y = y0 - 1 + yc, Z = z0 - 1 + zc;
-        const bool in = X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N;
-        const long long src = (((long long)Z * N + Y) * N + X) * CIN;
-        if constexpr (CIN == 16) {
-            v8s v = {0, 0, 0, 0, 0, 0, 0, 0};
-            if (in) v = *(const v8s *)(inb + src + 8 * q);
-            *(v8s *)&tile[(q * HC + cell) * 8] = v;
-        } else {
-            v4s v = {0, 0, 0, 0};
-            if (in) v = *(const v4s *)(inb + src);
-            *(v4s *)&tile[cell * 4] = v;
-        }
-    }
+    return CIN == 16 ? 2 * q + (kb >> 1) : 8 * q + 2 * kb + h;
 }
 
-// Halo cell of output cell (m, wave line, plane zo) shifted by tap t.
-__device__ __forceinline__ int halo_cell(int t, int m, int wave, int zo)
+// A operands: W[t][co][ci] of the chunk's taps in the dz plane dzi (0, 1, 2
+// for dz = -1, 0, +1), zeros for empty halves.
+template <int CIN>
+__device__ __forceinline__ v8s load_wchunk(const bf16_t *__restrict__ wt, int dzi, int q, int co, int kb)
 {
-    int dz, dy, dx;
-    tap_offset(t, dz, dy, dx);
-    return ((zo + dz + 1) * CONV_HY + (wave + dy + 1)) * CONV_HX + (m + dx + 1);
+    v8s a = {0, 0, 0, 0, 0, 0, 0, 0};
+    if constexpr (CIN == 16) {
+        const int e = chunk_tap<16>(q, kb, 0);
+        if (e < 9) a = *(const v8s *)(wt + ((9 * dzi + e) * 16 + co) * 16 + 8 * (kb & 1));
+    } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = chunk_tap<4>(q, kb, h);
+            if (e < 9) {
+                const v4s w = *(const v4s *)(wt + ((9 * dzi + e) * 16 + co) * 4);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[4 * h + j] = w[j];
+            }
+        }
+    }
+    return a;
+}
+
+// B operands of input plane z for the line (x0 + n, y): the chunk's taps at
+// (x0 + n + dx, y + dy, z), zeros outside the grid or for empty halves.
+template <int CIN>
+__device__ __forceinline__ void load_bplane(v8s (&bq)[conv_chunks<CIN>()], const bf16_t *__restrict__ inb, int N,
+                                            int x0, int y, int z, int n, int kb)
+{
+    const bool zin = z >= 0 && z < N;
+#pragma unroll
+    for (int q = 0; q < conv_chunks<CIN>(); ++q) {
+        v8s b = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < (CIN == 16 ? 1 : 2); ++h) {
+            const int e = chunk_tap<CIN>(q, kb, h);
+            const int X = x0 + n + tap9_dx(e), Y = y + tap9_dy(e);
+            if (e < 9 && zin && X >= 0 && X < N && Y >= 0 && Y < N) {
+                const long long cell = ((long long)z * N + Y) * N + X;
+                if constexpr (CIN == 16) {
+                    b = *(const v8s *)(inb + cell * 16 + 8 * (kb & 1));
+                } else {
+                    const v4s v = *(const v4s *)(inb + cell * 4);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) b[4 * h + j] = v[j];
+                }
+            }
+        }
+        bq[q] = b;
+    }
 }
 
 template <int CIN, int COUT, int EPI>
-__global__ void __launch_bounds__(64 * CONV_BY) k_lp_conv(int nb, int N, const bf16_t *__restrict__ in,
-                                                          const bf16_t *__restrict__ wt, const float *__restrict__ bias,
-                                                          const bf16_t *__restrict__ mask, float *__restrict__ pre,
-                                                          bf16_t *__restrict__ act)
+__global__ void __launch_bounds__(64 * CONV_LINES) k_lp_conv(int nb, int N, const bf16_t *__restrict__ in,
+                                                             const bf16_t *__restrict__ wt,
+                                                             const float *__restrict__ bias,
+                                                             const bf16_t *__restrict__ mask, float *__restrict__ pre,
+                                                             bf16_t *__restrict__ act)
 {
     constexpr int NCH = conv_chunks<CIN>();
-    // B operands: wp[((c * 4 + kb) * 16 + co) * 8 + j] = W[tap][co][ci] of k = 8 kb + j in chunk c
-    __shared__ __attribute__((aligned(16))) bf16_t wp[NCH * 4 * 16 * 8];
-    __shared__ __attribute__((aligned(16))) bf16_t tile[CONV_HCELLS * CIN];
-    for (int u = threadIdx.x; u < NCH * 4 * 16 * 8; u += blockDim.x) {
-        const int j = u & 7, co = (u >> 3) & 15, kb = (u >> 7) & 3, c = u >> 9;
-        int t, ci;
-        if (CIN == 16) { t = 2 * c + (kb >> 1); ci = 8 * (kb & 1) + j; }
-        else { t = 8 * c + 2 * kb + (j >> 2); ci = j & 3; }
-        wp[u] = t < LP_TAPS ? wt[(t * 16 + co) * CIN + ci] : (bf16_t)0;
-    }
-    const int lane = threadIdx.x & 63, kb = lane >> 4, m = lane & 15;
+    const int lane = threadIdx.x & 63, kb = lane >> 4, n = lane & 15;
     const int wave = threadIdx.x >> 6;
-    const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + CONV_BY - 1) / CONV_BY;
-    const int tiles_z = (N + CONV_BZ - 1) / CONV_BZ;
-    const long long nblocks = (long long)nb * tiles_z * tiles_y * tiles_x;
+    // tiles (system, z-run, x-tile, y-group), y-group fastest; each XCD takes a
+    // contiguous range of them when the count allows (neighbours share its L2)
+    const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + CONV_LINES - 1) / CONV_LINES;
+    const int runs = (N + CONV_ZR - 1) / CONV_ZR;
+    const long long ntiles = (long long)nb * runs * tiles_x * tiles_y;
+    long long tile = blockIdx.x;
+    if (ntiles % 8 == 0) tile = (tile % 8) * (ntiles / 8) + tile / 8;
+    const int ty = (int)(tile % tiles_y);
+    long long r = tile / tiles_y;
+    const int tx = (int)(r % tiles_x);
+    r /= tiles_x;
+    const int zr = (int)(r % runs);
+    const long long b = r / runs;
+    const int x0 = tx * CONV_BX, y = ty * CONV_LINES + wave, z0 = zr * CONV_ZR;
+    const int z1 = min(z0 + CONV_ZR, N);
+    if (y >= N) return; // wavefront-uniform; no barriers in this kernel
     const long long N3 = (long long)N * N * N;
-    for (long long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) { // workgroup-uniform
-        const int tx = (int)(blk % tiles_x);
-        long long r = blk / tiles_x;
-        const int ty = (int)(r % tiles_y);
-        r /= tiles_y;
-        const int tz = (int)(r % tiles_z);
-        const long long b = r / tiles_z;
-        const int x0 = tx * CONV_BX, y0 = ty * CONV_BY, z0 = tz * CONV_BZ;
-        __syncthreads(); // the previous block's readers are done (and the weights are in place)
-        stage_block<CIN>(tile, in + b * N3 * CIN, N, x0, y0, z0);
-        __syncthreads();
-        const int y = y0 + wave;
-        if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
-        v4f acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
-        for (int c = 0; c < NCH; ++c) {
-            const v8bf bw = __builtin_bit_cast(v8bf, *(const v8s *)&wp[((c * 4 + kb) * 16 + m) * 8]);
-            v8s a0 = {0, 0, 0, 0, 0, 0, 0, 0}, a1 = a0;
-            if constexpr (CIN == 16) {
-                const int t = 2 * c + (kb >> 1);
-                if (t < LP_TAPS) { // rows m past the grid's edge read valid LDS cells; their outputs are not stored
-                    a0 = *(const v8s *)&tile[((kb & 1) * CONV_HCELLS + halo_cell(t, m, wave, 0)) * 8];
-                    a1 = *(const v8s *)&tile[((kb & 1) * CONV_HCELLS + halo_cell(t, m, wave, 1)) * 8];
-                }
-            } else {
-                const int t = 8 * c + 2 * kb;
-                if (t < LP_TAPS) {
-                    const v4s p0 = *(const v4s *)&tile[halo_cell(t, m, wave, 0) * 4];
-                    const v4s p1 = *(const v4s *)&tile[halo_cell(t, m, wave, 1) * 4];
-                    a0[0] = p0[0]; a0[1] = p0[1]; a0[2] = p0[2]; a0[3] = p0[3];
-                    a1[0] = p1[0]; a1[1] = p1[1]; a1[2] = p1[2]; a1[3] = p1[3];
-                }
-                if (t + 1 < LP_TAPS) {
-                    const v4s p0 = *(const v4s *)&tile[halo_cell(t + 1, m, wave, 0) * 4];
-                    const v4s p1 = *(const v4s *)&tile[halo_cell(t + 1, m, wave, 1) * 4];
-                    a0[4] = p0[0]; a0[5] = p0[1]; a0[6] = p0[2]; a0[7] = p0[3];
-                    a1[4] = p1[0]; a1[5] = p1[1]; a1[6] = p1[2]; a1[7] = p1[3];
-                }
-            }
-            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a0), bw, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a1), bw, acc1, 0, 0, 0);
-        }
-        const int co = m;
-        if (co < COUT) {
+    const bf16_t *__restrict__ inb = in + b * N3 * CIN;
+    v8bf w[3][NCH];
 #pragma unroll
-            for (int zo = 0; zo < CONV_BZ; ++zo) {
-                const int z = z0 + zo;
-                if (z >= N) continue;
-                const v4f acc = zo ? acc1 : acc0;
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) w[d][q] = __builtin_bit_cast(v8bf, load_wchunk<CIN>(wt, d, q, n, kb));
+    float bv[4] = {0.f, 0.f, 0.f, 0.f};
+    if (EPI != EPI_MASK && 4 * kb < COUT)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = bias[4 * kb + j];
+    const int x = x0 + n;
+    v4f a_prev = {0.f, 0.f, 0.f, 0.f}, a_cur = a_prev, a_next = a_prev; // outputs p - 1, p, p + 1
+    v8s bn[NCH];
+    load_bplane<CIN>(bn, inb, N, x0, y, z0 - 1, n, kb);
+    for (int p = z0 - 1; p <= z1; ++p) {
+        v8s bq[NCH];
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) bq[q] = bn[q];
+        if (p < z1) load_bplane<CIN>(bn, inb, N, x0, y, p + 1, n, kb);
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) {
+            const v8bf bb = __builtin_bit_cast(v8bf, bq[q]);
+            a_next = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][q], bb, a_next, 0, 0, 0); // dz = -1: output p + 1
+            a_cur = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1][q], bb, a_cur, 0, 0, 0);   // dz = 0: output p
+            a_prev = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2][q], bb, a_prev, 0, 0, 0); // dz = +1: output p - 1
+        }
+        const int z = p - 1; // complete
+        if (z >= z0 && x < N && 4 * kb < COUT) {
+            const long long cell = b * N3 + ((long long)z * N + y) * N + x;
+            if (EPI == EPI_RELU) {
+                v4s o;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int x = x0 + 4 * kb + j;
-                    if (x >= N) continue;
-                    const long long cell = b * N3 + ((long long)z * N + y) * N + x;
-                    const float v = acc[j];
-                    if (EPI == EPI_RELU) {
-                        const float p = v + bias[co];
-                        if (pre) pre[cell * COUT + co] = p;
-                        act[cell * COUT + co] = f32_to_bf16(p > 0.f ? p : 0.f);
-                    } else if (EPI == EPI_LINEAR) {
-                        pre[cell * COUT + co] = v + bias[co];
-                    } else {
-                        // the relu of the forward layer was active where its stored
-                        // (bfloat16) activation is nonzero
-                        act[cell * COUT + co] = f32_to_bf16(mask[cell * COUT + co] != 0 ? v : 0.f);
-                    }
+                    const float v = a_prev[j] + bv[j];
+                    o[j] = (short)f32_to_bf16(v > 0.f ? v : 0.f);
                 }
+                *(v4s *)(act + cell * COUT + 4 * kb) = o;
+                if (pre)
+                    *(v4f *)(pre + cell * COUT + 4 * kb) =
+                        (v4f){a_prev[0] + bv[0], a_prev[1] + bv[1], a_prev[2] + bv[2], a_prev[3] + bv[3]};
+            } else if (EPI == EPI_LINEAR) {
+                *(v4f *)(pre + cell * COUT + 4 * kb) =
+                    (v4f){a_prev[0] + bv[0], a_prev[1] + bv[1], a_prev[2] + bv[2], a_prev[3] + bv[3]};
+            } else {
+                // the relu of the forward layer was active where its stored
+                // (bfloat16) activation is nonzero
+                const v4s mk = *(const v4s *)(mask + cell * COUT + 4 * kb);
+                v4s o;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) o[j] = (short)f32_to_bf16(mk[j] != 0 ? a_prev[j] : 0.f);
+                *(v4s *)(act + cell * COUT + 4 * kb) = o;
             }
         }
+        a_prev = a_cur;
+        a_cur = a_next;
+        a_next = (v4f){0.f, 0.f, 0.f, 0.f};
     }
 }
 
@@ -358,11 +384,12 @@ __global__ void k_lp_adam(int n, float *__restrict__ p, const float *__restrict_
 hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_t *in, const bf16_t *wt,
                           const float *bias, const bf16_t *mask, float *pre, bf16_t *act, hipStream_t s)
 {
-    const long long blocks = (long long)nb * ((N + CONV_BZ - 1) / CONV_BZ) * ((N + CONV_BY - 1) / CONV_BY) *
-                             ((N + CONV_BX - 1) / CONV_BX);
-    const int grid = (int)std::min<long long>(blocks, 8192);
-    const int block = 64 * CONV_BY;
-    if (grid <= 0) return hipSuccess;
+    const long long tiles = (long long)nb * ((N + CONV_ZR - 1) / CONV_ZR) * ((N + CONV_BX - 1) / CONV_BX) *
+                            ((N + CONV_LINES - 1) / CONV_LINES);
+    if (tiles <= 0) return hipSuccess;
+    if (tiles > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const int grid = (int)tiles;
+    const int block = 64 * CONV_LINES;
     if (cin == 4 && cout == 16 && epi == EPI_RELU)
         k_lp_conv<4, 16, EPI_RELU><<<grid, block, 0, s>>>(nb, N, in, wt, bias, mask, pre, act);
     else if (cin == 16 && cout == 16 && epi == EPI_RELU)

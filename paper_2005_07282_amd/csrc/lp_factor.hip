@@ -15,29 +15,35 @@ namespace rpcg {
 __device__ __forceinline__ float lp_clamp(float v) { return fminf(fmaxf(v, -LP_OCLAMP), LP_OCLAMP); }
 
 // features: ln(|a_ij| / a_ii) of the -x, -y, -z neighbours (LP_ABSENT if
-// missing), (number of absent neighbours) / 6; and s_i. Flags a non-positive
-// or missing diagonal.
-__global__ void k_lp_features(int N, const int *__restrict__ rp, const int *__restrict__ col,
-                              const double *__restrict__ val, bf16_t *__restrict__ feat, float *__restrict__ s,
-                              int *bad)
+// missing), (number of absent neighbours) / 6; and s_i. A non-positive or
+// missing diagonal stores gen into *bad. System k = blockIdx.y.
+__global__ void k_lp_features(int N, LpMatSet set, bf16_t *__restrict__ feat, float *__restrict__ s, int *bad, int gen)
 {
     const long long n = (long long)N * N * N;
+    const int k = blockIdx.y;
+    const int *__restrict__ rp = set.m[k].rp;
+    const int *__restrict__ col = set.m[k].col;
+    const double *__restrict__ val = set.m[k].val;
+    feat += (long long)k * n * 4;
+    s += (long long)k * n;
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((long long)N * N));
         double aii = 0.0, a[3] = {0.0, 0.0, 0.0};
         const long long nb[3] = {x > 0 ? i - 1 : -1, y > 0 ? i - N : -1, z > 0 ? i - (long long)N * N : -1};
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-            const long long c = col[k];
-            if (c == i) aii = val[k];
+        const int b = rp[i], e = rp[i + 1];
+        for (int q = b; q < e; ++q) {
+            const long long c = col[q];
+            const double v = val[q];
+            if (c == i) aii = v;
             for (int d = 0; d < 3; ++d)
-                if (c == nb[d]) a[d] = val[k];
+                if (c == nb[d]) a[d] = v;
         }
-        if (!(aii > 0.0)) atomicOr(bad, 1);
-        for (int d = 0; d < 3; ++d) {
-            const float f = (nb[d] >= 0 && a[d] != 0.0) ? (float)log(fabs(a[d]) / aii) : LP_ABSENT;
-            feat[i * 4 + d] = f32_to_bf16(f);
-        }
-        feat[i * 4 + 3] = f32_to_bf16((float)((7 - (rp[i + 1] - rp[i])) / 6.0));
+        if (!(aii > 0.0)) *bad = gen;
+        bf16_t f[4];
+        for (int d = 0; d < 3; ++d)
+            f[d] = f32_to_bf16((nb[d] >= 0 && a[d] != 0.0) ? (float)log(fabs(a[d]) / aii) : LP_ABSENT);
+        f[3] = f32_to_bf16((float)((7 - (e - b)) / 6.0));
+        *(v4s *)&feat[i * 4] = (v4s){(short)f[0], (short)f[1], (short)f[2], (short)f[3]};
         s[i] = (float)(1.0 / sqrt(aii));
     }
 }
@@ -80,11 +86,12 @@ __global__ void k_lp_to_bf16(long long n, const double *__restrict__ a, bf16_t *
 
 static int lp_grid(long long n) { return (int)std::min<long long>(std::max<long long>((n + 255) / 256, 1), 4096); }
 
-hipError_t launch_lp_features(int N, const int *rp, const int *col, const double *val, bf16_t *feat, float *s, int *bad,
+hipError_t launch_lp_features(int N, int nb, const LpMatSet &set, bf16_t *feat, float *s, int *bad, int gen,
                               hipStream_t st)
 {
     const long long n = (long long)N * N * N;
-    k_lp_features<<<lp_grid(n), 256, 0, st>>>(N, rp, col, val, feat, s, bad);
+    if (nb < 1 || nb > LP_MAT_ARGS) return hipErrorInvalidValue;
+    k_lp_features<<<dim3(lp_grid(n), nb), 256, 0, st>>>(N, set, feat, s, bad, gen);
     return hipGetLastError();
 }
 

@@ -13,7 +13,22 @@ namespace rpcg {
 constexpr float LP_ABSENT = -4.0f; // feature of an absent neighbour
 constexpr float LP_OCLAMP = 4.0f;  // clamp of the diagonal output
 
-hipError_t launch_lp_features(int N, const int *rp, const int *col, const double *val, bf16_t *feat, float *s, int *bad,
+// A CSR matrix in device memory (32-bit row pointers and column indices).
+struct LpMat {
+    const int *rp;
+    const int *col;
+    const double *val;
+};
+// Up to LP_MAT_ARGS matrices passed by value to one launch.
+constexpr int LP_MAT_ARGS = 16;
+struct LpMatSet {
+    LpMat m[LP_MAT_ARGS];
+};
+
+// Features and s of nb <= LP_MAT_ARGS systems (grid.y = system; feat and s of
+// system k at k n 4 and k n). A missing or non-positive diagonal stores gen
+// into *bad (host-visible memory; plain stores of one value).
+hipError_t launch_lp_features(int N, int nb, const LpMatSet &set, bf16_t *feat, float *s, int *bad, int gen,
                               hipStream_t st);
 // G, G^T values of nb instances (grid.y = instance): o, s, g_val, gt_val of
 // instance k at k times the given strides (in elements).
@@ -22,12 +37,6 @@ hipError_t launch_lp_factor(int N, int nb, const float *o, const float *s, const
 hipError_t launch_lp_to_bf16(long long n, const double *a, bf16_t *b, hipStream_t st);
 
 // ---- loss over a batch of (instance, probe) pairs (lp_loss.hip) ----
-// A CSR matrix in device memory (32-bit row pointers and column indices).
-struct LpMat {
-    const int *rp;
-    const int *col;
-    const double *val;
-};
 constexpr int LP_DOT_P = 3;         // lane expansion length of the exact dots
 constexpr int LP_DOT_CHUNKS = 64;   // workgroups (slots) per pair and dot
 // y_p = M_k x_p, p = k nu + m (mats[k], k < nb); x_p = xtab[p] if xtab, else xbase + p n.

@@ -152,6 +152,31 @@ def test_factor_independent_of_batch(R, net10):
     assert (Gs.T != Gts).nnz == 0
 
 
+def test_forward_large_batch_and_bad_diagonal(R):
+    """Batches above one launch's 16 matrices give the outputs of the systems
+    alone; a non-positive diagonal is reported, and a later good batch is
+    not affected by the earlier report."""
+    N = 6
+    net = R.LearnedPreconditioner(N, max_batch=18)
+    net.set_params(params(3))
+    As = systems(N, list(range(40, 58)))
+    mats = [R.CSR.from_host(A) for A in As]
+    together = net.forward(mats).cpu()
+    for k in (0, 15, 16, 17):
+        alone = net.forward([mats[k]]).cpu()[0]
+        assert torch.equal(together[k], alone), k
+    bad = As[5]
+    val = bad.val.copy()
+    rows = np.repeat(np.arange(bad.n), np.diff(bad.row_ptr))
+    val[np.flatnonzero(bad.col_idx == rows)[7]] = -1.0
+    badm = R.CSR.from_host(CSRHost(bad.n, bad.row_ptr, bad.col_idx, val))
+    with pytest.raises(R.RpcgError) as ei:
+        net.forward(mats[:17] + [badm])
+    assert ei.value.status == R.ERR_NOT_SPD
+    again = net.forward(mats).cpu()
+    assert torch.equal(again, together)
+
+
 def test_training_reproducible_and_learning(R):
     N = 12
     As = systems(N, [21, 22, 23, 24])
