@@ -29,8 +29,10 @@ __device__ __forceinline__ void tap_offset(int t, int &dz, int &dy, int &dx)
 // zeros outside the grid) feed the three output planes p + 1, p, p - 1
 // (dz = -1, 0, +1) with that dz's weights, so each input fragment is loaded
 // once per line and used three times; output plane p - 1 is complete after
-// plane p and is written. The next plane's fragments are loaded while the
-// current plane's products run. No LDS, no barriers.
+// plane p and is written. No LDS, no barriers; a plane's loads are issued
+// at its start and their latency is covered by the other wavefronts of the
+// SIMD (about 110 registers a lane leave room for three or four; loading the
+// next plane ahead would double the operand registers and halve that).
 constexpr int CONV_BX = 16, CONV_HX = CONV_BX + 2; // cells along x of a line (and with the x halo)
 constexpr int CONV_LINES = 4;                      // wavefronts (y-lines) per workgroup
 constexpr int CONV_ZR = 16;                        // output planes per wavefront
@@ -145,13 +147,9 @@ __global__ void __launch_bounds__(64 * CONV_LINES) k_lp_conv(int nb, int N, cons
         for (int j = 0; j < 4; ++j) bv[j] = bias[4 * kb + j];
     const int x = x0 + n;
     v4f a_prev = {0.f, 0.f, 0.f, 0.f}, a_cur = a_prev, a_next = a_prev; // outputs p - 1, p, p + 1
-    v8s bn[NCH];
-    load_bplane<CIN>(bn, inb, N, x0, y, z0 - 1, n, kb);
     for (int p = z0 - 1; p <= z1; ++p) {
         v8s bq[NCH];
-#pragma unroll
-        for (int q = 0; q < NCH; ++q) bq[q] = bn[q];
-        if (p < z1) load_bplane<CIN>(bn, inb, N, x0, y, p + 1, n, kb);
+        load_bplane<CIN>(bq, inb, N, x0, y, p, n, kb);
 #pragma unroll
         for (int q = 0; q < NCH; ++q) {
             const v8bf bb = __builtin_bit_cast(v8bf, bq[q]);
