@@ -27,7 +27,7 @@ struct rpcg_lpnet {
     int *bad = nullptr;     // pinned host flag: the generation of the last forward pass that met a bad diagonal
     int gen = 0;            // forward-pass generation
     int step = 0;           // Adam steps taken
-    static constexpr int DW_GRID = 256; // slots of the weight-gradient sums (fixed: fixed order)
+    static constexpr int DW_GRID = 1024; // slots of the weight-gradient sums (fixed: fixed order)
     Buffer params, grad, am, av, w1, w2, w3, w2t, w3t;
     Buffer feat, s, h1, h2, o, do64, dob, d2, d1, pw, pb;
     Buffer g_rp, g_col, gt_rp, gt_col, g_val, gt_val, scal;

@@ -47,8 +47,9 @@ enum { EPI_RELU = 0, EPI_LINEAR = 1, EPI_MASK = 2 };
 // nonzero, else 0 (the adjoint pass of a relu layer).
 hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_t *in, const bf16_t *wt,
                           const float *bias, const bf16_t *mask, float *pre, bf16_t *act, hipStream_t s);
-// Partial weight and bias gradients in grid slots (three workgroups per slot, one per dz):
-// pw[g][27][16][16] (out, in), pb[g][16]; then a fixed-order sum over slots.
+// Partial weight and bias gradients in grid slots (one workgroup of three
+// wavefronts per slot): pw[g][27][16][16] (out, in), pb[g][16]; then a
+// fixed-order sum over the slots.
 hipError_t launch_lp_conv_dw(int cin, int cout, int nb, int N, const bf16_t *in, const bf16_t *dout, float *pw,
                              float *pb, int grid, hipStream_t s);
 hipError_t launch_lp_reduce(int nslots, int cout, int cin, const float *pw, const float *pb, float *gw, float *gb,

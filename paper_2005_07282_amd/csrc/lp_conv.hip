@@ -33,7 +33,7 @@ __device__ __forceinline__ void tap_offset(int t, int &dz, int &dy, int &dx)
 // at its start and their latency is covered by the other wavefronts of the
 // SIMD (about 110 registers a lane leave room for three or four; loading the
 // next plane ahead would double the operand registers and halve that).
-constexpr int CONV_BX = 16, CONV_HX = CONV_BX + 2; // cells along x of a line (and with the x halo)
+constexpr int CONV_BX = 16;    // cells along x of a line
 constexpr int CONV_LINES = 4;                      // wavefronts (y-lines) per workgroup
 constexpr int CONV_ZR = 16;                        // output planes per wavefront
 
@@ -190,160 +190,232 @@ __global__ void __launch_bounds__(64 * CONV_LINES) k_lp_conv(int nb, int N, cons
     }
 }
 
-// Weight gradients: the staged inputs are kept in groups of four channels: group q of cell c
-// is the 8 bytes at tile[(q * P + c) * 4], with a pitch P = 1 (mod 16) cells
-// so that the four groups of one cell fall in different LDS banks.
-__host__ __device__ constexpr int halo_pitch(int cells) { return cells + (17 - cells % 16) % 16; }
+// Weight gradient dW[t][co][ci] = sum over cells of dout[cell][co] in[cell + off(t)][ci]
+// and bias gradient db[co] = sum of dout[cell][co], on 16x16x32 MFMA with
+// M = co, N = ci and K = 32 cells along x: lane l supplies dout at cells
+// 8(l/16) + j of channel l%16 (A) and the input at the same cells shifted by
+// the tap, channel l%16 (B). A workgroup is three wavefronts, one per dz,
+// each holding the nine tap tiles of its plane, and walks its items (system,
+// z-run, y-line, 32-cell x-segment) one z-plane at a time. Per plane it
+// stages, with 16-byte loads, the dout row of the plane and the three input
+// rows y - 1 .. y + 1 of the next plane into a ring of three planes in LDS
+// (zeros outside the grid), so every input row is loaded once and read by
+// the three wavefronts (dz = -1, 0, +1 read the planes z - 1, z, z + 1); the
+// loads of the next plane go to registers under the current plane's
+// products and are written to LDS at the start of the next step. The
+// operands are then gathered from LDS as 16-bit values: per input row a lane
+// reads the ten cells x - 1 .. x + 8 around its eight and forms the three dx
+// fragments from them. Every eighth staged cell is followed by a gap of one
+// cell (16 channels), so the four k-groups of a gather fall in different
+// banks. Each wavefront writes its nine taps to the workgroup's slot; the
+// slots are summed in a fixed order later.
+constexpr int DW_SEG = 32; // cells along x per item (the K of one product)
+constexpr int DW_ZR = 64;  // z-planes per item
+constexpr int DW_XC = DW_SEG + 2; // staged input cells per row
 
-// Stage the inputs of the block of BY y-lines of 16 cells at (x0, y0) of
-// system b, with a one-cell halo in x and y, over the HZ planes from z0,
-// into cells (zc * (BY + 2) + yc) * 18 + xc of tile (zeros outside the
-// grid). 8-byte units; sixteen consecutive threads take one channel group of
-// sixteen consecutive cells, so a wavefront reads whole runs of the input
-// and writes whole LDS rows.
-template <int CIN, int BY, int HZ>
-__device__ __forceinline__ void stage_halo(bf16_t *tile, const bf16_t *__restrict__ inb, int N, int x0, int y0, int z0)
+// Byte offset of staged cell c in a row of cells of C channels.
+template <int C>
+__host__ __device__ constexpr int dw_cell(int c) { return C == 16 ? (c + (c >> 3)) * 32 : c * 8; }
+template <int C>
+__host__ __device__ constexpr int dw_row_bytes(int cells) { return dw_cell<C>(cells); }
+
+// Stage `cells` cells of row (Z, Y) from x = X0 on (zeros outside the grid)
+// at dst, with all threads of the workgroup; 16-byte units (8 channels), or
+// one 8-byte unit per cell for 4 channels.
+template <int C>
+__device__ __forceinline__ void dw_stage_row(unsigned char *dst, const bf16_t *__restrict__ src, int N, int Z, int Y,
+                                             int X0, int cells, int first, int stride)
 {
-    constexpr int UPC = CIN / 4, HY = BY + 2, HC = CONV_HX * HY * HZ, P = halo_pitch(HC);
-    constexpr int RUNS = (HC + 15) / 16;
-    for (int u = threadIdx.x; u < RUNS * 16 * UPC; u += blockDim.x) {
-        const int q = (u >> 4) % UPC, cell = (u / (16 * UPC)) * 16 + (u & 15);
-        if (cell >= HC) continue;
-        const int xc = cell % CONV_HX, yc = (cell / CONV_HX) % HY, zc = cell / (CONV_HX * HY);
-        const int X = x0 - 1 + xc, Y = y0 - 1 + yc, Z = z0 + zc;
-        v4s v = {0, 0, 0, 0};
-        if (X >= 0 && X < N && Y >= 0 && Y < N && Z >= 0 && Z < N)
-            v = *(const v4s *)(inb + (((long long)Z * N + Y) * N + X) * CIN + 4 * q);
-        *(v4s *)&tile[(q * P + cell) * 4] = v;
+    constexpr int UPC = C == 16 ? 2 : 1;
+    const bool row_in = Z >= 0 && Z < N && Y >= 0 && Y < N;
+    for (int u = first; u < cells * UPC; u += stride) {
+        const int c = u / UPC, q = u % UPC, X = X0 + c;
+        const bool in = row_in && X >= 0 && X < N;
+        const long long cell = ((long long)Z * N + Y) * N + X;
+        if constexpr (C == 16) {
+            v8s v = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (in) v = *(const v8s *)(src + cell * 16 + 8 * q);
+            *(v8s *)(dst + dw_cell<16>(c) + 16 * q) = v;
+        } else {
+            v4s v = {0, 0, 0, 0};
+            if (in) v = *(const v4s *)(src + cell * 4);
+            *(v4s *)(dst + dw_cell<4>(c)) = v;
+        }
     }
 }
 
-// Weight gradient dW[t][co][ci] = sum over cells of dout[cell][co] in[cell + off(t)][ci]
-// and bias gradient db[co] = sum of dout[cell][co], on 16x16x16 MFMA with
-// M = co, N = ci, K = the 16 cells of a tile. The workgroups come in threes
-// per slot, one for each dz, so a workgroup keeps the nine tap tiles of its
-// dz plane (not all 27), which leaves room for more wavefronts per SIMD. A
-// workgroup of DW_BY wavefronts takes blocks of 16 x DW_BY x 1 cells (one
-// y-line per wavefront), stages the inputs of its plane with the x and y
-// halo in LDS, and each wavefront accumulates its line's nine tap products;
-// the B operands come from LDS, six cells per dy serving the three dx taps.
-// The three workgroups of a slot take the same blocks in the same order, so
-// each tap sums exactly as one workgroup with all 27 taps would. Each
-// workgroup sums its waves in wave order and writes its taps of the slot;
-// the slots are summed in slot order later.
-constexpr int DW_BY = 8;
+// The same staging in two halves: dw_load_row reads the units thread
+// `first` owns (at most K of them) into registers, dw_store_row writes them
+// to LDS, so the loads of the next plane can run under the current plane's
+// products.
+template <int C, int K>
+__device__ __forceinline__ void dw_load_row(v8s (&reg)[K], const bf16_t *__restrict__ src, int N, int Z, int Y, int X0,
+                                            int cells, int first, int stride)
+{
+    constexpr int UPC = C == 16 ? 2 : 1;
+    const bool row_in = Z >= 0 && Z < N && Y >= 0 && Y < N;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int u = first + k * stride;
+        const int c = u / UPC, q = u % UPC, X = X0 + c;
+        const bool in = row_in && u < cells * UPC && X >= 0 && X < N;
+        const long long cell = ((long long)Z * N + Y) * N + X;
+        v8s v = {0, 0, 0, 0, 0, 0, 0, 0};
+        if constexpr (C == 16) {
+            if (in) v = *(const v8s *)(src + cell * 16 + 8 * q);
+        } else {
+            if (in) {
+                const v4s w = *(const v4s *)(src + cell * 4);
+                v[0] = w[0]; v[1] = w[1]; v[2] = w[2]; v[3] = w[3];
+            }
+        }
+        reg[k] = v;
+    }
+}
+
+template <int C, int K>
+__device__ __forceinline__ void dw_store_row(unsigned char *dst, const v8s (&reg)[K], int cells, int first, int stride)
+{
+    constexpr int UPC = C == 16 ? 2 : 1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int u = first + k * stride;
+        if (u >= cells * UPC) break;
+        const int c = u / UPC, q = u % UPC;
+        if constexpr (C == 16) {
+            *(v8s *)(dst + dw_cell<16>(c) + 16 * q) = reg[k];
+        } else {
+            *(v4s *)(dst + dw_cell<4>(c)) = (v4s){reg[k][0], reg[k][1], reg[k][2], reg[k][3]};
+        }
+    }
+}
 
 template <int CIN, int COUT>
-__global__ void __launch_bounds__(64 * DW_BY) k_lp_conv_dw(int nb, int N, const bf16_t *__restrict__ in,
-                                                          const bf16_t *__restrict__ dout, float *__restrict__ pw,
-                                                          float *__restrict__ pb)
+__global__ void __launch_bounds__(192) k_lp_conv_dw(int nb, int N, const bf16_t *__restrict__ in,
+                                                    const bf16_t *__restrict__ dout, float *__restrict__ pw,
+                                                    float *__restrict__ pb)
 {
-    constexpr int HY = DW_BY + 2, P = halo_pitch(CONV_HX * HY);
-    __shared__ float sw[9][16][16];
-    __shared__ float sbl[DW_BY][4][16]; // [wave][lane group][co]
-    __shared__ __attribute__((aligned(16))) bf16_t tile[CIN / 4 * P * 4];
-    const int lane = threadIdx.x & 63, g = lane >> 4, m = lane & 15;
-    const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
-    const int dzi = blockIdx.x % 3, slot = blockIdx.x / 3, nslots = gridDim.x / 3; // taps 9 dzi .. 9 dzi + 8
-    const int tiles_x = (N + CONV_BX - 1) / CONV_BX, tiles_y = (N + DW_BY - 1) / DW_BY;
-    const long long nblocks = (long long)nb * N * tiles_y * tiles_x;
+    constexpr int RB = dw_row_bytes<CIN>(DW_XC), DB = dw_row_bytes<COUT>(DW_SEG);
+    __shared__ __attribute__((aligned(16))) unsigned char ring[3][3][RB]; // [plane slot][dy][row]
+    __shared__ __attribute__((aligned(16))) unsigned char drow[DB];
+    const int lane = threadIdx.x & 63, kb = lane >> 4, c16 = lane & 15;
+    const int dzi = threadIdx.x >> 6;
+    const int segs = (N + DW_SEG - 1) / DW_SEG, runs = (N + DW_ZR - 1) / DW_ZR;
+    const long long items = (long long)nb * runs * N * segs;
     const long long N3 = (long long)N * N * N;
     v4f acc[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    for (long long blk = slot; blk < nblocks; blk += nslots) { // workgroup-uniform
-        const int tx = (int)(blk % tiles_x);
-        long long r = blk / tiles_x;
-        const int ty = (int)(r % tiles_y);
-        r /= tiles_y;
-        const int z = (int)(r % N);
-        const long long b = r / N;
-        const int x0 = tx * CONV_BX, y0 = ty * DW_BY;
-        __syncthreads(); // the previous block's readers are done
-        stage_halo<CIN, DW_BY, 1>(tile, in + b * N3 * CIN, N, x0, y0, z + dzi - 1);
-        __syncthreads();
-        const int y = y0 + wave;
-        if (y >= N) continue; // wavefront-uniform; the loop's barrier comes first in the next block
-        // A[m = co][k = cell 4g + j]
-        v4s a = {0, 0, 0, 0};
+    for (long long it = blockIdx.x; it < items; it += gridDim.x) { // workgroup-uniform
+        const int seg = (int)(it % segs);
+        long long r = it / segs;
+        const int y = (int)(r % N);
+        r /= N;
+        const int zr = (int)(r % runs);
+        const long long b = r / runs;
+        const int x0 = seg * DW_SEG;
+        const bf16_t *__restrict__ Db = dout + b * N3 * COUT;
+        const bf16_t *__restrict__ Ib = in + b * N3 * CIN;
+        const int z0 = zr * DW_ZR, z1 = min(z0 + DW_ZR, N);
+        __syncthreads(); // the previous item's readers are done
+        for (int p = z0 - 1; p <= z0; ++p)
+            for (int dy = 0; dy < 3; ++dy)
+                dw_stage_row<CIN>(ring[(p + 3) % 3][dy], Ib, N, p, y + dy - 1, x0 - 1, DW_XC, threadIdx.x, 192);
+        // registers for the next plane's input rows and dout row (loaded one plane ahead)
+        constexpr int KI = (DW_XC * (CIN == 16 ? 2 : 1) + 191) / 192, KD = (DW_SEG * (COUT == 16 ? 2 : 1) + 191) / 192;
+        v8s ri[3][KI], rd[KD];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int x = x0 + 4 * g + j;
-            if (m < COUT && x < N) {
-                const bf16_t h = dout[(b * N3 + ((long long)z * N + y) * N + x) * COUT + m];
-                a[j] = (short)h;
-                bsum += bf16_to_f32(h);
+        for (int dy = 0; dy < 3; ++dy) dw_load_row<CIN, KI>(ri[dy], Ib, N, z0 + 1, y + dy - 1, x0 - 1, DW_XC, threadIdx.x, 192);
+        dw_load_row<COUT, KD>(rd, Db, N, z0, y, x0, DW_SEG, threadIdx.x, 192);
+        for (int z = z0; z < z1; ++z) {
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy) dw_store_row<CIN, KI>(ring[(z + 4) % 3][dy], ri[dy], DW_XC, threadIdx.x, 192);
+            dw_store_row<COUT, KD>(drow, rd, DW_SEG, threadIdx.x, 192);
+            if (z + 1 < z1) {
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+                    dw_load_row<CIN, KI>(ri[dy], Ib, N, z + 2, y + dy - 1, x0 - 1, DW_XC, threadIdx.x, 192);
+                dw_load_row<COUT, KD>(rd, Db, N, z + 1, y, x0, DW_SEG, threadIdx.x, 192);
             }
-        }
-        // B[k = cell 4g + j][n = ci] = in[cell + off(t)][ci]; columns past the
-        // row end meet zero A entries, so their (finite) values do not matter
+            __syncthreads();
+            // A: dout at cells 8 kb + j of channel c16
+            v8s a = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (c16 < COUT) {
 #pragma unroll
-        for (int dy3 = 0; dy3 < 3; ++dy3) {
-            short v[6] = {0, 0, 0, 0, 0, 0};
-            if (m < CIN) {
-                const int row = (wave + dy3) * CONV_HX + 4 * g;
-#pragma unroll
-                for (int i = 0; i < 6; ++i) v[i] = (short)tile[((m >> 2) * P + row + i) * 4 + (m & 3)];
+                for (int j = 0; j < 8; ++j) a[j] = *(const short *)(drow + dw_cell<COUT>(8 * kb + j) + 2 * c16);
             }
+            if (dzi == 1) {
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const v4s bv = {v[dx], v[dx + 1], v[dx + 2], v[dx + 3]};
-                acc[dy3 * 3 + dx] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bv, acc[dy3 * 3 + dx], 0, 0, 0);
+                for (int j = 0; j < 8; ++j) bsum += bf16_to_f32((bf16_t)a[j]);
             }
-        }
-    }
-    // workgroup sum in wave order; lane l holds dW[9 dzi + t][4g + j][l % 16]
-    sbl[wave][g][m] = bsum;
-    for (int w = 0; w < waves; ++w) {
-        if (wave == w) {
+            const v8bf av = __builtin_bit_cast(v8bf, a);
+            const unsigned char(*pl)[RB] = ring[(z + dzi + 2) % 3]; // plane z + dz
 #pragma unroll
-            for (int t = 0; t < 9; ++t)
+            for (int dyi = 0; dyi < 3; ++dyi) {
+                // staged cells 8 kb .. 8 kb + 9 = x - 1 .. x + 8 of channel c16
+                short v[10];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    float &dst = sw[t][4 * g + j][m];
-                    dst = (w == 0) ? acc[t][j] : dst + acc[t][j];
+                for (int m = 0; m < 10; ++m)
+                    v[m] = c16 < CIN ? *(const short *)(pl[dyi] + dw_cell<CIN>(8 * kb + m) + 2 * c16) : (short)0;
+#pragma unroll
+                for (int dxi = 0; dxi < 3; ++dxi) {
+                    v8s bq;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) bq[j] = v[j + dxi];
+                    acc[3 * dyi + dxi] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(v8bf, bq),
+                                                                                acc[3 * dyi + dxi], 0, 0, 0);
                 }
+            }
+            __syncthreads(); // readers done before the next plane is staged
         }
-        __syncthreads();
     }
-    for (int e = threadIdx.x; e < 9 * 256; e += blockDim.x)
-        pw[((long long)slot * LP_TAPS + 9 * dzi) * 256 + e] = (&sw[0][0][0])[e];
-    if (dzi == 0 && threadIdx.x < 16) {
-        float t = 0.f;
-        for (int w = 0; w < waves; ++w)
-            for (int gg = 0; gg < 4; ++gg) t += sbl[w][gg][threadIdx.x];
-        pb[slot * 16 + threadIdx.x] = t;
+    // lane l holds dW[9 dzi + t][co = 4(l/16) + j][ci = l%16]
+    float *__restrict__ dst = pw + ((long long)blockIdx.x * LP_TAPS + 9 * dzi) * 256;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) dst[(t * 16 + 4 * kb + j) * 16 + c16] = acc[t][j];
+    if (dzi == 1) {
+        // lane (co, kb) holds the bias partial of cells 8 kb .. 8 kb + 7: sum over kb in order
+        const float p1 = __shfl(bsum, c16 + 16, 64), p2 = __shfl(bsum, c16 + 32, 64), p3 = __shfl(bsum, c16 + 48, 64);
+        const float tot = ((bsum + p1) + p2) + p3;
+        if (kb == 0) pb[blockIdx.x * 16 + c16] = tot;
     }
 }
 
-// Gradient of one layer from the slots, summed in slot order: weights in the
-// layer's layout [27][cout][cin] from the padded [27][16][16] partials, then
-// the cout bias entries.
-__global__ void k_lp_reduce(int nslots, int cout, int cin, const float *__restrict__ pw, const float *__restrict__ pb,
-                            float *__restrict__ gw, float *__restrict__ gb)
+// Gradient of one layer from the slots in a fixed order: thread group g of
+// an element sums the slots g, g + 16, ... in increasing order, then the 16
+// group sums are added in group order. Weights in the [tap][out][in] layout
+// of the parameters (the slots hold [tap][16][16]), then the bias.
+__global__ void __launch_bounds__(256) k_lp_reduce(int nslots, int cout, int cin, const float *__restrict__ pw,
+                                                   const float *__restrict__ pb, float *__restrict__ gw,
+                                                   float *__restrict__ gb)
 {
+    __shared__ float part[16][17];
     const int nw = LP_TAPS * cout * cin;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nw + cout; i += gridDim.x * blockDim.x) {
-        float s = 0.f;
-        if (i < nw) {
-            const int t = i / (cout * cin), o = (i / cin) % cout, c = i % cin;
-            const int src = (t * 16 + o) * 16 + c;
-            // the loads run ahead of the adds, which keep the slot order
-#pragma unroll 16
-            for (int k = 0; k < nslots; ++k) s += pw[(long long)k * LP_TAPS * 256 + src];
-            gw[i] = s;
-        } else {
-            const int o = i - nw;
-#pragma unroll 16
-            for (int k = 0; k < nslots; ++k) s += pb[k * 16 + o];
-            gb[o] = s;
-        }
+    const int e = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int i = blockIdx.x * 16 + e;
+    float s = 0.f;
+    if (i < nw) {
+        const int t = i / (cout * cin), o = (i / cin) % cout, c = i % cin;
+        const int src = (t * 16 + o) * 16 + c;
+#pragma unroll 8
+        for (int k = g; k < nslots; k += 16) s += pw[(long long)k * LP_TAPS * 256 + src];
+    } else if (i < nw + cout) {
+#pragma unroll 8
+        for (int k = g; k < nslots; k += 16) s += pb[k * 16 + (i - nw)];
+    }
+    part[g][e] = s;
+    __syncthreads();
+    if (g == 0 && i < nw + cout) {
+        float tot = 0.f;
+        for (int q = 0; q < 16; ++q) tot += part[q][e];
+        if (i < nw) gw[i] = tot;
+        else gb[i - nw] = tot;
     }
 }
 
-// Forward weights [27][16][CIN] (outputs padded to 16 with zeros) and the
-// adjoint weights of layers 2 and 3: wT[26 - t][ci][co] = W[t][co][ci].
 __global__ void k_lp_prep(const float *__restrict__ p, bf16_t *w1, bf16_t *w2, bf16_t *w3, bf16_t *w2t, bf16_t *w3t)
 {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -406,8 +478,7 @@ hipError_t launch_lp_conv(int cin, int cout, int epi, int nb, int N, const bf16_
 hipError_t launch_lp_conv_dw(int cin, int cout, int nb, int N, const bf16_t *in, const bf16_t *dout, float *pw,
                              float *pb, int grid, hipStream_t s)
 {
-    const int block = 64 * DW_BY;
-    grid *= 3; // one workgroup per slot and dz
+    const int block = 192; // one wavefront per dz
     if (cin == 16 && cout == 4)
         k_lp_conv_dw<16, 4><<<grid, block, 0, s>>>(nb, N, in, dout, pw, pb);
     else if (cin == 16 && cout == 16)
@@ -423,7 +494,7 @@ hipError_t launch_lp_reduce(int nslots, int cout, int cin, const float *pw, cons
                             hipStream_t s)
 {
     const int len = LP_TAPS * cout * cin + cout;
-    k_lp_reduce<<<(len + 255) / 256, 256, 0, s>>>(nslots, cout, cin, pw, pb, gw, gb);
+    k_lp_reduce<<<(len + 15) / 16, 256, 0, s>>>(nslots, cout, cin, pw, pb, gw, gb);
     return hipGetLastError();
 }
 
