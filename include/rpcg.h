@@ -413,8 +413,10 @@ int64_t rpcg_lp_pattern_nnz(int32_t N);
 int rpcg_lp_pattern(int32_t N, int32_t *g_row_ptr, int32_t *g_col, int32_t *gt_row_ptr, int32_t *gt_col);
 
 /* A network for systems on N^3 grids, batches of up to max_batch systems
- * (device workspace of roughly 200 bytes per cell and system). Parameters
- * start at zero; set them with rpcg_lp_set_params. */
+ * (device workspace of roughly 230 bytes per cell and system, plus 32 nu
+ * bytes per cell and system for the loss vectors, allocated by the first
+ * loss or training call with nu vectors). Parameters start at zero; set
+ * them with rpcg_lp_set_params. Calls on one network must not overlap. */
 int rpcg_lp_create(rpcg_ctx *ctx, int32_t N, int32_t max_batch, rpcg_lpnet **out /* host */);
 void rpcg_lp_destroy(rpcg_lpnet *net);
 /* params: host array of RPCG_LP_NPARAMS floats (layout above). Setting them

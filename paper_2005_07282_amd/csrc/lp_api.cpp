@@ -29,7 +29,7 @@ struct rpcg_lpnet {
     int step = 0;           // Adam steps taken
     static constexpr int DW_GRID = 1024; // slots of the weight-gradient sums (fixed: fixed order)
     Buffer params, grad, am, av, w1, w2, w3, w2t, w3t;
-    Buffer feat, s, h1, h2, o, do64, dob, d2, d1, pw, pb;
+    Buffer feat, s, h1, h2, o, dob, d2, d1, pw, pb;
     Buffer g_rp, g_col, gt_rp, gt_col, g_val, gt_val, scal;
     // loss over (instance, probe) pairs: v, y, r, q per pair, the exact-dot
     // slots and results, and the matrix / probe pointer table
@@ -136,10 +136,10 @@ int lp_ensure_dot_ws(rpcg_lpnet *L, int slots)
     return RPCG_OK;
 }
 
-// Loss and dL/do (binary64 into do64, bfloat16 into dob) over the cached
-// forward pass, for the nb x nu (instance, probe) pairs at once.
+// Loss and dL/do (bfloat16 into dob, binary64 into dout if given) over the
+// cached forward pass, for the nb x nu (instance, probe) pairs at once.
 int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *u, int nu, double eps, double *loss,
-                 hipStream_t s)
+                 double *dout, hipStream_t s)
 {
     const long long n = L->n;
     const long long P = (long long)nb * nu;
@@ -176,7 +176,7 @@ int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *
     RPCG_TRY(launch_lp_dots_merge((int)P, L->wu, L->wr, L->lws_slots, (double *)L->dots.p, flags, s));
     RPCG_TRY(launch_lp_mv(n, nb, nu, mGt, nullptr, r, q, s));                                      // q = G^T r
     RPCG_TRY(launch_lp_dodg_all(L->N, nb, nu, scale, (const double *)L->dots.p, (const float *)L->o.p,
-                                (const float *)L->s.p, mG, r, y, v, q, (double *)L->do64.p, (bf16_t *)L->dob.p,
+                                (const float *)L->s.p, mG, r, y, v, q, dout, (bf16_t *)L->dob.p,
                                 (double *)L->scal.p + 2, s));
     if (loss) {
         RPCG_TRY(hipMemcpyAsync(loss, (double *)L->scal.p + 2, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -224,7 +224,6 @@ int lp_create_body(rpcg_lpnet *L)
     RPCG_TRY(L->h1.ensure(sizeof(bf16_t) * 16 * cells));
     RPCG_TRY(L->h2.ensure(sizeof(bf16_t) * 16 * cells));
     RPCG_TRY(L->o.ensure(sizeof(float) * 4 * cells));
-    RPCG_TRY(L->do64.ensure(sizeof(double) * 4 * cells));
     RPCG_TRY(L->dob.ensure(sizeof(bf16_t) * 4 * cells));
     RPCG_TRY(L->d2.ensure(sizeof(bf16_t) * 16 * cells));
     RPCG_TRY(L->d1.ensure(sizeof(bf16_t) * 16 * cells));
@@ -272,7 +271,7 @@ void rpcg_lp_destroy(rpcg_lpnet *L)
     hipSetDevice(L->ctx->device);
     hipDeviceSynchronize();
     for (Buffer *b : {&L->params, &L->grad, &L->am, &L->av, &L->w1, &L->w2, &L->w3, &L->w2t, &L->w3t, &L->feat, &L->s,
-                      &L->h1, &L->h2, &L->o, &L->do64, &L->dob, &L->d2, &L->d1, &L->pw, &L->pb,
+                      &L->h1, &L->h2, &L->o, &L->dob, &L->d2, &L->d1, &L->pw, &L->pb,
                       &L->g_rp, &L->g_col, &L->gt_rp, &L->gt_col, &L->g_val, &L->gt_val, &L->scal, &L->lvec,
                       &L->lws, &L->dots, &L->tab})
         b->release();
@@ -360,9 +359,8 @@ int rpcg_lp_loss_grad(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const double
     hipStream_t s = (hipStream_t)stream;
     rc = lp_forward(L, nb, A, nullptr, s);
     if (rc != RPCG_OK) return rc;
-    rc = lp_loss_grad(L, nb, A, u, nu, eps, loss, s);
+    rc = lp_loss_grad(L, nb, A, u, nu, eps, loss, dout, s);
     if (rc != RPCG_OK) return rc;
-    if (dout) RPCG_TRY(hipMemcpyAsync(dout, L->do64.p, sizeof(double) * 4 * L->n * nb, hipMemcpyDeviceToDevice, s));
     RPCG_TRY(hipStreamSynchronize(s));
     return RPCG_OK;
 }
@@ -394,7 +392,7 @@ int rpcg_lp_train_step(rpcg_lpnet *L, int32_t nb, const rpcg_csr *A, const doubl
     hipStream_t s = (hipStream_t)stream;
     rc = lp_forward(L, nb, A, nullptr, s);
     if (rc != RPCG_OK) return rc;
-    rc = lp_loss_grad(L, nb, A, u, nu, eps, nullptr, s);
+    rc = lp_loss_grad(L, nb, A, u, nu, eps, nullptr, nullptr, s);
     if (rc != RPCG_OK) return rc;
     rc = lp_backward(L, nb, s);
     if (rc != RPCG_OK) return rc;

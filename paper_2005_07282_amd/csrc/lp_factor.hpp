@@ -50,7 +50,7 @@ hipError_t launch_lp_resid_dots(long long n, int nb, int nu, double eps, const L
 // dots[2p] = <u_p, u_p>, dots[2p + 1] = <r_p, r_p>, each correctly rounded.
 hipError_t launch_lp_dots_merge(int npairs, const DotWs &wu, const DotWs &wr, int stride, double *dots, int *flags,
                                 hipStream_t st);
-// dL/do of every instance (binary64 into do64, bfloat16 into dob) and the loss.
+// dL/do of every instance (bfloat16 into dob; binary64 into do64 unless null) and the loss.
 hipError_t launch_lp_dodg_all(int N, int nb, int nu, double scale, const double *dots, const float *o, const float *s,
                               const LpMat *gm, const double *r, const double *y, const double *v, const double *q,
                               double *do64, bf16_t *dob, double *loss, hipStream_t st);

@@ -18,6 +18,7 @@ namespace rpcg {
 
 constexpr int LPL_BLOCK = 256;
 constexpr int LPL_ROWCAP = 8; // rows up to this length are held in registers across the nu vectors
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 // y_p = M_k x_p for p = k nu + m, m < nu (grid.y = k). x_p from the pointer
 // table xtab when given, else xbase + p n; y_p = ybase + p n. Each row is an
@@ -60,24 +61,53 @@ __global__ void __launch_bounds__(LPL_BLOCK) k_lp_mv(long long n, int nu, const 
     }
 }
 
-// r_p = (G_k y_p + eps v_p) - u_p and the exact-dot partials of <u_p, u_p>
-// and <r_p, r_p> into slots p chunks + blockIdx.x (grid: chunks x pairs).
+// r_p = (G_k y_p + eps v_p) - u_p for the nu pairs of instance k =
+// blockIdx.y (a row of G is read once for all of them).
+__global__ void __launch_bounds__(LPL_BLOCK) k_lp_resid(long long n, int nu, double eps,
+                                                        const LpMat *__restrict__ gm,
+                                                        const double *const *__restrict__ utab,
+                                                        const double *__restrict__ ybase,
+                                                        const double *__restrict__ vbase, double *__restrict__ rbase)
+{
+    const int k = blockIdx.y;
+    const LpMat G = gm[k];
+    for (long long i = (long long)blockIdx.x * LPL_BLOCK + threadIdx.x; i < n;
+         i += (long long)gridDim.x * LPL_BLOCK) {
+        const int b = G.rp[i], len = G.rp[i + 1] - b;
+        double a[LPL_ROWCAP];
+        int c[LPL_ROWCAP];
+#pragma unroll
+        for (int j = 0; j < LPL_ROWCAP; ++j) {
+            a[j] = j < len ? G.val[b + j] : 0.0;
+            c[j] = j < len ? G.col[b + j] : 0;
+        }
+        for (int m = 0; m < nu; ++m) {
+            const long long p = (long long)k * nu + m;
+            const double *__restrict__ y = ybase + p * n;
+            double w = 0.0;
+            if (len <= LPL_ROWCAP) {
+#pragma unroll
+                for (int j = 0; j < LPL_ROWCAP; ++j)
+                    if (j < len) w = __builtin_fma(a[j], y[c[j]], w);
+            } else {
+                for (int j = 0; j < len; ++j) w = __builtin_fma(G.val[b + j], y[G.col[b + j]], w);
+            }
+            rbase[p * n + i] = (w + eps * vbase[p * n + i]) - utab[p][i];
+        }
+    }
+}
+
+// The exact-dot partials of <u_p, u_p> and <r_p, r_p> into slots p chunks +
+// blockIdx.x (grid: chunks x pairs).
 template <int P>
-__global__ void __launch_bounds__(LPL_BLOCK) k_lp_resid_dots(long long n, int nu, double eps,
-                                                             const LpMat *__restrict__ gm,
-                                                             const double *const *__restrict__ utab,
-                                                             const double *__restrict__ ybase,
-                                                             const double *__restrict__ vbase,
-                                                             double *__restrict__ rbase, SlotView su, SlotView sr,
-                                                             int *flags)
+__global__ void __launch_bounds__(LPL_BLOCK) k_lp_dots(long long n, const double *const *__restrict__ utab,
+                                                       const double *__restrict__ rbase, SlotView su, SlotView sr,
+                                                       int *flags)
 {
     __shared__ RedShared sh;
-    const int p = blockIdx.y, k = p / nu;
-    const LpMat G = gm[k];
+    const int p = blockIdx.y;
     const double *__restrict__ u = utab[p];
-    const double *__restrict__ y = ybase + (long long)p * n;
-    const double *__restrict__ v = vbase + (long long)p * n;
-    double *__restrict__ r = rbase + (long long)p * n;
+    const double *__restrict__ r = rbase + (long long)p * n;
     zero_acc(sh.acc[0]);
     zero_acc(sh.acc[1]);
     __syncthreads();
@@ -86,11 +116,7 @@ __global__ void __launch_bounds__(LPL_BLOCK) k_lp_resid_dots(long long n, int nu
     Lr.init();
     for (long long i = (long long)blockIdx.x * LPL_BLOCK + threadIdx.x; i < n;
          i += (long long)gridDim.x * LPL_BLOCK) {
-        double w = 0.0;
-        for (int j = G.rp[i]; j < G.rp[i + 1]; ++j) w = __builtin_fma(G.val[j], y[G.col[j]], w);
-        const double ui = u[i];
-        const double ri = (w + eps * v[i]) - ui;
-        r[i] = ri;
+        const double ui = u[i], ri = r[i];
         Lu.add(ui, ui, sh.acc[0], true, true);
         Lr.add(ri, ri, sh.acc[1], true, true);
     }
@@ -118,8 +144,8 @@ __global__ void __launch_bounds__(LPL_BLOCK) k_lp_dots_merge(int chunks, SlotVie
 }
 
 // dL/do of instance k = blockIdx.y (summed over its nu pairs in order m = 0,
-// 1, ...), written in binary64 to do64 and rounded to bfloat16 into dob; the
-// loss (pairs in order) by one thread.
+// 1, ...), rounded to bfloat16 into dob and, if do64 is given, written in
+// binary64 there; the loss (pairs in order) by one thread.
 __global__ void __launch_bounds__(LPL_BLOCK) k_lp_dodg(int N, int nu, int npairs, double scale,
                                                        const double *__restrict__ dots, const float *__restrict__ o,
                                                        const float *__restrict__ s, const LpMat *__restrict__ gm,
@@ -139,7 +165,7 @@ __global__ void __launch_bounds__(LPL_BLOCK) k_lp_dodg(int N, int nu, int npairs
     const LpMat G = gm[k];
     o += (long long)k * n * 4;
     s += (long long)k * n;
-    do64 += (long long)k * n * 4;
+    if (do64) do64 += (long long)k * n * 4;
     dob += (long long)k * n * 4;
     for (long long i = (long long)blockIdx.x * LPL_BLOCK + threadIdx.x; i < n;
          i += (long long)gridDim.x * LPL_BLOCK) {
@@ -162,11 +188,9 @@ __global__ void __launch_bounds__(LPL_BLOCK) k_lp_dodg(int N, int nu, int npairs
             }
         }
         if (!(fabsf(o[i * 4]) < LP_OCLAMP)) g[0] = 0.0; // clamped: no gradient through the diagonal output
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            do64[i * 4 + d] = g[d];
-            dob[i * 4 + d] = f32_to_bf16((float)g[d]);
-        }
+        if (do64) *(v4d *)(do64 + i * 4) = (v4d){g[0], g[1], g[2], g[3]};
+        *(v4s *)(dob + i * 4) = (v4s){(short)f32_to_bf16((float)g[0]), (short)f32_to_bf16((float)g[1]),
+                                      (short)f32_to_bf16((float)g[2]), (short)f32_to_bf16((float)g[3])};
     }
 }
 
@@ -185,8 +209,9 @@ hipError_t launch_lp_resid_dots(long long n, int nb, int nu, double eps, const L
                                 int stride, int *flags, hipStream_t st)
 {
     SlotView su{wu, stride}, sr{wr, stride};
-    hipLaunchKernelGGL(k_lp_resid_dots<LP_DOT_P>, dim3(LP_DOT_CHUNKS, nb * nu), dim3(LPL_BLOCK), 0, st, n, nu, eps,
-                       gm, utab, y, v, r, su, sr, flags);
+    hipLaunchKernelGGL(k_lp_resid, dim3(lpl_grid(n), nb), dim3(LPL_BLOCK), 0, st, n, nu, eps, gm, utab, y, v, r);
+    hipLaunchKernelGGL(k_lp_dots<LP_DOT_P>, dim3(LP_DOT_CHUNKS, nb * nu), dim3(LPL_BLOCK), 0, st, n, utab, r, su, sr,
+                       flags);
     return hipGetLastError();
 }
 
