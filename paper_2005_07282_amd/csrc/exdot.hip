@@ -103,6 +103,9 @@ __global__ void k_acc_round(const long long *digits, double *out)
 // row inside the chunk, reading LDS. The accumulator stays in the row's
 // thread across chunks, so a row of any length is one sequential chain in
 // storage order, exactly as the definition reads.
+// The next chunk's values and columns are loaded under the current chunk's
+// chains and its x entries gathered right after them, so rows longer than a
+// chunk's share no longer leave the memory idle while their chains run.
 
 #ifndef RPCG_SPMV_R
 #define RPCG_SPMV_R 512
@@ -129,22 +132,32 @@ k_spmv_csr(int n, const int *__restrict__ rp, const int *__restrict__ col, const
         long long rs = b1, re = b1;
         if (i < r1) { rs = rp[i]; re = rp[i + 1]; }
         double acc = 0.0;
+        double a[PER], g[PER];
+        int c[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const long long k = b0 + j * R + t;
+            const bool in = k < b1;
+            a[j] = in ? __builtin_nontemporal_load(val + k) : 0.0;
+            c[j] = in ? __builtin_nontemporal_load(col + k) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) g[j] = x[c[j]];
         for (long long k0 = b0; k0 < b1; k0 += E) {
-            double a[PER], g[PER];
-            int c[PER];
-#pragma unroll
-            for (int j = 0; j < PER; ++j) {
-                const long long k = k0 + j * R + t;
-                const bool in = k < b1;
-                a[j] = in ? __builtin_nontemporal_load(val + k) : 0.0;
-                c[j] = in ? __builtin_nontemporal_load(col + k) : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < PER; ++j) g[j] = x[c[j]]; // c = 0 off the range: a valid index
             if (k0 != b0) __syncthreads(); // the previous chunk has been read
 #pragma unroll
             for (int j = 0; j < PER; ++j) st[j * R + t] = make_double2(a[j], g[j]);
             __syncthreads();
+            const long long k1 = k0 + E;
+            if (k1 < b1) { // the next chunk's values and columns, loaded under this chunk's chains
+#pragma unroll
+                for (int j = 0; j < PER; ++j) {
+                    const long long k = k1 + j * R + t;
+                    const bool in = k < b1;
+                    a[j] = in ? __builtin_nontemporal_load(val + k) : 0.0;
+                    c[j] = in ? __builtin_nontemporal_load(col + k) : 0;
+                }
+            }
             const int lo = (int)((rs > k0 ? rs : k0) - k0);
             const int hi = (int)((re < k0 + E ? re : k0 + E) - k0);
             int k = lo;
@@ -156,6 +169,10 @@ k_spmv_csr(int n, const int *__restrict__ rp, const int *__restrict__ col, const
                 acc = __builtin_fma(e3.x, e3.y, acc);
             }
             for (; k < hi; ++k) acc = __builtin_fma(st[k].x, st[k].y, acc);
+            if (k1 < b1) {
+#pragma unroll
+                for (int j = 0; j < PER; ++j) g[j] = x[c[j]];
+            }
         }
         if (i < r1) y[i] = acc;
         __syncthreads(); // the next block's first chunk overwrites st
