@@ -104,9 +104,10 @@ def test_backward_matches_oracle(R, net10):
 
 
 def test_forward_backward_ragged_blocks(R):
-    """N = 21 cuts the convolutions' blocks raggedly: one full and one
-    5-cell tile along x, y-blocks of 4 (forward) and 8 (weight gradient)
-    with remainders, and halos on every side."""
+    """N = 21 cuts the kernels' tiles raggedly: forward and adjoint passes
+    take one full and one 5-cell tile along x, y-groups of 4 lines with a
+    remainder and z-runs of 16 + 5 planes; the weight gradient one 32-cell
+    x-segment holding 21 cells; halos on every side."""
     N = 21
     net = R.LearnedPreconditioner(N, max_batch=2)
     net.set_params(params(3))
@@ -135,6 +136,56 @@ def test_forward_backward_ragged_blocks(R):
         print(f"N=21 gradient {name}: relative difference {rel:.2e}", flush=True)
         assert rel < 2e-2, name
         off += m
+
+
+def test_weight_gradient_two_segments(R):
+    """N = 37: the weight gradient's x-segments of 32 cells are one full and
+    one of 5 cells, so the staged x halo crosses a segment boundary."""
+    N = 37
+    net = R.LearnedPreconditioner(N, max_batch=1)
+    net.set_params(params(4))
+    A = systems(N, [33])[0]
+    mats = [R.CSR.from_host(A)]
+    rng = np.random.default_rng(11)
+    dout = rng.standard_normal((1, N ** 3, 4))
+    g = net.backward(mats, torch.from_numpy(dout).cuda()).cpu().numpy().astype(np.float64)
+    net.close()
+    p = params(4).astype(np.float64)
+    c = lpnet.forward(p, lpnet.features(A, N), bf16=True)
+    ref = lpnet.backward(c, dout[0].reshape(N, N, N, 4))
+    off = 0
+    for name, shape in lpnet.SHAPES:
+        m = int(np.prod(shape))
+        rel = np.linalg.norm(g[off:off + m] - ref[off:off + m]) / np.linalg.norm(ref[off:off + m])
+        print(f"N=37 gradient {name}: relative difference {rel:.2e}", flush=True)
+        assert rel < 2e-2, name
+        off += m
+
+
+def test_loss_grad_batch_above_16(R):
+    """18 systems x 3 vectors in one call (the matrix table holds more than
+    the 16 matrices one feature launch takes) give the per-system losses and
+    output gradients: the batch loss is their mean, each system's gradient
+    its own divided by the batch size (to rounding: the scale factors and
+    the order of the loss sum differ)."""
+    N = 6
+    nb, nu = 18, 3
+    net = R.LearnedPreconditioner(N, max_batch=nb)
+    net.set_params(params(5))
+    As = systems(N, list(range(60, 60 + nb)))
+    mats = [R.CSR.from_host(A) for A in As]
+    us = [[torch.from_numpy(uniform_pm1(500 + 7 * k + m, As[0].n)).cuda() for m in range(nu)] for k in range(nb)]
+    loss, dout = net.loss_grad(mats, us, eps=1e-6)
+    losses = []
+    for k in range(nb):
+        lk, dk = net.loss_grad([mats[k]], [us[k]], eps=1e-6)
+        losses.append(lk)
+        a, b = dout[k].cpu().numpy(), dk[0].cpu().numpy() / nb
+        assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b)), k
+    net.close()
+    ref = float(np.mean(losses))
+    print(f"batch loss {loss:.15g}, mean of per-system losses {ref:.15g}", flush=True)
+    assert abs(loss - ref) <= 1e-12 * abs(ref)
 
 
 def test_factor_independent_of_batch(R, net10):
