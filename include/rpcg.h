@@ -415,8 +415,9 @@ int rpcg_lp_pattern(int32_t N, int32_t *g_row_ptr, int32_t *g_col, int32_t *gt_r
 /* A network for systems on N^3 grids, batches of up to max_batch systems
  * (device workspace of roughly 230 bytes per cell and system, plus 32 nu
  * bytes per cell and system for the loss vectors, allocated by the first
- * loss or training call with nu vectors). Parameters start at zero; set
- * them with rpcg_lp_set_params. Calls on one network must not overlap. */
+ * loss or training call with nu vectors). max_batch <= 65535 and
+ * N^3 max_batch <= 2^30, else RPCG_ERR_INVALID. Parameters start at zero;
+ * set them with rpcg_lp_set_params. Calls on one network must not overlap. */
 int rpcg_lp_create(rpcg_ctx *ctx, int32_t N, int32_t max_batch, rpcg_lpnet **out /* host */);
 void rpcg_lp_destroy(rpcg_lpnet *net);
 /* params: host array of RPCG_LP_NPARAMS floats (layout above). Setting them
@@ -434,7 +435,8 @@ int rpcg_lp_factor(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, rpcg_csr *G, 
 /* Training loss (host, may be NULL) and its gradient with respect to the
  * outputs (device, binary64 [nb][N^3][4], may be NULL), averaged over the nb
  * systems and their nu vectors u (host array of nb * nu device pointers,
- * system-major). Waits for completion. */
+ * system-major; nb * nu <= 65535, else RPCG_ERR_INVALID). Waits for
+ * completion. */
 int rpcg_lp_loss_grad(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, const double *const *u, int32_t nu,
                       double eps, double *loss, double *dout, void *stream);
 /* Parameter gradient (device, float32 RPCG_LP_NPARAMS) for an output gradient

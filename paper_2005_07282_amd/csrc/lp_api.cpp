@@ -143,7 +143,7 @@ int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *
 {
     const long long n = L->n;
     const long long P = (long long)nb * nu;
-    if (P * LP_DOT_CHUNKS > (1ll << 30)) return RPCG_ERR_INVALID;
+    if (P > 65535) return RPCG_ERR_INVALID; // pairs index the second grid dimension
     RPCG_TRY(L->lvec.ensure(sizeof(double) * 4 * n * P));
     RPCG_TRY(L->dots.ensure(sizeof(double) * 2 * P));
     int rc = lp_ensure_dot_ws(L, (int)(P * LP_DOT_CHUNKS));
@@ -283,7 +283,8 @@ int rpcg_lp_create(rpcg_ctx *c, int32_t N, int32_t max_batch, rpcg_lpnet **out)
 {
     if (!out) return RPCG_ERR_INVALID;
     *out = nullptr;
-    if (!c || N < 2 || max_batch < 1 || (long long)N * N * N * max_batch > (1ll << 30)) return RPCG_ERR_INVALID;
+    if (!c || N < 2 || max_batch < 1 || max_batch > 65535 || (long long)N * N * N * max_batch > (1ll << 30))
+        return RPCG_ERR_INVALID;
     RPCG_TRY(hipSetDevice(c->device));
     rpcg_lpnet *L = new (std::nothrow) rpcg_lpnet();
     if (!L) return RPCG_ERR_OOM;

@@ -188,6 +188,22 @@ def test_loss_grad_batch_above_16(R):
     assert abs(loss - ref) <= 1e-12 * abs(ref)
 
 
+def test_lp_limits(R):
+    """Batches beyond what the kernels' grids index are rejected up front."""
+    with pytest.raises(R.RpcgError) as ei:
+        R.LearnedPreconditioner(2, max_batch=70000)
+    assert ei.value.status == R.ERR_INVALID
+    N = 4
+    net = R.LearnedPreconditioner(N, max_batch=2)
+    A = systems(N, [70])[0]
+    mats = [R.CSR.from_host(A)]
+    u = torch.from_numpy(uniform_pm1(3, A.n)).cuda()
+    with pytest.raises(R.RpcgError) as ei:
+        net.loss_grad(mats, [[u] * 65536])
+    assert ei.value.status == R.ERR_INVALID
+    net.close()
+
+
 def test_factor_independent_of_batch(R, net10):
     N = 10
     As = systems(N, [16, 17, 18])
