@@ -191,17 +191,17 @@ static int run_exdot(rpcg_ctx *c, int mode, int64_t n, const double *x, const do
     // 1024-thread workgroups; four per CU for the expansion modes, eight for
     // plain (measured at 2^28 elements: 5.2 / 3.8 TB/s exact on narrow / wide
     // data against 4.5 / 3.0 with 256-thread workgroups, eight per CU). The
-    // exact modes give a thread at least 64 elements where that still leaves
-    // a workgroup per CU: the workgroup's accumulator setup and partial and
-    // the lanes' overflow windows are then paid over more data (2^22 and
-    // 2^24 elements: 10-25% faster).
+    // exact modes give a thread at least 256 elements where that still
+    // leaves a workgroup per CU: the workgroup's accumulator setup and
+    // partial and the lanes' overflow windows are then paid over more data
+    // (2^22 to 2^26 elements: 5-25% faster; 2^28 keeps four per CU).
     LaunchCfg cfg = make_cfg(c, o, std::max<int64_t>(1, (n + 7) / 8), 1024, s);
     if (!o.grid_size) {
         cfg.grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 8ll * cfg.block - 1) / (8ll * cfg.block),
                                                                (mode == MODE_PLAIN ? 8ll : 4ll) * c->num_cus));
         if (mode != MODE_PLAIN)
             cfg.grid = (int)std::max<int64_t>(std::min<int64_t>(cfg.grid, c->num_cus),
-                                              std::min<int64_t>(cfg.grid, (n + 64ll * cfg.block - 1) / (64ll * cfg.block)));
+                                              std::min<int64_t>(cfg.grid, (n + 256ll * cfg.block - 1) / (256ll * cfg.block)));
     }
     int rc = ensure_ws(c, cfg.grid);
     if (rc != RPCG_OK) return rc;

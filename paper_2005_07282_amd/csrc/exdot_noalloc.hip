@@ -93,7 +93,7 @@ extern "C" int rpcg_exdot_noalloc(rpcg_mode mode_in, int64_t n, const double *x,
                                                                          (mode == MODE_PLAIN ? 8ll : 4ll) * cus));
     if (!o.grid_size && mode != MODE_PLAIN)
         cfg.grid = (int)std::max<int64_t>(std::min<int64_t>(cfg.grid, cus),
-                                          std::min<int64_t>(cfg.grid, (n + 64ll * cfg.block - 1) / (64ll * cfg.block)));
+                                          std::min<int64_t>(cfg.grid, (n + 256ll * cfg.block - 1) / (256ll * cfg.block)));
     cfg.grid = std::min(cfg.grid, NA_GROUPS);
     cfg.early_exit = o.early_exit != 0;
     cfg.fpe_size = o.fpe_size;
