@@ -145,8 +145,8 @@ int rpcg_create(rpcg_ctx **out, int device)
 void rpcg_destroy(rpcg_ctx *c)
 {
     if (!c) return;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(c->device); // teardown reports nothing
+    (void)hipDeviceSynchronize();
     c->ws_mem.release();
     c->scalars.release();
     c->sell_off.release();
@@ -159,12 +159,12 @@ void rpcg_destroy(rpcg_ctx *c)
     c->vecs.release();
     c->ir_vecs.release();
     c->beta_hist.release();
-    if (c->host_done) hipHostFree(c->host_done);
-    if (c->host_state) hipHostFree(c->host_state);
-    if (c->host_ir) hipHostFree(c->host_ir);
-    for (hipEvent_t e : c->events) hipEventDestroy(e);
-    for (hipEvent_t e : c->ir_events) hipEventDestroy(e);
-    for (hipEvent_t e : c->poll_ev) if (e) hipEventDestroy(e);
+    if (c->host_done) (void)hipHostFree(c->host_done);
+    if (c->host_state) (void)hipHostFree(c->host_state);
+    if (c->host_ir) (void)hipHostFree(c->host_ir);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->ir_events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->poll_ev) if (e) (void)hipEventDestroy(e);
     delete c;
 }
 

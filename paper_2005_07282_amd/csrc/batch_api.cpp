@@ -97,8 +97,8 @@ int ensure_batch_ws(rpcg_batch *B, int groups)
 
 void drop_graph(rpcg_batch *B)
 {
-    if (B->exec) hipGraphExecDestroy(B->exec);
-    if (B->graph) hipGraphDestroy(B->graph);
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
     B->exec = nullptr;
     B->graph = nullptr;
     B->graph_valid = false;
@@ -228,7 +228,7 @@ int build_schedule(rpcg_batch *B)
     if (need > B->stage_bytes) {
         RPCG_TRY(hipStreamSynchronize(B->gs));
         for (char *&p : B->stage) {
-            if (p) hipHostFree(p);
+            if (p) (void)hipHostFree(p);
             p = nullptr;
         }
         B->stage_bytes = 0;
@@ -313,7 +313,7 @@ int capture_graph(rpcg_batch *B, bool with_hist)
                                      B->ws_cap, cfg);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(B->gs, &g);
-    if (err != hipSuccess) { if (g) hipGraphDestroy(g); return hip_status(err); }
+    if (err != hipSuccess) { if (g) (void)hipGraphDestroy(g); return hip_status(err); }
     RPCG_TRY(e2);
     B->graph = g;
     RPCG_TRY(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
@@ -342,20 +342,20 @@ extern "C" {
 void rpcg_batch_destroy(rpcg_batch *B)
 {
     if (!B) return;
-    hipSetDevice(B->ctx->device);
-    if (B->gs) hipStreamSynchronize(B->gs);
+    (void)hipSetDevice(B->ctx->device); // teardown reports nothing
+    if (B->gs) (void)hipStreamSynchronize(B->gs);
     drop_graph(B);
     for (Buffer *b : {&B->off, &B->val, &B->col, &B->cfirst, &B->len8, &B->vecs, &B->st, &B->hist_ptrs, &B->active,
                       &B->dsys, &B->druns, &B->dwg, &B->ws_mem})
         b->release();
     for (hipEvent_t e : {B->ev_in, B->ev_out, B->poll_ev[0], B->poll_ev[1], B->t_ev[0], B->t_ev[1], B->stage_ev[0],
                          B->stage_ev[1]})
-        if (e) hipEventDestroy(e);
-    if (B->host_active) hipHostFree(B->host_active);
-    if (B->host_poll_st) hipHostFree(B->host_poll_st);
+        if (e) (void)hipEventDestroy(e);
+    if (B->host_active) (void)hipHostFree(B->host_active);
+    if (B->host_poll_st) (void)hipHostFree(B->host_poll_st);
     for (char *p : B->stage)
-        if (p) hipHostFree(p);
-    if (B->gs) hipStreamDestroy(B->gs);
+        if (p) (void)hipHostFree(p);
+    if (B->gs) (void)hipStreamDestroy(B->gs);
     delete B;
 }
 

@@ -27,7 +27,7 @@ struct Buffer {
     }
     void release()
     {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p); // teardown: nothing to report to
         p = nullptr;
         bytes = 0;
     }

@@ -268,14 +268,15 @@ int rpcg_lp_pattern(int32_t N, int32_t *g_row_ptr, int32_t *g_col, int32_t *gt_r
 void rpcg_lp_destroy(rpcg_lpnet *L)
 {
     if (!L) return;
-    hipSetDevice(L->ctx->device);
-    hipDeviceSynchronize();
+    // teardown reports nothing: release what can be released
+    (void)hipSetDevice(L->ctx->device);
+    (void)hipDeviceSynchronize();
     for (Buffer *b : {&L->params, &L->grad, &L->am, &L->av, &L->w1, &L->w2, &L->w3, &L->w2t, &L->w3t, &L->feat, &L->s,
                       &L->h1, &L->h2, &L->o, &L->dob, &L->d2, &L->d1, &L->pw, &L->pb,
                       &L->g_rp, &L->g_col, &L->gt_rp, &L->gt_col, &L->g_val, &L->gt_val, &L->scal, &L->lvec,
                       &L->lws, &L->dots, &L->tab})
         b->release();
-    if (L->bad) hipHostFree(L->bad);
+    if (L->bad) (void)hipHostFree(L->bad);
     delete L;
 }
 
