@@ -425,9 +425,11 @@ void rpcg_lp_destroy(rpcg_lpnet *net);
 int rpcg_lp_set_params(rpcg_lpnet *net, const float *params);
 int rpcg_lp_get_params(rpcg_lpnet *net, float *params);
 
-/* Network outputs o (device, float32 [nb][N^3][4]) for nb systems A (host
- * array of device CSR 7-point operators on the N^3 grid). RPCG_ERR_NOT_SPD if
- * a diagonal entry is not positive. */
+/* Network outputs o (device, float32 [nb][N^3][4]; may be NULL to run the
+ * pass only) for nb systems A (host array of device CSR 7-point operators on
+ * the N^3 grid). RPCG_ERR_NOT_SPD if a diagonal entry is missing or not
+ * positive (o is then undefined). Waits for completion (the diagonal check).
+ * Every call below runs this forward pass on its own systems first. */
 int rpcg_lp_forward(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, float *o, void *stream);
 /* G and G^T of nb systems into caller-allocated device CSR (structure from
  * rpcg_lp_pattern, values written as binary64). Waits for completion. */
@@ -440,7 +442,8 @@ int rpcg_lp_factor(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, rpcg_csr *G, 
 int rpcg_lp_loss_grad(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, const double *const *u, int32_t nu,
                       double eps, double *loss, double *dout, void *stream);
 /* Parameter gradient (device, float32 RPCG_LP_NPARAMS) for an output gradient
- * dout (device, binary64 [nb][N^3][4], rounded to bfloat16 first). */
+ * dout (device, binary64 [nb][N^3][4], rounded to bfloat16 first), summed in
+ * a fixed order (bit-reproducible). Waits for completion. */
 int rpcg_lp_backward(rpcg_lpnet *net, int32_t nb, const rpcg_csr *A, const double *dout, float *grad,
                      void *stream);
 /* One optimisation step (Adam, beta1 0.9, beta2 0.999, epsilon 1e-8, step
