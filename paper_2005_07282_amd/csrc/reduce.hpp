@@ -72,9 +72,12 @@ __device__ __forceinline__ void acc_add_lds(long long *acc, double v, int &flags
 }
 
 // Exact product x y added to the long accumulator as one integer: the
-// 106-bit product of the significands, shifted onto the accumulator's word
-// grid, in up to five 32-bit chunks. It is the same exact value as RN(x y)
-// plus its TwoProd error, added with one atomic fewer on average. The caller
+// 106-bit product of the significands, negated once as a 128-bit two's
+// complement value if the signs differ, shifted onto the accumulator's word
+// grid and added as four unsigned 32-bit digits and the signed rest above
+// them (five adds at most, each below 2^32 in magnitude). It is the same
+// exact value as RN(x y) plus its TwoProd error, added with one atomic
+// fewer on average. The caller
 // ensures RN(x y) is finite and at least 2^-969 in magnitude: then x and y
 // are finite and nonzero, TwoProd is exact, and the product's bits lie
 // between the accumulator's lowest weight and its top word.
@@ -91,16 +94,24 @@ __device__ __forceinline__ void acc_add_product_lds(long long *acc, double x, do
     // x y = mx my 2^(ex + ey - 2150); off = offset of its last bit above 2^ACC_EXP0
     const int off = ex + ey - 2150 - ACC_EXP0;
     const int k = off >> 5, s = off & 31;
-    const unsigned long long lo = mx * my, hi = __umul64hi(mx, my); // hi < 2^42
+    unsigned long long lo = mx * my, hi = __umul64hi(mx, my); // hi < 2^42
+    // the signed product as a 128-bit two's complement value (hi now signed)
+    const bool neg = ((bx ^ by) >> 63) != 0;
+    if (neg) {
+        const unsigned long long nlo = 0ull - lo;
+        hi = ~hi + (lo == 0 ? 1ull : 0ull);
+        lo = nlo;
+    }
+    // shifted by s onto the word grid: 32-bit digits of the low 128 bits
+    // (unsigned) and the signed rest above them
     const unsigned long long w0 = lo << s;
     const unsigned long long w1 = (hi << s) | (s ? lo >> (64 - s) : 0ull);
-    const unsigned long long w2 = s ? hi >> (64 - s) : 0ull;
+    const long long w2 = s ? (long long)hi >> (64 - s) : ((long long)hi >> 63);
     const long long c[5] = {(long long)(w0 & 0xFFFFFFFFull), (long long)(w0 >> 32), (long long)(w1 & 0xFFFFFFFFull),
-                            (long long)(w1 >> 32), (long long)w2};
-    const bool neg = ((bx ^ by) >> 63) != 0;
+                            (long long)(w1 >> 32), w2};
 #pragma unroll
     for (int i = 0; i < 5; ++i)
-        if (c[i]) atomicAdd((unsigned long long *)&acc[k + i], (unsigned long long)(neg ? -c[i] : c[i]));
+        if (c[i]) atomicAdd((unsigned long long *)&acc[k + i], (unsigned long long)c[i]);
 }
 
 __device__ __forceinline__ bool product_in_integer_range(double r)
