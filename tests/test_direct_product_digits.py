@@ -1,0 +1,95 @@
+"""Host check of the digit split the exact dot's direct path uses for a
+product x y (Section 4.1: the product enters the long accumulator exactly).
+The device forms the 106-bit product of the significands, negates it once as
+a 128-bit two's complement value when the signs differ, shifts it onto the
+accumulator's 32-bit word grid and adds four unsigned 32-bit digits and the
+signed rest. This test replays that integer arithmetic with 64-bit
+wraparound and checks, against exact rationals, that the five adds sum to
+x y exactly, that each is below 2^32 in magnitude (the accumulator's
+headroom argument) and that the top word stays inside the 68 words."""
+
+import math
+import random
+import struct
+from fractions import Fraction
+
+M64 = (1 << 64) - 1
+ACC_EXP0 = -1088
+ACC_WORDS = 68
+
+
+def _bits(x):
+    return struct.unpack("<Q", struct.pack("<d", x))[0]
+
+
+def _sar64(v, n):
+    v = v - (1 << 64) if v >> 63 else v
+    return (v >> n) & M64
+
+
+def _digits(x, y):
+    bx, by = _bits(x), _bits(y)
+    ex, ey = (bx >> 52) & 0x7FF, (by >> 52) & 0x7FF
+    mx, my = bx & ((1 << 52) - 1), by & ((1 << 52) - 1)
+    if ex:
+        mx |= 1 << 52
+    else:
+        ex = 1
+    if ey:
+        my |= 1 << 52
+    else:
+        ey = 1
+    off = ex + ey - 2150 - ACC_EXP0
+    k, s = off >> 5, off & 31
+    p = mx * my
+    lo, hi = p & M64, p >> 64
+    if (bx ^ by) >> 63:
+        nlo = (0 - lo) & M64
+        hi = (~hi + (1 if lo == 0 else 0)) & M64
+        lo = nlo
+    w0 = (lo << s) & M64
+    w1 = ((hi << s) | ((lo >> (64 - s)) if s else 0)) & M64
+    w2 = _sar64(hi, 64 - s) if s else _sar64(hi, 63)
+    c = [w0 & 0xFFFFFFFF, w0 >> 32, w1 & 0xFFFFFFFF, w1 >> 32, w2]
+    return k, [v - (1 << 64) if v >> 63 else v for v in c]
+
+
+def _check(x, y):
+    k, c = _digits(x, y)
+    assert 0 <= k and k + 4 < ACC_WORDS, (x, y, k)
+    assert all(abs(v) < (1 << 32) for v in c), (x, y, c)
+    got = sum(Fraction(v) * Fraction(2) ** (32 * (k + i) + ACC_EXP0) for i, v in enumerate(c))
+    assert got == Fraction(x) * Fraction(y), (x, y)
+
+
+def _in_range(x, y):
+    r = x * y
+    return x != 0 and y != 0 and math.isfinite(r) and abs(r) >= 2.0 ** -969
+
+
+def test_random_products_all_exponents():
+    rng = random.Random(20)
+    n = 0
+    while n < 20000:
+        x = rng.choice((-1, 1)) * rng.random() * 2.0 ** rng.randint(-1074, 1023)
+        y = rng.choice((-1, 1)) * rng.random() * 2.0 ** rng.randint(-1074, 1023)
+        if _in_range(x, y):
+            _check(x, y)
+            n += 1
+
+
+def test_edge_products():
+    tiny = 5e-324
+    big = 1.7976931348623157e308
+    cases = [(tiny, 2.0 ** 1000), (-3 * tiny, 2.0 ** 1023), (big, 0.9999999999999999), (-big, 0.5),
+             (2.0 ** -500, -2.0 ** -469), (-1.0, -1.0), (1.0, -1.0), (-(2.0 ** 53 - 1), 2.0 ** 53 - 1)]
+    for x, y in cases:
+        assert _in_range(x, y)
+        _check(x, y)
+
+
+def test_every_shift_both_signs():
+    for s in range(64):
+        for sign in (1, -1):
+            _check(sign * (1 + 2.0 ** -52) * 2.0 ** (s - 10), 3.0 * 2.0 ** 7)
+            _check(sign * 2.0 ** (s - 40), -(2.0 - 2.0 ** -52))
