@@ -270,7 +270,7 @@ int rpcg_spmv(rpcg_ctx *c, const rpcg_csr *A, const double *x, double *y, void *
 {
     if (!c || !valid_csr(A) || (A->n > 0 && (!x || !y)) || (A->n > 0 && x == y)) return RPCG_ERR_INVALID;
     RPCG_TRY(hipSetDevice(c->device));
-    RPCG_TRY(launch_spmv_csr(A->n, A->row_ptr, A->col_idx, A->val, x, y, 0, (hipStream_t)stream));
+    RPCG_TRY(launch_spmv_csr(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, x, y, (hipStream_t)stream));
     return RPCG_OK;
 }
 

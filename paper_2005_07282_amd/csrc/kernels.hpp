@@ -130,10 +130,10 @@ hipError_t launch_exdot_partial(long long n, const double *x, const double *y, l
 hipError_t launch_acc_round(const long long *digits, double *out, hipStream_t s);
 // Exponent range (floor(log2 |v|)) of the nonzero finite entries of v, merged into *emin, *emax.
 hipError_t launch_exp_range(long long n, const double *v, int *emin, int *emax, hipStream_t s);
-// CSR SpMV; grid = workgroups of 512 rows each (0: one per row block, else a
-// grid-stride loop over the blocks).
-hipError_t launch_spmv_csr(int n, const int *row_ptr, const int *col, const double *val,
-                           const double *x, double *y, int grid, hipStream_t s);
+// CSR SpMV (nnz = row_ptr[n]): workgroups of 512 rows, one per row block;
+// the staging chunk is chosen by the average row length.
+hipError_t launch_spmv_csr(int n, long long nnz, const int *row_ptr, const int *col, const double *val,
+                           const double *x, double *y, hipStream_t s);
 
 // CSR structural check (*bad set if malformed), slice widths rounded up to a
 // multiple of vec (off_plus1), longest row, and the range of the 16-bit column
