@@ -166,6 +166,7 @@ int lp_loss_grad(rpcg_lpnet *L, int nb, const rpcg_csr *A, const double *const *
     RPCG_TRY(hipMemcpyAsync(L->tab.p, L->tab_host.data(), tab_bytes, hipMemcpyHostToDevice, s));
     const LpMat *mA = (const LpMat *)L->tab.p, *mG = mA + nb, *mGt = mA + 2 * nb;
     const double *const *ut = (const double *const *)((const char *)L->tab.p + mat_bytes);
+    // v, y, r, q: the nu vectors of an instance interleaved ([instance][cell][vector])
     double *v = (double *)L->lvec.p, *y = v + P * n, *r = y + P * n, *q = r + P * n;
     int *flags = (int *)((double *)L->scal.p + 4); // exact-dot flags of the loss (not reported)
     const double scale = 1.0 / (double)P;

@@ -39,18 +39,24 @@ hipError_t launch_lp_to_bf16(long long n, const double *a, bf16_t *b, hipStream_
 // ---- loss over a batch of (instance, probe) pairs (lp_loss.hip) ----
 constexpr int LP_DOT_P = 3;         // lane expansion length of the exact dots
 constexpr int LP_DOT_CHUNKS = 64;   // workgroups (slots) per pair and dot
-// y_p = M_k x_p, p = k nu + m (mats[k], k < nb); x_p = xtab[p] if xtab, else xbase + p n.
+// The loss's vectors v, y, r, q are interleaved per instance: entry i of the
+// vector of pair p = k nu + m at base + (k n + i) nu + m; the probes u_p are
+// read through the pointer table utab.
+// Y_k = M_k X_k (mats[k], k < nb) for the nu vectors of each instance: X from
+// xtab (one pointer per pair) if given, else interleaved at xbase.
 hipError_t launch_lp_mv(long long n, int nb, int nu, const LpMat *mats, const double *const *xtab, const double *xbase,
                         double *ybase, hipStream_t st);
-// r_p = (G_k y_p + eps v_p) - u_p and the slot partials of <u_p, u_p>, <r_p, r_p>
-// (slots p * LP_DOT_CHUNKS + c of wu, wr; capacity stride >= nb nu LP_DOT_CHUNKS).
+// R = (G_k Y + eps V) - U (interleaved; U through utab) and the slot partials
+// of <u_p, u_p>, <r_p, r_p> (slots p * LP_DOT_CHUNKS + c of wu, wr; capacity
+// stride >= nb nu LP_DOT_CHUNKS).
 hipError_t launch_lp_resid_dots(long long n, int nb, int nu, double eps, const LpMat *gm, const double *const *utab,
                                 const double *y, const double *v, double *r, const DotWs &wu, const DotWs &wr,
                                 int stride, int *flags, hipStream_t st);
 // dots[2p] = <u_p, u_p>, dots[2p + 1] = <r_p, r_p>, each correctly rounded.
 hipError_t launch_lp_dots_merge(int npairs, const DotWs &wu, const DotWs &wr, int stride, double *dots, int *flags,
                                 hipStream_t st);
-// dL/do of every instance (bfloat16 into dob; binary64 into do64 unless null) and the loss.
+// dL/do of every instance (bfloat16 into dob; binary64 into do64 unless null)
+// and the loss, from the interleaved R, Y, V, Q.
 hipError_t launch_lp_dodg_all(int N, int nb, int nu, double scale, const double *dots, const float *o, const float *s,
                               const LpMat *gm, const double *r, const double *y, const double *v, const double *q,
                               double *do64, bf16_t *dob, double *loss, hipStream_t st);
