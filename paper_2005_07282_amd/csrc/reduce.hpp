@@ -94,7 +94,14 @@ __device__ __forceinline__ void acc_add_product_lds(long long *acc, double x, do
     // x y = mx my 2^(ex + ey - 2150); off = offset of its last bit above 2^ACC_EXP0
     const int off = ex + ey - 2150 - ACC_EXP0;
     const int k = off >> 5, s = off & 31;
-    unsigned long long lo = mx * my, hi = __umul64hi(mx, my); // hi < 2^42
+    // schoolbook on 32-bit halves (the high halves are below 2^21): four
+    // 32 x 32 -> 64 products, the middle sum below 2^55
+    const unsigned xl = (unsigned)mx, xh = (unsigned)(mx >> 32), yl = (unsigned)my, yh = (unsigned)(my >> 32);
+    const unsigned long long p0 = (unsigned long long)xl * yl;
+    unsigned long long mid = (unsigned long long)xl * yh + (p0 >> 32);
+    mid += (unsigned long long)xh * yl;
+    unsigned long long lo = (p0 & 0xFFFFFFFFull) | (mid << 32);
+    unsigned long long hi = (unsigned long long)xh * yh + (mid >> 32); // hi < 2^42
     // the signed product as a 128-bit two's complement value (hi now signed)
     const bool neg = ((bx ^ by) >> 63) != 0;
     if (neg) {

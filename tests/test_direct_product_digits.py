@@ -1,6 +1,7 @@
 """Host check of the digit split the exact dot's direct path uses for a
 product x y (Section 4.1: the product enters the long accumulator exactly).
-The device forms the 106-bit product of the significands, negates it once as
+The device forms the 106-bit product of the significands (four 32 x 32-bit
+products of their halves), negates it once as
 a 128-bit two's complement value when the signs differ, shifts it onto the
 accumulator's 32-bit word grid and adds four unsigned 32-bit digits and the
 signed rest. This test replays that integer arithmetic with 64-bit
@@ -41,8 +42,16 @@ def _digits(x, y):
         ey = 1
     off = ex + ey - 2150 - ACC_EXP0
     k, s = off >> 5, off & 31
-    p = mx * my
-    lo, hi = p & M64, p >> 64
+    # the device's schoolbook on 32-bit halves, each step checked for 64-bit overflow
+    xl, xh, yl, yh = mx & 0xFFFFFFFF, mx >> 32, my & 0xFFFFFFFF, my >> 32
+    p0 = xl * yl
+    mid = xl * yh + (p0 >> 32)
+    assert mid <= M64
+    mid += xh * yl
+    assert mid <= M64
+    lo = (p0 & 0xFFFFFFFF) | ((mid << 32) & M64)
+    hi = xh * yh + (mid >> 32)
+    assert hi < 1 << 42 and (hi << 64) | lo == mx * my
     if (bx ^ by) >> 63:
         nlo = (0 - lo) & M64
         hi = (~hi + (1 if lo == 0 else 0)) & M64
