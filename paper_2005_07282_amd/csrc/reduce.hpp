@@ -126,6 +126,18 @@ __device__ __forceinline__ bool product_in_integer_range(double r)
     return is_finite_bits(r) && __builtin_fabs(r) >= 0x1p-969;
 }
 
+// The same condition decided from the biased exponents alone (sufficient, not
+// necessary): for normal x and y, |x y| lies in [2^(ex+ey-2046), 2^(ex+ey-2044)),
+// so ex + ey >= 1077 gives |RN(x y)| >= 2^-969 and ex + ey <= 3067 keeps it
+// at most 2^1023.
+__device__ __forceinline__ bool product_exponents_in_range(double x, double y)
+{
+    const int ex = (int)((__builtin_bit_cast(unsigned long long, x) >> 52) & 0x7FF);
+    const int ey = (int)((__builtin_bit_cast(unsigned long long, y) >> 52) & 0x7FF);
+    const int e = ex + ey;
+    return ex != 0 && ey != 0 && ex != 0x7FF && ey != 0x7FF && e >= 1077 && e <= 3067;
+}
+
 // Per-lane accumulator of one dot product.
 //
 // EXBLAS (Section 4.1, Listing 1): the TwoProd result and error go into one
@@ -165,10 +177,24 @@ struct LaneDot {
         win = wfl = direct = 0;
     }
 
+    // ADAPT: end of one add of the measurement window
+    __device__ __forceinline__ void adapt_tick()
+    {
+        if (++win == ADAPT_WINDOW) {
+            // more than one flush per add on average: go direct
+            direct = direct ? direct - 1 : (wfl > ADAPT_WINDOW ? ADAPT_DIRECT : 0);
+            win = wfl = 0;
+        }
+    }
+
     __device__ __forceinline__ void add(double x, double y, long long *acc, bool ee, bool capture)
     {
         if constexpr (MODE == MODE_PLAIN) {
             s = __builtin_fma(x, y, s);
+        } else if (MODE == MODE_EXBLAS && ADAPT && direct && product_exponents_in_range(x, y)) {
+            // direct mode, product in range by its exponents: no TwoProd needed
+            acc_add_product_lds(acc, x, y);
+            adapt_tick();
         } else {
             double r, t;
             two_prod(x, y, r, t);
@@ -187,11 +213,7 @@ struct LaneDot {
                     left = fpe_accumulate_from<P, (P > 1 ? 1 : 0)>(a, t);
                     if (left != 0.0) { acc_add_lds(acc, left, flags); ++wfl; }
                 }
-                if (++win == ADAPT_WINDOW) {
-                    // more than one flush per add on average: go direct
-                    direct = direct ? direct - 1 : (wfl > ADAPT_WINDOW ? ADAPT_DIRECT : 0);
-                    win = wfl = 0;
-                }
+                adapt_tick();
             } else if constexpr (MODE == MODE_EXBLAS) {
                 // the TwoProd error is about 2^-53 of the product: it enters
                 // the expansion one level down

@@ -102,3 +102,39 @@ def test_every_shift_both_signs():
         for sign in (1, -1):
             _check(sign * (1 + 2.0 ** -52) * 2.0 ** (s - 10), 3.0 * 2.0 ** 7)
             _check(sign * 2.0 ** (s - 40), -(2.0 - 2.0 ** -52))
+
+
+def _exponents_in_range(x, y):
+    """The device's exponent-only test for the direct add (normal operands,
+    1077 <= ex + ey <= 3067 on the biased exponents)."""
+    ex, ey = (_bits(x) >> 52) & 0x7FF, (_bits(y) >> 52) & 0x7FF
+    return 0 < ex < 0x7FF and 0 < ey < 0x7FF and 1077 <= ex + ey <= 3067
+
+
+def test_exponent_test_implies_range():
+    """Where the exponent-only test admits a product, the rounded-product
+    condition holds too (so the direct add's preconditions are met), checked
+    at the bounds of the test with the smallest and largest significands and
+    on random pairs."""
+    lo_sig, hi_sig = 1.0, 2.0 - 2.0 ** -52
+    cases = []
+    for e in (1077, 1078, 2046, 3066, 3067):
+        for ex in (max(1, e - 2046), e // 2, min(2046, e - 1)):
+            ey = e - ex
+            if not (0 < ex < 2047 and 0 < ey < 2047):
+                continue
+            for sx in (lo_sig, hi_sig):
+                for sy in (lo_sig, hi_sig):
+                    cases.append((sx * 2.0 ** (ex - 1023), -sy * 2.0 ** (ey - 1023)))
+    rng = random.Random(21)
+    while len(cases) < 20000:
+        x = rng.choice((-1, 1)) * (1 + rng.random()) * 2.0 ** rng.randint(-1022, 1023)
+        y = rng.choice((-1, 1)) * (1 + rng.random()) * 2.0 ** rng.randint(-1022, 1023)
+        if _exponents_in_range(x, y):
+            cases.append((x, y))
+    for x, y in cases:
+        assert _exponents_in_range(x, y), (x, y)
+        assert _in_range(x, y), (x, y)
+        _check(x, y)
+    # the bounds are tight: one binade lower may fall below 2^-969
+    assert not _in_range(2.0 ** -485, 2.0 ** -485)
