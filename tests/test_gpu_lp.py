@@ -61,18 +61,22 @@ def test_forward_matches_oracle(R, net10):
         assert np.mean(err > 1e-3 * scale) < 0.01
 
 
-def test_loss_grad_matches_oracle(R, net10):
+@pytest.mark.parametrize("nu", [2, 4, 9])
+def test_loss_grad_matches_oracle(R, net10, nu):
+    """Loss and dL/do against the oracle; nu = 4 takes the device's
+    four-vector path, 2 and 9 the general one (9: two passes of eight and one
+    over the interleaved vectors)."""
     N = 10
     As = systems(N, [13])
     mats = [R.CSR.from_host(A) for A in As]
-    us = [[uniform_pm1(30 + m, As[0].n) for m in range(2)]]
+    us = [[uniform_pm1(30 + m, As[0].n) for m in range(nu)]]
     ud = [[torch.from_numpy(u).cuda() for u in row] for row in us]
     loss, dout = net10.loss_grad(mats, ud, eps=1e-6)
     o = net10.forward(mats).cpu().numpy()[0]
     G, dgdo = lpnet.factor(As[0], N, o)
     L, dG = lpnet.loss_grad(As[0], G, us[0], 1e-6)
     do = lpnet.do_from_dg(G, dG, dgdo, N).reshape(-1, 4)
-    print(f"loss gpu {loss:.12g} oracle {L:.12g}", flush=True)
+    print(f"nu={nu}: loss gpu {loss:.12g} oracle {L:.12g}", flush=True)
     # the exponential of the diagonal output is the only step not correctly
     # rounded on both sides (last-bit differences of G_ii)
     assert abs(loss - L) <= 1e-6 * abs(L)
