@@ -298,12 +298,62 @@ __device__ __forceinline__ int fpe_sum_capture(double (&a)[P], const double (&b)
 // Exact sum of the lanes' expansions of one wavefront added to the long
 // accumulator (EXBLAS): every lane cuts its components into the
 // accumulator's 32-bit digit chunks, the wavefront sums each word's chunks
-// over its lanes with integer shuffles (exact: at most 64 * 3 * P chunks
+// over its lanes with integer DPP steps (exact: at most 64 * 3 * P chunks
 // below 2^32 each), and one lane adds each word sum to the accumulator.
 // Integers add exactly in any order, so this is the same value as merging
 // the expansions and flushing the remainders; the words are independent,
 // so there is no chain of dependent TwoSums. Words outside the wavefront's
 // range of chunks hold nothing and are skipped.
+// One DPP step of a 64-bit integer (both halves moved by the same lane
+// pattern; lanes without a source, or outside the row mask, read 0).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ long long dpp_i64(long long v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROW_MASK, 0xF, true);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Sum of a 64-bit integer over the wavefront's 64 lanes, exact, left in lane
+// 63: prefix sums within each row of 16 lanes (row shifts by 1, 2, 4, 8),
+// then row 0's total broadcast into row 1 and row 2's into row 3, then the
+// total of rows 0-1 into rows 2-3. Register moves only, no LDS round trips.
+__device__ __forceinline__ long long wave_sum_i64_last(long long v)
+{
+    v += dpp_i64<0x111>(v);      // row_shr:1
+    v += dpp_i64<0x112>(v);      // row_shr:2
+    v += dpp_i64<0x114>(v);      // row_shr:4
+    v += dpp_i64<0x118>(v);      // row_shr:8
+    v += dpp_i64<0x142, 0xA>(v); // row_bcast:15 into rows 1 and 3
+    v += dpp_i64<0x143, 0xC>(v); // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// The same sum in every lane (read from lane 63).
+__device__ __forceinline__ long long wave_sum_i64_all(long long v)
+{
+    v = wave_sum_i64_last(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(v >> 32), 63);
+    return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+// Minimum / maximum of an int over the wavefront, in every lane: the same
+// DPP pattern, lanes without a source keeping the identity.
+template <bool MAX>
+__device__ __forceinline__ int wave_minmax_i32_all(int v)
+{
+    constexpr int ID = MAX ? -2147483647 - 1 : 2147483647;
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x111, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x112, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x114, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x118, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x142, 0xA, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(ID, v, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 template <int P>
 __device__ __forceinline__ void wave_flush_exact(const double (&a)[P], long long *acc, int &flags)
 {
@@ -328,11 +378,8 @@ __device__ __forceinline__ void wave_flush_exact(const double (&a)[P], long long
             }
         }
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, __shfl_xor(lo, off, 64));
-        hi = max(hi, __shfl_xor(hi, off, 64));
-    }
+    lo = wave_minmax_i32_all<false>(lo);
+    hi = wave_minmax_i32_all<true>(hi);
     for (int w = lo; w <= hi; ++w) {
         long long v = 0;
 #pragma unroll
@@ -340,9 +387,8 @@ __device__ __forceinline__ void wave_flush_exact(const double (&a)[P], long long
             const int d = w - k[i];
             v += d == 0 ? c0[i] : (d == 1 ? c1[i] : (d == 2 ? c2[i] : 0ll));
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane_id() == 0 && v != 0) atomicAdd((unsigned long long *)&acc[w], (unsigned long long)v);
+        v = wave_sum_i64_last(v);
+        if (lane_id() == 63 && v != 0) atomicAdd((unsigned long long *)&acc[w], (unsigned long long)v);
     }
 }
 
@@ -397,19 +443,11 @@ __device__ __forceinline__ void wave_flush_exact2(const double (&a0)[P], long lo
     int lo = ACC_DIGITS, hi = -1;
     q0.cut(a0, lo, hi, flags0);
     q1.cut(a1, lo, hi, flags1);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        lo = min(lo, __shfl_xor(lo, off, 64));
-        hi = max(hi, __shfl_xor(hi, off, 64));
-    }
+    lo = wave_minmax_i32_all<false>(lo);
+    hi = wave_minmax_i32_all<true>(hi);
     for (int w = lo; w <= hi; ++w) {
-        long long v0 = q0.word(w), v1 = q1.word(w);
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            v0 += __shfl_xor(v0, off, 64);
-            v1 += __shfl_xor(v1, off, 64);
-        }
-        if (lane_id() == 0) {
+        const long long v0 = wave_sum_i64_last(q0.word(w)), v1 = wave_sum_i64_last(q1.word(w));
+        if (lane_id() == 63) {
             if (v0 != 0) atomicAdd((unsigned long long *)&acc0[w], (unsigned long long)v0);
             if (v1 != 0) atomicAdd((unsigned long long *)&acc1[w], (unsigned long long)v1);
         }
@@ -660,7 +698,7 @@ __device__ inline T wave_acc_round(const long long *acc)
 // LDS accumulator the merge may overwrite. *esc_out (thread 0) receives the
 // escapes (FPE); flags seen on the way are or-ed into *flags_out.
 
-// Sum of row[0..G) by one wavefront (result in lane 0); eight independent
+// Sum of row[0..G) by one wavefront (result in every lane); eight independent
 // loads per lane are in flight at a time.
 __device__ __forceinline__ long long sum_row(const long long *row, int G)
 {
@@ -672,7 +710,7 @@ __device__ __forceinline__ long long sum_row(const long long *row, int G)
     }
     for (; g < G; g += 64) s[0] += row[g];
     long long t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
-    return wave_sum_down(t);
+    return wave_sum_i64_all(t);
 }
 
 template <int MODE, int P, typename T = double>
@@ -717,11 +755,8 @@ __device__ __forceinline__ T merge_slots(const SlotView &sv, int G, bool ee, boo
             kmin = min(kmin, sv.ws.range[2 * g]);
             kmax = max(kmax, sv.ws.range[2 * g + 1]);
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            kmin = min(kmin, __shfl_down(kmin, off, 64));
-            kmax = max(kmax, __shfl_down(kmax, off, 64));
-        }
+        kmin = wave_minmax_i32_all<false>(kmin);
+        kmax = wave_minmax_i32_all<true>(kmax);
         if (lane_id() == 0) { atomicMin(&sh.rng[0], kmin); atomicMax(&sh.rng[1], kmax); }
         __syncthreads();
         const int K0 = sh.rng[0], K1 = sh.rng[1];
