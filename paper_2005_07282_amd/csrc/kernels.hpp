@@ -73,9 +73,11 @@ struct PcgState {
 // V-entry interleave: entry k of row 64*s + j sits at
 //     off[s] + 64*V*(k/V) + V*j + (k%V),
 // so lane j reads V consecutive entries of its row with one vector load while
-// each load of the wavefront is one contiguous segment. Slice widths are
-// multiples of V; rows keep their CSR order and length; padding entries hold
-// the value 0 and a valid column. T is the type the solver computes in and V
+// each load of the wavefront is one contiguous segment. The slice width is
+// its longest row; when it is not a multiple of V (V = 2, odd width w) the
+// last entry k = w-1 sits alone at off[s] + 64*(w-1) + j, so an odd row
+// length costs no padding entry. Rows keep their CSR order and length;
+// padding entries hold the value 0 and a valid column. T is the type the solver computes in and V
 // = sell_vec<T>() (two for binary64: 16-byte loads; one for binary32).
 //
 // Columns: with col16 (16-bit column codes), the column of rank 0 of row

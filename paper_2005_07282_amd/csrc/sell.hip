@@ -72,7 +72,7 @@ __device__ __forceinline__ void max_to(unsigned long long *p, unsigned long long
 
 // Pass 1, one slice at a time per wavefront (grid-stride): structural check
 // of the CSR (row_ptr[0] = 0, row_ptr[n] = nnz, non-decreasing, columns in
-// [0, n)), slice widths (rounded up to a multiple of vec), the longest row,
+// [0, n)), slice widths (the slice's longest row), the longest row,
 // and whether the 16-bit column codes can represent the slice: *max_delta
 // receives the largest |rank-0 code|, or 2^40 if a step between consecutive
 // columns of a row is negative or above 65535. Each wavefront keeps its
@@ -99,7 +99,7 @@ __global__ void k_csr_scan(int n, int nnz, int nslices, const int *__restrict__ 
         int w = len;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
-        if (lane == 0) off_plus1[s] = 64ll * ((w + vec - 1) / vec * vec);
+        if (lane == 0) off_plus1[s] = 64ll * w; // an odd width ends in a single-entry column
         wmax = max(wmax, w);
         if (__ballot(!ok) != 0) { // rows inconsistent: the entries are not read
             failed = true;
@@ -231,9 +231,13 @@ __global__ void __launch_bounds__(64) k_sell_fill(int n, int nslices, const int 
         // the chunk's run in layout order: t = 64 vec (q / vec) + vec j + q % vec for rank k0 + q of row j
         const int nk = min(FILL_RANKS, width - k0);
         const long long run = base + 64ll * k0;
+        // chunk rank of the single-entry last column of an odd width (even,
+        // as k0 is), past the chunk when there is none here
+        const int tq = (vec > 1 && (width % vec) != 0) ? width - 1 - k0 : FILL_RANKS;
         for (int t = lane; t < 64 * nk; t += 64) {
-            const int q = vec * (t / (64 * vec)) + t % vec;
-            const int j = (t % (64 * vec)) / vec;
+            const bool last = t >= 64 * tq;
+            const int q = last ? tq : vec * (t / (64 * vec)) + t % vec;
+            const int j = last ? t - 64 * tq : (t % (64 * vec)) / vec;
             const double v = tv[q * FILL_PITCH + j];
             const int c = tc[q * FILL_PITCH + j];
             if (sval64) sval64[run + t] = v;

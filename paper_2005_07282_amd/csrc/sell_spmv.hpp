@@ -10,8 +10,9 @@ namespace rpcg {
 
 // Entries of one row loaded per batch: the loads of a batch are issued
 // together so the wavefront waits for memory once per batch, not once per
-// entry (14 = two batches per interior 27-point row padded to 28 with the
-// two-entry interleave; 9 divides the 27 entries without it).
+// entry (14 with the two-entry interleave: an interior 27-point row is one
+// batch of 14 and a last batch of 12 plus its single-entry last column; 9
+// divides the 27 entries without it).
 template <typename T>
 __host__ __device__ constexpr int spmv_batch()
 {
@@ -80,6 +81,75 @@ __device__ __forceinline__ int sell_len(const SellMat<T> &A, long long i)
     return A.len8 ? (int)A.len8[i] : A.row_ptr[i + 1] - A.row_ptr[i];
 }
 
+// R consecutive groups of this lane's row, from group g0, as one batch: all
+// loads, then all gathers, then the fma chain in storage order (only the
+// row's own entries enter it).
+template <typename T, bool COL16, bool DIAG, int R, bool LAST = false>
+__device__ __forceinline__ void sell_batch(const SellMat<T> &A, long long p0, int g0, int first, int &cur, int len,
+                                           long long i, const T *__restrict__ x, T &sum, T *aii, bool *found,
+                                           long long pl = 0, int kl = 0)
+{
+    constexpr int V = sell_vec<T>();
+    int c[R + 1][V];
+    T a[R + 1][V];
+#pragma unroll
+    for (int u = 0; u < R; ++u) sell_group<T, COL16>(A, p0 + 64ll * V * (g0 + u), V * (g0 + u), first, cur, c[u], a[u]);
+    // LAST: the single-entry last column (entry kl = width-1 at pl)
+    int cl = 0;
+    T al = T(0);
+    if constexpr (LAST) {
+        al = __builtin_nontemporal_load(A.val + pl);
+        if constexpr (COL16) {
+            const unsigned code = __builtin_nontemporal_load(A.col16 + pl);
+            cur = kl == 0 ? first + (int)(short)code : cur + (int)code;
+            cl = cur;
+        } else {
+            cl = __builtin_nontemporal_load(A.col + pl);
+        }
+    }
+    T g[R + 1][V];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) g[u][v] = x[c[u][v]];
+    T gl = T(0);
+    if constexpr (LAST) gl = x[cl];
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const bool in = V * (g0 + u) + v < len;
+            const T t = fma_t(a[u][v], g[u][v], sum);
+            sum = in ? t : sum;
+            if constexpr (DIAG) {
+                if (in && c[u][v] == (int)i) { *aii = a[u][v]; *found = true; }
+            }
+        }
+    if constexpr (LAST) {
+        const bool in = kl < len;
+        const T t = fma_t(al, gl, sum);
+        sum = in ? t : sum;
+        if constexpr (DIAG) {
+            if (in && cl == (int)i) { *aii = al; *found = true; }
+        }
+    }
+}
+
+// The last rest < R groups as one batch of exactly that many (rest is
+// wavefront-uniform, so the choice is a scalar branch and each batch is
+// straight-line code).
+template <typename T, bool COL16, bool DIAG, int R, bool LAST>
+__device__ __forceinline__ void sell_rest(int rest, const SellMat<T> &A, long long p0, int g0, int first, int &cur,
+                                          int len, long long i, const T *__restrict__ x, T &sum, T *aii, bool *found,
+                                          long long pl, int kl)
+{
+    if constexpr (R > 0 || (LAST && R == 0)) {
+        if (rest == R) sell_batch<T, COL16, DIAG, R, LAST>(A, p0, g0, first, cur, len, i, x, sum, aii, found, pl, kl);
+        else if constexpr (R > 0)
+            sell_rest<T, COL16, DIAG, R - 1, LAST>(rest, A, p0, g0, first, cur, len, i, x, sum, aii, found, pl, kl);
+    }
+}
+
 // sum = fold over k < len of fma(a_ik, x[col_ik], sum) from +0 in T, for the
 // row of this lane in slice s (base = off[s], width = slice width, both
 // uniform). Every position up to the width holds a valid column (padding
@@ -101,59 +171,14 @@ __device__ __forceinline__ T sell_row(const SellMat<T> &A, long long base, int w
     const int groups = width / V;
     T sum = T(0);
     int g0 = 0;
-    for (; g0 + BG <= groups; g0 += BG) {
-        int c[BG][V];
-        T a[BG][V];
-#pragma unroll
-        for (int u = 0; u < BG; ++u) sell_group<T, COL16>(A, p0 + 64ll * V * (g0 + u), V * (g0 + u), first, cur, c[u], a[u]);
-        T g[BG][V];
-#pragma unroll
-        for (int u = 0; u < BG; ++u)
-#pragma unroll
-            for (int v = 0; v < V; ++v) g[u][v] = x[c[u][v]];
-#pragma unroll
-        for (int u = 0; u < BG; ++u)
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const bool in = V * (g0 + u) + v < len;
-                const T t = fma_t(a[u][v], g[u][v], sum);
-                sum = in ? t : sum;
-                if constexpr (DIAG) {
-                    if (in && c[u][v] == (int)i) { *aii = a[u][v]; *found = true; }
-                }
-            }
-    }
-    // the remaining groups (fewer than a batch; wavefront-uniform count) as
-    // one more batch whose loads are issued together, so a short row (a
-    // 7-point row is four groups) waits for memory once
-    const int rest = groups - g0;
-    if (rest > 0) {
-        int c[BG][V];
-        T a[BG][V];
-#pragma unroll
-        for (int u = 0; u < BG; ++u)
-            if (u < rest) sell_group<T, COL16>(A, p0 + 64ll * V * (g0 + u), V * (g0 + u), first, cur, c[u], a[u]);
-        T g[BG][V];
-#pragma unroll
-        for (int u = 0; u < BG; ++u)
-            if (u < rest) {
-#pragma unroll
-                for (int v = 0; v < V; ++v) g[u][v] = x[c[u][v]];
-            }
-#pragma unroll
-        for (int u = 0; u < BG; ++u)
-            if (u < rest) {
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const bool in = V * (g0 + u) + v < len;
-                    const T t = fma_t(a[u][v], g[u][v], sum);
-                    sum = in ? t : sum;
-                    if constexpr (DIAG) {
-                        if (in && c[u][v] == (int)i) { *aii = a[u][v]; *found = true; }
-                    }
-                }
-            }
-    }
+    for (; g0 + BG <= groups; g0 += BG) sell_batch<T, COL16, DIAG, BG>(A, p0, g0, first, cur, len, i, x, sum, aii, found);
+    // the remaining groups (fewer than a batch) as one more batch, so a
+    // short row (a 7-point row is four groups) waits for memory once
+    if (V > 1 && (width % V) != 0) // odd width: the single-entry last column joins this batch
+        sell_rest<T, COL16, DIAG, BG - 1, true>(groups - g0, A, p0, g0, first, cur, len, i, x, sum, aii, found,
+                                                 base + 64ll * (width - 1) + lane, width - 1);
+    else
+        sell_rest<T, COL16, DIAG, BG - 1, false>(groups - g0, A, p0, g0, first, cur, len, i, x, sum, aii, found, 0, 0);
     return sum;
 }
 

@@ -10,7 +10,7 @@ import math
 import numpy as np
 import pytest
 
-from rpcg_workloads import (CSRHost, random_spd_csr, stencil27_csr, stencil27_rhs_from_int52,
+from rpcg_workloads import (CSRHost, band_csr, random_spd_csr, stencil27_csr, stencil27_rhs_from_int52,
                             stencil7_varcoef_csr, uniform_pm1, uniform_pm1_int52)
 
 pytestmark = pytest.mark.gpu
@@ -159,6 +159,24 @@ def test_permuted_matrix_wide_columns(R, orc):
     for mode in ("exblas", "fpe"):
         x, info = _solve(R, A, b, mode)
         assert info["iterations"] == ref["iters"]
+        assert _eq(info["hist"].numpy(), ref["hist"])
+        assert _eq(x, ref["x"])
+
+
+@pytest.mark.parametrize("w", [0, 1, 7, 13, 14, 20])
+def test_band_row_lengths_bitexact(R, orc, w):
+    """Rows of 2w + 1 entries (shorter at the band's ends): odd widths of the
+    solver's sliced-ELL copy, whose last entry sits in a single-entry column,
+    read alone (w = 0), after a partial batch of pairs (1, 13, 20) or right
+    after full batches (7, 14). Bit-identical to the oracle in both exact
+    modes."""
+    A = band_csr(300 + w, w)
+    b = uniform_pm1(40 + w, A.n)
+    ref = orc.pcg(A, b, tol=1e-10, maxit=2000)
+    for mode in ("exblas", "fpe"):
+        x, info = _solve(R, A, b, mode, tol=1e-10, maxit=2000)
+        assert info["status"] == ref["status"]
+        assert info["iterations"] == ref["iters"], (w, mode)
         assert _eq(info["hist"].numpy(), ref["hist"])
         assert _eq(x, ref["x"])
 
