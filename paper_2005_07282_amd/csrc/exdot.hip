@@ -10,15 +10,26 @@ namespace rpcg {
 // Standalone dot product: per-workgroup partials, then a one-workgroup
 // finalize that merges them and rounds once.
 
+constexpr int EX_COPIES = 4;
+constexpr int EX_PITCH = ACC_DIGITS; // 136 dwords: copies 8 banks apart
+
 template <int MODE, int P>
 __global__ void __launch_bounds__(MAX_BLOCK)
 k_exdot_part(long long n, const double *__restrict__ x, const double *__restrict__ y, SlotView sv,
              DotInfo *info, bool ee, bool capture)
 {
     __shared__ RedShared sh;
+    // lanes add into one of EX_COPIES copies of the long accumulator by
+    // lane & (EX_COPIES - 1), so lanes that hit the same word in the same
+    // instruction mostly hit different addresses (copies EX_PITCH words
+    // apart start in different LDS banks); summed into copy 0 at the end
+    __shared__ long long accx[EX_COPIES - 1][EX_PITCH];
     long long *acc = sh.acc[0];
     zero_acc(acc);
+    for (int q = threadIdx.x; q < (EX_COPIES - 1) * EX_PITCH; q += blockDim.x) (&accx[0][0])[q] = 0;
     __syncthreads();
+    const int cp = threadIdx.x & (EX_COPIES - 1);
+    long long *accl = cp ? accx[cp - 1] : acc;
 
     LaneDot<MODE, P, MODE != MODE_PLAIN> L;
     L.init();
@@ -31,12 +42,22 @@ k_exdot_part(long long n, const double *__restrict__ x, const double *__restrict
         const double2 *y2 = reinterpret_cast<const double2 *>(y);
         for (long long i = tid; i < n2; i += stride) {
             double2 a = x2[i], b = y2[i];
-            L.add(a.x, b.x, acc, ee, capture);
-            L.add(a.y, b.y, acc, ee, capture);
+            L.add(a.x, b.x, accl, ee, capture);
+            L.add(a.y, b.y, accl, ee, capture);
         }
-        if ((n & 1) && tid == 0) L.add(x[n - 1], y[n - 1], acc, ee, capture);
+        if ((n & 1) && tid == 0) L.add(x[n - 1], y[n - 1], accl, ee, capture);
     } else {
-        for (long long i = tid; i < n; i += stride) L.add(x[i], y[i], acc, ee, capture);
+        for (long long i = tid; i < n; i += stride) L.add(x[i], y[i], accl, ee, capture);
+    }
+    if constexpr (MODE != MODE_PLAIN) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < ACC_DIGITS; q += blockDim.x) {
+            long long v = acc[q];
+#pragma unroll
+            for (int c = 0; c < EX_COPIES - 1; ++c) v += accx[c][q];
+            acc[q] = v;
+        }
+        __syncthreads();
     }
     block_finish<MODE, P>(L, acc, sv, blockIdx.x, ee, capture, &info->flags, sh);
 }
