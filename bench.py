@@ -65,31 +65,45 @@ def k1_traffic():
     return None
 
 
-def time_spmv(rpcg, torch, Ad, n, nnz, reps=20):
-    """The exported CSR SpMV (rpcg_spmv) on the caller's CSR: median of reps
-    event-timed calls against its algorithmic bytes 12 nnz + 4 (n+1) + 8 n
-    (x read once) + 8 n (y written)."""
+def time_spmv(rpcg, torch, Ad, n, nnz, reps=20, prepared=False):
+    """The exported SpMV on the caller's CSR (rpcg_spmv), or with
+    prepared=True on a prepared sliced-ELL copy (rpcg_smat_spmv; the copy's
+    creation timed once, apart): median of reps event-timed calls against
+    the CSR algorithmic bytes 12 nnz + 4 (n+1) + 8 n (x read once) + 8 n (y
+    written)."""
     import numpy as np
     dev = Ad.row_ptr.device
     x = torch.ones(n, dtype=torch.float64, device=dev)
     y = torch.empty(n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    extra = {}
+    if prepared:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M = rpcg.PreparedMatrix(Ad)
+        extra["create_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        call, name = (lambda: M.spmv(x, y)), "k_sell_spmv (rpcg_smat_spmv)"
+    else:
+        M = None
+        call, name = (lambda: rpcg.spmv(Ad, x, y)), "k_spmv_csr (rpcg_spmv)"
     for _ in range(5):
-        rpcg.spmv(Ad, x, y)
+        call()
     times = []
     for _ in range(reps):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        rpcg.spmv(Ad, x, y)
+        call()
         e1.record(stream)
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
+    if M is not None:
+        M.close()
     tm = float(np.median(times))
     byt = 12 * nnz + 4 * (n + 1) + 16 * n
     gbs = byt / (tm * 1e-3) / 1e9
     del x, y
-    return {"kernel": "k_spmv_csr (rpcg_spmv)", "ms": round(tm, 5), "bytes": byt, "GB_s": round(gbs, 1),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return {"kernel": name, "ms": round(tm, 5), "bytes": byt, "GB_s": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), **extra}
 
 
 def iteration_bytes(n, nnz):
@@ -313,10 +327,13 @@ def run_stress(n, w, n_ill, w_ill, rpcg, torch, dev):
     k1_bytes_band = 10 * nnz + 4 * (n + 1) + 16 * n  # 16-bit codes + values, row pointers, d, w (SELL-64)
     spmv_band = time_spmv(rpcg, torch, Ad, n, nnz)
     log(f"[bench]   rpcg_spmv on the band: {spmv_band['ms']} ms, {spmv_band['GB_s']} GB/s")
+    smat_band = time_spmv(rpcg, torch, Ad, n, nnz, prepared=True)
+    log(f"[bench]   rpcg_smat_spmv on the band: {smat_band['ms']} ms, {smat_band['GB_s']} GB/s")
     out["band"] = {
         "workload": f"band matrix n={n}, bandL = bandU = {w} (nnz={nnz}), 2w+1 on the diagonal, -1 in the band, "
                     f"b = A 1, x0 = 0, tol 1e-8",
         "rpcg_spmv": spmv_band,
+        "rpcg_smat_spmv": smat_band,
         "fpe_size_auto": p_auto, "exponent_range": rng,
         "runs": runs,
         "exblas_over_plain": round(runs["exblas"]["ms_per_iteration"] / runs["plain"]["ms_per_iteration"], 4),
@@ -731,6 +748,8 @@ def main():
     _, full = solve("exblas", 2000)
     spmv160 = time_spmv(rpcg, torch, Ad, n, nnz)
     log(f"[bench] rpcg_spmv {N}^3: {spmv160['ms']} ms, {spmv160['GB_s']} GB/s")
+    smat160 = time_spmv(rpcg, torch, Ad, n, nnz, prepared=True)
+    log(f"[bench] rpcg_smat_spmv {N}^3: {smat160['ms']} ms, {smat160['GB_s']} GB/s")
     del Ad, bd
     torch.cuda.empty_cache()
 
@@ -780,6 +799,7 @@ def main():
             "kernel_ms": {"spmv_dot": round(k1_ms, 5), "update_dots": round(k2_ms, 5),
                           "direction": round(k3_ms, 5)},
             "rpcg_spmv": spmv160,
+            "rpcg_smat_spmv": smat160,
             "exdot_n": ne,
             "exdot": exd,
             "exdot_grid": exgrid,

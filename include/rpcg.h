@@ -185,6 +185,34 @@ int rpcg_exdot_noalloc(rpcg_mode mode, int64_t n, const double *x, const double 
 int rpcg_spmv(rpcg_ctx *ctx, const rpcg_csr *A /* host struct */, const double *x, double *y,
               void *stream);
 
+/* A matrix prepared for repeated products (Section 4.3 SpMV): a device copy
+ * in the solver's sliced-ELL layout (binary64 values, 16-bit column codes
+ * where the columns allow them; about 10 bytes per stored entry plus 9 bytes
+ * per row), owned by the handle. Products with it are the same fma chains as
+ * rpcg_spmv, so y is bit-identical to rpcg_spmv on the matrix it was made
+ * from, at the streaming rate of the solver's own SpMV. */
+typedef struct rpcg_smat rpcg_smat;
+
+/* Builds the copy of A (device CSR; its structure is checked on the device,
+ * RPCG_ERR_INVALID if row_ptr or a column index is out of range) on ctx's
+ * device and waits for the stream. The copy does not refer to A afterwards:
+ * A may be freed or changed (the copy keeps the values it was made from).
+ * *out receives the handle, or NULL on error (RPCG_ERR_INVALID for NULL
+ * ctx, A or out; RPCG_ERR_OOM / RPCG_ERR_HIP if device memory runs out).
+ * Uses ctx's scratch memory while it runs: calls on one context must not
+ * overlap. */
+int rpcg_smat_create(rpcg_ctx *ctx, const rpcg_csr *A /* host struct */, rpcg_smat **out, void *stream);
+
+/* y = A x with a prepared matrix: y_i = fold over the stored entries of row
+ * i in order of acc = fma(a_ik, x[col_k], acc) from +0. x, y: n doubles on
+ * the matrix's device; y must not alias x (RPCG_ERR_INVALID). Asynchronous;
+ * returns after enqueueing. Products on different streams may overlap (the
+ * handle is only read). */
+int rpcg_smat_spmv(rpcg_smat *M, const double *x, double *y, void *stream);
+
+/* Frees the copy (NULL is ignored). No product with it may be pending. */
+void rpcg_smat_destroy(rpcg_smat *M);
+
 /* Expansion length for FPE mode bound to the data's dynamic range (the
  * binding of the FPE length to the dynamic range that Section 7 proposes as
  * future work). With R = largest minus smallest binary exponent over the

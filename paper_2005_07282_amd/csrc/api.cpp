@@ -292,20 +292,32 @@ struct SellBuilt {
     const unsigned char *len8 = nullptr;
 };
 
+// Device buffers a sliced-ELL copy is built into (the context's for the
+// solver, a rpcg_smat's own for prepared matrices).
+struct SellBufs {
+    rpcg_host::Buffer *off, *val, *val32, *col, *cfirst, *len;
+};
+
+static SellBufs ctx_sell_bufs(rpcg_ctx *c)
+{
+    return {&c->sell_off, &c->sell_val, &c->sell_val32, &c->sell_col, &c->sell_cfirst, &c->sell_len};
+}
+
 // One pass over the CSR checks its structure and measures the slices
 // (nothing indexes through the matrix before the check has passed), then the
 // copy is filled. Source values: v64 or v32; kept as binary64 (out64) and/or
 // rounded to binary32 (out32). The interleave is that of the solver's value
 // type: two entries for a binary64-only copy, one when binary32 values are
 // kept. Waits for the stream.
-static int build_sell(rpcg_ctx *c, int n, int nnz, const int *rp, const int *col, const double *v64,
-                      const float *v32, bool out64, bool out32, bool no_col16, hipStream_t s, SellBuilt *out)
+static int build_sell(rpcg_ctx *c, const SellBufs &bf, int n, int nnz, const int *rp, const int *col,
+                      const double *v64, const float *v32, bool out64, bool out32, bool no_col16, hipStream_t s,
+                      SellBuilt *out)
 {
     const int nslices = (n + 63) / 64;
     const int vec = out32 ? sell_vec<float>() : sell_vec<double>();
     RPCG_TRY(hipMemsetAsync(c->info, 0, sizeof(DotInfo), s));
-    RPCG_TRY(c->sell_off.ensure(sizeof(long long) * (nslices + 1)));
-    long long *off = (long long *)c->sell_off.p;
+    RPCG_TRY(bf.off->ensure(sizeof(long long) * (nslices + 1)));
+    long long *off = (long long *)bf.off->p;
     RPCG_TRY(hipMemsetAsync(off, 0, sizeof(long long) * (nslices + 1), s));
     RPCG_TRY(launch_csr_scan(n, nnz, rp, col, vec, off + 1, &c->info->flags, &c->info->max_len,
                              &c->info->max_delta, s));
@@ -320,28 +332,28 @@ static int build_sell(rpcg_ctx *c, int n, int nnz, const int *rp, const int *col
     const size_t np = (size_t)std::max(1ll, padded);
     double *s64 = nullptr;
     float *s32 = nullptr;
-    if (out64) { RPCG_TRY(c->sell_val.ensure(sizeof(double) * np)); s64 = (double *)c->sell_val.p; }
-    if (out32) { RPCG_TRY(c->sell_val32.ensure(sizeof(float) * np)); s32 = (float *)c->sell_val32.p; }
-    RPCG_TRY(c->sell_col.ensure((col16 ? sizeof(short) : sizeof(int)) * np));
+    if (out64) { RPCG_TRY(bf.val->ensure(sizeof(double) * np)); s64 = (double *)bf.val->p; }
+    if (out32) { RPCG_TRY(bf.val32->ensure(sizeof(float) * np)); s32 = (float *)bf.val32->p; }
+    RPCG_TRY(bf.col->ensure((col16 ? sizeof(short) : sizeof(int)) * np));
     int *cfirst = nullptr;
     if (col16) {
-        RPCG_TRY(c->sell_cfirst.ensure(sizeof(int) * (size_t)std::max(1, nslices)));
-        cfirst = (int *)c->sell_cfirst.p;
+        RPCG_TRY(bf.cfirst->ensure(sizeof(int) * (size_t)std::max(1, nslices)));
+        cfirst = (int *)bf.cfirst->p;
     }
     unsigned char *len8 = nullptr;
     if (scan_info.max_len < 256) {
-        RPCG_TRY(c->sell_len.ensure((size_t)std::max(1, n)));
-        len8 = (unsigned char *)c->sell_len.p;
+        RPCG_TRY(bf.len->ensure((size_t)std::max(1, n)));
+        len8 = (unsigned char *)bf.len->p;
     }
-    RPCG_TRY(launch_sell_fill(n, rp, col, v64, v32, vec, off, s64, s32, col16 ? nullptr : (int *)c->sell_col.p,
-                              col16 ? (unsigned short *)c->sell_col.p : nullptr, cfirst, len8, s));
+    RPCG_TRY(launch_sell_fill(n, rp, col, v64, v32, vec, off, s64, s32, col16 ? nullptr : (int *)bf.col->p,
+                              col16 ? (unsigned short *)bf.col->p : nullptr, cfirst, len8, s));
     out->nslices = nslices;
     out->col16 = col16;
     out->off = off;
     out->val64 = s64;
     out->val32 = s32;
-    out->col = col16 ? nullptr : (const int *)c->sell_col.p;
-    out->col16p = col16 ? (const unsigned short *)c->sell_col.p : nullptr;
+    out->col = col16 ? nullptr : (const int *)bf.col->p;
+    out->col16p = col16 ? (const unsigned short *)bf.col->p : nullptr;
     out->cfirst = cfirst;
     out->len8 = len8;
     return RPCG_OK;
@@ -560,7 +572,7 @@ static int pcg_solve_any(rpcg_ctx *c, int mode, int n, int nnz, const int *rp, c
     int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
     if (rc != RPCG_OK) return rc;
     SellBuilt B;
-    rc = build_sell(c, n, nnz, rp, col, v64, v32, !F32, F32, o.no_col16 != 0, s, &B);
+    rc = build_sell(c, ctx_sell_bufs(c), n, nnz, rp, col, v64, v32, !F32, F32, o.no_col16 != 0, s, &B);
     if (rc != RPCG_OK) return rc;
     for (const rpcg_csr *E : {extra0, extra1}) {
         if (!E) continue;
@@ -669,7 +681,8 @@ static int ir_body(rpcg_ctx *c, int mode, const rpcg_csr *A, const double *b, do
     int rc = ensure_ws(c, std::max(std::max(cfg_rows.grid, cfg_sl.grid), std::max(cfg_res.grid, cfg_dot.grid)));
     if (rc != RPCG_OK) return rc;
     SellBuilt B;
-    rc = build_sell(c, n, A->nnz, A->row_ptr, A->col_idx, A->val, nullptr, true, true, o.no_col16 != 0, s, &B);
+    rc = build_sell(c, ctx_sell_bufs(c), n, A->nnz, A->row_ptr, A->col_idx, A->val, nullptr, true, true, o.no_col16 != 0, s,
+                    &B);
     if (rc != RPCG_OK) return rc;
     SellMat<float> M = sell_mat<float>(B, B.val32, n, A->row_ptr);
     const size_t nn = (size_t)std::max(1, n);
@@ -778,6 +791,72 @@ int rpcg_ir_solve(rpcg_ctx *c, rpcg_mode mode, const rpcg_csr *A, const double *
     int rc = ir_body(c, (int)mode, A, b, x, io, res, (hipStream_t)stream);
     if (res) res->status = rc;
     return rc;
+}
+
+} // extern "C"
+
+// A matrix kept in the sliced-ELL layout for repeated products.
+struct rpcg_smat {
+    int device = 0;
+    int num_cus = 256;
+    int n = 0;
+    rpcg_host::Buffer off, val, val32, col, cfirst, len, rp;
+    SellBuilt B;
+};
+
+static int smat_build(rpcg_ctx *c, const rpcg_csr *A, rpcg_smat *M, hipStream_t s)
+{
+    const SellBufs bf{&M->off, &M->val, &M->val32, &M->col, &M->cfirst, &M->len};
+    int rc = build_sell(c, bf, A->n, A->nnz, A->row_ptr, A->col_idx, A->val, nullptr, true, false, false, s, &M->B);
+    if (rc != RPCG_OK) return rc;
+    if (!M->B.len8) { // rows of 256 or more entries: the row lengths come from a copy of row_ptr
+        RPCG_TRY(M->rp.ensure(sizeof(int) * ((size_t)A->n + 1)));
+        RPCG_TRY(hipMemcpyAsync(M->rp.p, A->row_ptr, sizeof(int) * ((size_t)A->n + 1), hipMemcpyDeviceToDevice, s));
+    }
+    RPCG_TRY(hipStreamSynchronize(s));
+    return RPCG_OK;
+}
+
+extern "C" {
+
+int rpcg_smat_create(rpcg_ctx *c, const rpcg_csr *A, rpcg_smat **out, void *stream)
+{
+    if (out) *out = nullptr;
+    if (!c || !out || !valid_csr(A)) return RPCG_ERR_INVALID;
+    RPCG_TRY(hipSetDevice(c->device));
+    rpcg_smat *M = new (std::nothrow) rpcg_smat;
+    if (!M) return RPCG_ERR_OOM;
+    M->device = c->device;
+    M->num_cus = c->num_cus;
+    M->n = A->n;
+    const int rc = A->n > 0 ? smat_build(c, A, M, (hipStream_t)stream) : RPCG_OK;
+    if (rc != RPCG_OK) {
+        rpcg_smat_destroy(M);
+        return rc;
+    }
+    *out = M;
+    return RPCG_OK;
+}
+
+int rpcg_smat_spmv(rpcg_smat *M, const double *x, double *y, void *stream)
+{
+    if (!M || (M->n > 0 && (!x || !y || x == y))) return RPCG_ERR_INVALID;
+    if (M->n == 0) return RPCG_OK;
+    RPCG_TRY(hipSetDevice(M->device));
+    const SellMat<double> A = sell_mat<double>(M->B, M->B.val64, M->n, (const int *)M->rp.p);
+    // one workgroup of four wavefronts per four slices, at most two per CU
+    const long long want = ((long long)M->B.nslices + 3) / 4;
+    const int grid = (int)std::max(1ll, std::min(want, 2ll * M->num_cus));
+    RPCG_TRY(launch_sell_spmv(A, x, y, grid, (hipStream_t)stream));
+    return RPCG_OK;
+}
+
+void rpcg_smat_destroy(rpcg_smat *M)
+{
+    if (!M) return;
+    (void)hipSetDevice(M->device); // teardown: nothing to report to
+    for (rpcg_host::Buffer *b : {&M->off, &M->val, &M->val32, &M->col, &M->cfirst, &M->len, &M->rp}) b->release();
+    delete M;
 }
 
 } // extern "C"

@@ -152,6 +152,8 @@ hipError_t launch_sell_scan(long long *off, int nslices, hipStream_t s);
 hipError_t launch_sell_fill(int n, const int *row_ptr, const int *col, const double *val64_in,
                             const float *val32_in, int vec, const long long *off, double *sval64, float *sval32,
                             int *scol, unsigned short *scol16, int *cfirst, unsigned char *len8, hipStream_t s);
+// y = A x on a binary64 sliced-ELL copy (grid workgroups of 256 threads).
+hipError_t launch_sell_spmv(const SellMat<double> &A, const double *x, double *y, int grid, hipStream_t s);
 
 template <typename T>
 struct PcgVecs {

@@ -8,6 +8,7 @@
 // starts, which sit one per lane); the fill gathers rank chunks row segment
 // by row segment and writes them through LDS.
 #include "kernels.hpp"
+#include "sell_spmv.hpp"
 
 #include <algorithm>
 
@@ -249,6 +250,27 @@ __global__ void __launch_bounds__(64) k_sell_fill(int n, int nslices, const int 
     }
 }
 
+// y = A x on a prepared sliced-ELL copy (Section 4.3): lane j of a wavefront
+// computes row 64 s + j as the sequential fma chain of sell_row (the same
+// chain, from +0 in storage order, as the CSR kernel); wavefronts stride over
+// the slices.
+template <bool COL16>
+__global__ void __launch_bounds__(256) k_sell_spmv(SellMat<double> A, const double *__restrict__ x,
+                                                   double *__restrict__ y)
+{
+    const int lane = lane_of();
+    const int W = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (long long s = (long long)blockIdx.x * W + wave; s < A.nslices; s += (long long)gridDim.x * W) {
+        const long long base = uniform_ll(A.off[s]);
+        const int width = __builtin_amdgcn_readfirstlane((int)((A.off[s + 1] - base) >> 6));
+        const long long i = s * 64 + lane;
+        const int len = sell_len(A, i);
+        const double sum = sell_row<double, COL16, false>(A, base, width, i, len, x, nullptr, nullptr);
+        if (i < A.n) y[i] = sum;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launch functions
 
@@ -261,6 +283,15 @@ hipError_t launch_csr_scan(int n, int nnz, const int *row_ptr, const int *col, i
     const int grid = (int)std::min<long long>((nslices + 3) / 4, 4096);
     hipLaunchKernelGGL(k_csr_scan, dim3(grid), dim3(256), 0, s, n, nnz, nslices, row_ptr, col, vec, off_plus1, bad,
                        max_len, max_delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_sell_spmv(const SellMat<double> &A, const double *x, double *y, int grid, hipStream_t s)
+{
+    if (A.nslices == 0) return hipSuccess;
+    if (grid < 1) return hipErrorInvalidValue;
+    if (A.col16) hipLaunchKernelGGL(k_sell_spmv<true>, dim3(grid), dim3(256), 0, s, A, x, y);
+    else hipLaunchKernelGGL(k_sell_spmv<false>, dim3(grid), dim3(256), 0, s, A, x, y);
     return hipGetLastError();
 }
 

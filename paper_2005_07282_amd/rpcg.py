@@ -111,6 +111,12 @@ def lib():
         L.rpcg_fpe_size_auto.restype = ctypes.c_int
         L.rpcg_spmv.argtypes = [P, ctypes.POINTER(_Csr), P, P, P]
         L.rpcg_spmv.restype = ctypes.c_int
+        L.rpcg_smat_create.argtypes = [P, ctypes.POINTER(_Csr), ctypes.POINTER(P), P]
+        L.rpcg_smat_create.restype = ctypes.c_int
+        L.rpcg_smat_spmv.argtypes = [P, P, P, P]
+        L.rpcg_smat_spmv.restype = ctypes.c_int
+        L.rpcg_smat_destroy.argtypes = [P]
+        L.rpcg_smat_destroy.restype = None
         L.rpcg_pcg_solve.argtypes = [P, ctypes.c_int, ctypes.POINTER(_Csr), P, P, ctypes.POINTER(_Opts),
                                      ctypes.POINTER(_Result), P]
         L.rpcg_pcg_solve.restype = ctypes.c_int
@@ -171,7 +177,7 @@ def lib():
 
 EXPORTED = ["rpcg_opts_default", "rpcg_status_string", "rpcg_create", "rpcg_destroy", "rpcg_exdot", "rpcg_exdot_noalloc",
             "rpcg_fpe_size_auto",
-            "rpcg_spmv", "rpcg_pcg_solve", "rpcg_pcg_solve_factored", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
+            "rpcg_spmv", "rpcg_smat_create", "rpcg_smat_spmv", "rpcg_smat_destroy", "rpcg_pcg_solve", "rpcg_pcg_solve_factored", "rpcg_pcg_solve_f32", "rpcg_ir_opts_default", "rpcg_ir_solve",
             "rpcg_batch_create", "rpcg_batch_destroy", "rpcg_batch_get_tuning", "rpcg_batch_set_tuning",
             "rpcg_batch_tune", "rpcg_batch_solve", "rpcg_lp_pattern_nnz", "rpcg_lp_pattern", "rpcg_lp_create",
             "rpcg_lp_destroy", "rpcg_lp_set_params", "rpcg_lp_get_params", "rpcg_lp_forward", "rpcg_lp_factor",
@@ -335,6 +341,44 @@ def spmv(A: CSR, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor
     if rc < 0:
         raise RpcgError(rc, "rpcg_spmv")
     return y
+
+
+class PreparedMatrix:
+    """A CSR matrix copied into the sliced-ELL layout for repeated products
+    (rpcg_smat_*); products are bit-identical to spmv(). The copy does not
+    refer to the CSR arrays afterwards."""
+
+    def __init__(self, A: CSR):
+        self.n = A.n
+        self.device = A.val.device
+        h = ctypes.c_void_p()
+        c = A._c()
+        rc = lib().rpcg_smat_create(context(self.device.index), ctypes.byref(c), ctypes.byref(h),
+                                    _stream(self.device))
+        if rc != 0:
+            raise RpcgError(rc, "rpcg_smat_create")
+        self._h = h
+
+    def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
+        _check(x, torch.float64, "x")
+        if y is None:
+            y = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        _check(y, torch.float64, "y")
+        rc = lib().rpcg_smat_spmv(self._h, x.data_ptr(), y.data_ptr(), _stream(x.device))
+        if rc < 0:
+            raise RpcgError(rc, "rpcg_smat_spmv")
+        return y
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rpcg_smat_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pcg_solve(A: CSR, b: torch.Tensor, x0: torch.Tensor | None = None, mode: str = "exblas",

@@ -114,3 +114,71 @@ def test_spmv_full_size_stencil(R, orc):
     want = orc.spmv(A, x)
     y = R.spmv(R.CSR.from_host(A), torch.from_numpy(x).cuda())
     assert np.array_equal(y.cpu().numpy().view(np.uint64), want.view(np.uint64))
+
+
+def _prepared_case(case):
+    if case == "random":  # unsorted columns: 32-bit column indices in the copy
+        return _random_csr(10007, 21)
+    if case == "stencil27":  # 16-bit column codes, odd widths
+        return stencil27_csr(19)
+    if case == "stencil7":
+        return stencil7_varcoef_csr(17, 3)
+    if case == "empty_rows":
+        return CSRHost(5, np.array([0, 0, 2, 2, 3, 3], np.int32), np.array([4, 0, 1], np.int32),
+                       np.array([2.0, -0.0, 3.0]))
+    if case == "tiny":
+        return CSRHost(1, np.array([0, 1], np.int32), np.array([0], np.int32), np.array([2.0]))
+    if case == "band100":
+        return band_csr(30_011, 100)
+    if case == "long_rows":  # rows of 256 or more entries: lengths from the copied row pointers
+        return _long_rows_csr(20_011, 24)
+    if case == "one_long_row":
+        return CSRHost(3, np.array([0, 0, 20_000, 20_001], np.int32),
+                       np.concatenate([np.arange(20_000) % 3, [2]]).astype(np.int32),
+                       np.random.default_rng(3).standard_normal(20_001))
+    raise ValueError(case)
+
+
+@pytest.mark.parametrize("case", ["random", "stencil27", "stencil7", "empty_rows", "tiny", "band100", "long_rows",
+                                  "one_long_row"])
+def test_prepared_matrix_bitexact(R, orc, case):
+    """A prepared (sliced-ELL) copy gives the oracle's fma chains bit for bit
+    and the same bits as rpcg_spmv, on two vectors in a row, and still gives
+    them after the CSR arrays it was made from are overwritten."""
+    print(f"prepared spmv {case}", flush=True)
+    A = _prepared_case(case)
+    Ad = R.CSR.from_host(A)
+    M = R.PreparedMatrix(Ad)
+    outs = []
+    for seed in (11, 12):
+        x = uniform_pm1(seed, A.n) * 7.7
+        xd = torch.from_numpy(x).cuda()
+        want = orc.spmv(A, x)
+        got = M.spmv(xd).cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), seed
+        assert np.array_equal(R.spmv(Ad, xd).cpu().numpy().view(np.uint64), got.view(np.uint64))
+        outs.append((xd, got))
+    Ad.val.fill_(0.0)
+    Ad.col_idx.fill_(0)
+    Ad.row_ptr.fill_(0)
+    for xd, got in outs:
+        assert np.array_equal(M.spmv(xd).cpu().numpy().view(np.uint64), got.view(np.uint64))
+    M.close()
+
+
+def test_prepared_matrix_errors(R):
+    """Zero rows, aliasing, a malformed CSR (column out of range) and closing twice."""
+    Z = R.PreparedMatrix(R.CSR.from_host(CSRHost(0, np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0))))
+    assert Z.spmv(torch.zeros(0, dtype=torch.float64, device="cuda")).numel() == 0
+    Z.close()
+    A = stencil27_csr(4)
+    M = R.PreparedMatrix(R.CSR.from_host(A))
+    x = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(R.RpcgError):
+        M.spmv(x, x)
+    M.close()
+    M.close()
+    bad = CSRHost(2, np.array([0, 1, 2], np.int32), np.array([0, 5], np.int32), np.array([1.0, 1.0]))
+    with pytest.raises(R.RpcgError) as e:
+        R.PreparedMatrix(R.CSR.from_host(bad))
+    assert e.value.status == R.ERR_INVALID

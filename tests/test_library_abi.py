@@ -90,6 +90,9 @@ def test_null_arguments_rejected_without_gpu(L):
     assert L.rpcg_create(None, 0) == rpcg.ERR_INVALID
     assert L.rpcg_exdot(None, 2, 10, None, None, None, None, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_spmv(None, None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_smat_create(None, None, None, None) == rpcg.ERR_INVALID
+    assert L.rpcg_smat_spmv(None, None, None, None) == rpcg.ERR_INVALID
+    L.rpcg_smat_destroy(None)
     assert L.rpcg_pcg_solve(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_acc_round(None, None, None, None) == rpcg.ERR_INVALID
     assert L.rpcg_pcg_solve_f32(None, 2, None, None, None, None, None, None) == rpcg.ERR_INVALID
