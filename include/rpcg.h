@@ -392,8 +392,10 @@ int rpcg_batch_set_tuning(rpcg_batch *batch, const rpcg_batch_tuning *tuning /* 
 
 /* Autotuner: times trial_iterations (1..1000) iterations of the batch from
  * x = 0 on right-hand sides b (host array of nsys device pointers) for each
- * candidate schedule, keeps the fastest for this batch and records it in the
- * context for batches of the same sizes. *chosen (may be NULL) receives it. */
+ * candidate schedule, twice (the faster trial counts), keeps the fastest for
+ * this batch (among those within 1% of it, the one with the fewest
+ * workgroups) and records it in the context for batches of the same sizes.
+ * *chosen (may be NULL) receives it. */
 int rpcg_batch_tune(rpcg_batch *batch, const double *const *b /* host array */, int32_t trial_iterations,
                     rpcg_batch_tuning *chosen /* host */, void *stream);
 

@@ -173,7 +173,8 @@ __device__ __forceinline__ T sell_row(const SellMat<T> &A, long long base, int w
     int g0 = 0;
     for (; g0 + BG <= groups; g0 += BG) sell_batch<T, COL16, DIAG, BG>(A, p0, g0, first, cur, len, i, x, sum, aii, found);
     // the remaining groups (fewer than a batch) as one more batch, so a
-    // short row (a 7-point row is four groups) waits for memory once
+    // short row (a 7-point row is three groups and its last column) waits
+    // for memory once
     if (V > 1 && (width % V) != 0) // odd width: the single-entry last column joins this batch
         sell_rest<T, COL16, DIAG, BG - 1, true>(groups - g0, A, p0, g0, first, cur, len, i, x, sum, aii, found,
                                                  base + 64ll * (width - 1) + lane, width - 1);
