@@ -815,7 +815,7 @@ def main():
             "unit": "GB/s",
             "frac": round(k1_gbs / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "k_pcg_spmv_dot<exblas, 3, 16-bit column codes, binary64>",
+            "kernel": "k_pcg_spmv_dot<exblas, 4, 16-bit column codes, binary64>",
             "bytes_per_launch": k1_bytes(n, nnz),
             "stream_read": {"GB_s": round(stream_gbs, 1), "frac": round(k1_gbs / stream_gbs, 4),
                             "kernel": "torch.sum over a 2 GiB binary64 vector (fastest of 10)"},

@@ -82,7 +82,8 @@ typedef struct {
     double tol;            /* stop when <r,r> <= RN(RN(tol*tol) * <b,b>) (Fig. 1 tau_max; default 1e-8, Section 5.1) */
     int32_t maxit;         /* default 2000 */
     int32_t fpe_size;      /* expansion length p, 1..8 (Section 4.2: tunable); 0 = auto (default):
-                              4 in FPE mode, 3 in EXBLAS mode (whose result does not depend on it) */
+                              4 in FPE mode; in EXBLAS mode (whose result does not depend on
+                              it) 3, and 4 in the binary64 solver's SpMV and setup kernels */
     int32_t early_exit;    /* FPE mode: stop propagating zero errors (Section 4.2); default 1.
                               Results do not depend on it. The EXBLAS lane path always runs
                               every level (a divergent exit saves nothing on a 64-wide

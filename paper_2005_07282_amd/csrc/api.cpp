@@ -569,6 +569,11 @@ static int pcg_solve_any(rpcg_ctx *c, int mode, int n, int nnz, const int *rp, c
     constexpr bool F32 = std::is_same<T, float>::value;
     LaunchCfg cfg_rows = make_vec_cfg(c, o, std::max(1, n), s);
     LaunchCfg cfg_sl = make_spmv_cfg(c, o, nslices, s, F32);
+    // EXBLAS results do not depend on the lane expansion length. With the
+    // default, the binary64 SpMV kernel (and the setup) keep four terms: its
+    // <d, w> lanes then flush to the long accumulator less often, while the
+    // vector kernels' two dots per element are cheapest with three
+    if (!F32 && mode == MODE_EXBLAS && (!opts || opts->fpe_size == 0)) cfg_sl.fpe_size = 4;
     int rc = ensure_ws(c, std::max(cfg_rows.grid, cfg_sl.grid));
     if (rc != RPCG_OK) return rc;
     SellBuilt B;
