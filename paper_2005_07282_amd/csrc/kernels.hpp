@@ -137,10 +137,10 @@ hipError_t launch_exp_range(long long n, const double *v, int *emin, int *emax, 
 hipError_t launch_spmv_csr(int n, long long nnz, const int *row_ptr, const int *col, const double *val,
                            const double *x, double *y, hipStream_t s);
 
-// CSR structural check (*bad set if malformed), slice widths rounded up to a
-// multiple of vec (off_plus1), longest row, and the range of the 16-bit column
-// codes (*max_delta <= 32767 iff every code fits), one wavefront per 64-row
-// slice.
+// CSR structural check (*bad set if malformed), slice sizes (64 times the
+// slice's longest row, into off_plus1), longest row, and the range of the
+// 16-bit column codes (*max_delta <= 32767 iff every code fits), one
+// wavefront per 64-row slice.
 hipError_t launch_csr_scan(int n, int nnz, const int *row_ptr, const int *col, int vec, long long *off_plus1,
                            int *bad, int *max_len, long long *max_delta, hipStream_t s);
 
