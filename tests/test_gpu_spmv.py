@@ -182,3 +182,20 @@ def test_prepared_matrix_errors(R):
     with pytest.raises(R.RpcgError) as e:
         R.PreparedMatrix(R.CSR.from_host(bad))
     assert e.value.status == R.ERR_INVALID
+
+
+@pytest.mark.slow
+def test_prepared_matrix_full_size_stencil(R, orc):
+    """The prepared copy of the 27-point 160^3 operator (odd widths, 16-bit
+    codes): every row bit-identical to the oracle and to rpcg_spmv."""
+    A = stencil27_csr(160)
+    x = uniform_pm1(9, A.n)
+    print("prepared spmv 160^3", flush=True)
+    want = orc.spmv(A, x)
+    Ad = R.CSR.from_host(A)
+    xd = torch.from_numpy(x).cuda()
+    M = R.PreparedMatrix(Ad)
+    got = M.spmv(xd).cpu().numpy()
+    M.close()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    assert np.array_equal(R.spmv(Ad, xd).cpu().numpy().view(np.uint64), got.view(np.uint64))
